@@ -153,7 +153,8 @@ def test_switch_key_identity():
     s = C.secret_key(p, st["sk"])
     s2 = C.negacyclic_square(s)
     big = 2 ** 127 - 1  # prime, far above any coefficient of s^2
-    sb = T.negacyclic_schoolbook(s % big, s % big, big)
+    sl = [int(x) % big for x in s]
+    sb = T.negacyclic_schoolbook(sl, sl, big)
     assert [int(x) for x in s2] == [x if x <= big // 2 else x - big for x in sb]
     evk = C.relin_key(p, s, st["rlk"])
     qp = p.q + p.p
