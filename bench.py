@@ -1,0 +1,237 @@
+"""Throughput benchmark of the CKKS key-switching hot path on one MI355X.
+
+Workload (CKKS, N = 2^16, 24 Q-primes: one of 60 bits and 23 of 45 bits, 4
+special 60-bit primes, hybrid key switching with dnum = 3 digits of alpha = 8
+primes, uint64 limbs): seeded uniform residues for the ciphertexts and keys
+(throughput does not depend on the values), resident in HBM before timing.
+
+One step = HMult+Relin of two 24-limb ciphertexts, rescale of the product,
+and HRotate of a 24-limb ciphertext by a random amount in [1, N/2).
+``value`` counts the two key-switching operations of each step per second.
+
+Also reported: per-operation rates from their own timed loops, per-kernel
+durations from HIP events recorded on the launch stream (rf_profile_*), the
+roofline of the dominant kernel, and the CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Integer VALU issue slots of the whole chip: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz.
+VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="ckks_n16_l24")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(kernel: str, nl: int, K: int, alpha: int, n: int, op: str) -> float:
+    """Bytes one launch must move (read + write, 8 B per residue) in the HMult+Relin /
+    HRotate chain at nl Q-limbs; NTT passes read and write every limb once."""
+    dn = (nl + alpha - 1) // alpha
+    ext = sum(nl - min(alpha, nl - j * alpha) + K for j in range(dn))
+    limb = 8.0 * n
+    table = {
+        "tensor": 7 * nl,
+        "modup_bconv": nl + ext,
+        "inner_product": dn * (nl + K) + 2 * dn * (nl + K) + 2 * (nl + K),
+        "moddown_bconv": 2 * K + 2 * nl,
+        "moddown_tail": 8 * nl if op == "hmult" else 7 * nl,
+        "automorphism": 2 * nl,
+    }
+    return table[kernel] * limb if kernel in table else float("nan")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X; "
+              "--gpus %d is not supported (the multi-GPU design is described, not built)" % args.gpus)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_2503_22227_amd import Context, galois_element
+    from paper_2503_22227_amd import _lib
+    from paper_2503_22227_amd.params import chain_for
+
+    w = synthetic.WORKLOADS[args.workload]
+    ch = chain_for(w)
+    n = 1 << w["log_n"]
+    ctx = Context(ch["q"], ch["p"], w["log_n"], w["alpha"], log_nmax=w["log_nmax"])
+    L, K, alpha = len(ch["q"]), len(ch["p"]), w["alpha"]
+    dnum = (L + alpha - 1) // alpha
+    st = synthetic.streams(w["seed"])
+    qp = ch["q"] + ch["p"]
+
+    def dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()
+
+    a = dev(np.stack([synthetic.uniform_residues(st["ct_a"], ch["q"], n) for _ in range(2)]))
+    b = dev(np.stack([synthetic.uniform_residues(st["ct_a"], ch["q"], n) for _ in range(2)]))
+    rlk = dev(np.stack([np.stack([synthetic.uniform_residues(st["rlk"], qp, n) for _ in range(2)])
+                        for _ in range(dnum)]))
+    gk = dev(np.stack([np.stack([synthetic.uniform_residues(st["galois"], qp, n) for _ in range(2)])
+                       for _ in range(dnum)]))
+    r = synthetic.rotation_index(st["rot"], n)
+    g = galois_element(r, n)
+    m_out = ctx.empty(2, L, n)
+    r_out = ctx.empty(2, L - 1, n)
+    ro_out = ctx.empty(2, L, n)
+
+    def step():
+        ctx.hmult_relin(a, b, rlk, out=m_out)
+        ctx.rescale(m_out, out=r_out)
+        ctx.rotate(a, g, gk, out=ro_out)
+
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t_steps = timed(step, args.steps)
+    ms_per_step = t_steps / args.steps * 1e3
+    value = 2 * args.steps / t_steps
+
+    # per-operation rates, each in its own loop
+    reps = max(args.steps, 10)
+    t_hm = timed(lambda: ctx.hmult_relin(a, b, rlk, out=m_out), reps)
+    t_ro = timed(lambda: ctx.rotate(a, g, gk, out=ro_out), reps)
+    t_rs = timed(lambda: ctx.rescale(m_out, out=r_out), reps)
+
+    # per-kernel durations from HIP events on the launch stream
+    _lib.profile_read()
+    _lib.profile_enable(True)
+    prof_steps = min(args.steps, 20)
+    for _ in range(prof_steps):
+        step()
+    torch.cuda.synchronize()
+    prof = _lib.profile_read()
+    _lib.profile_enable(False)
+    kernels = {k: {"launches_per_step": c / prof_steps, "avg_us": ms / c * 1e3,
+                   "us_per_step": ms / prof_steps * 1e3} for k, (c, ms) in prof.items()}
+    dominant = max(kernels, key=lambda k: kernels[k]["us_per_step"])
+
+    # roofline of the dominant kernel
+    roof = None
+    kd = kernels[dominant]
+    if dominant.startswith("ntt"):
+        # one pass of the two-pass NTT: half of the log2(N) stages of N/2 butterflies per limb;
+        # average limbs per launch over the step's launches of this pass
+        limbs_per_launch = _ntt_limbs_per_launch(dominant, L, K, alpha)
+        bfly = limbs_per_launch * (n // 2) * (w["log_n"] // 2)
+        slots = bfly * BFLY_SLOTS
+        achieved = slots / (kd["avg_us"] * 1e-6) / 1e12
+        peak = VALU_SLOTS_PER_S / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+                "unit": "Tslot/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": dominant, "work_per_launch": "%d butterflies x %d VALU slots" % (bfly, BFLY_SLOTS)}
+    else:
+        op = "rotate" if dominant == "automorphism" else "hmult"
+        by = algorithmic_bytes(dominant, L, K, alpha, n, op)
+        achieved = by / (kd["avg_us"] * 1e-6) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dominant}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w)
+
+    line = {
+        "metric": "CKKS HMult+Relin/HRotate per sec @N=2^16 L=24",
+        "value": round(value, 2),
+        "unit": "ops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "CKKS N=2^16 L=24 k=4 dnum=3 (alpha=8): HMult+Relin, rescale, HRotate "
+                               "on single ciphertexts", "log_n": w["log_n"], "limbs": L,
+                   "special_primes": K, "alpha": alpha, "rotation": r},
+        "ops": {"hmult_relin_per_s": round(reps / t_hm, 2), "hrotate_per_s": round(reps / t_ro, 2),
+                "rescale_per_s": round(reps / t_rs, 2),
+                "hmult_relin_us": round(t_hm / reps * 1e6, 2), "hrotate_us": round(t_ro / reps * 1e6, 2),
+                "rescale_us": round(t_rs / reps * 1e6, 2)},
+        "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in sorted(kernels.items())},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+# VALU issue slots of one Harvey/Shoup butterfly with 64-bit words built from
+# 32-bit operations (10 quarter-rate multiplies = 40 slots, 24 full-rate adds,
+# compares and selects); see the roofline notes of the design document.
+BFLY_SLOTS = 64
+
+
+def _ntt_limbs_per_launch(name: str, L: int, K: int, alpha: int) -> float:
+    """Mean limbs per launch of an NTT pass in one step (HMult+Relin, rescale, HRotate at L limbs)."""
+    dn = (L + alpha - 1) // alpha
+    ext = sum(L - min(alpha, L - j * alpha) + K for j in range(dn))
+    fwd = [ext, 2 * L] * 2 + [2 * (L - 1)]          # ModUp NTT, ModDown NTT (x2 ops), rescale
+    inv = [L, 2 * K] * 2 + [2]                       # INTT of d, of the P-limbs (x2 ops), rescale
+    launches = fwd if "fwd" in name else inv
+    return sum(launches) / len(launches)
+
+
+def cpu_baseline(w):
+    """The oracle, as it stands, on a bounded sample: one HMult+Relin and one HRotate at full size."""
+    import numpy as np
+
+    import synthetic
+    from oracle import ckks as C
+    from oracle import params as P
+
+    p = P.make_params(w)
+    rng = np.random.default_rng(1)
+    ct = lambda: np.stack([synthetic.uniform_residues(rng, p.q, p.n) for _ in range(2)])  # noqa: E731
+    qp = p.q + p.p
+    key = lambda: np.stack([np.stack([synthetic.uniform_residues(rng, qp, p.n) for _ in range(2)])  # noqa: E731
+                            for _ in range(p.dnum())])
+    a, b, rlk, gk = ct(), ct(), key(), key()
+    g = C.galois_element(3, p.n)
+    t0 = time.perf_counter()
+    C.hmult_relin(C.Ciphertext(a, 1.0), C.Ciphertext(b, 1.0), rlk, p)
+    C.rotate(C.Ciphertext(a, 1.0), g, gk, p)
+    dt = time.perf_counter() - t0
+    return {"value": round(2 / dt, 4), "unit": "ops/s", "cores": 1, "kind": "oracle",
+            "sample": "1 HMult+Relin + 1 HRotate at N=2^16, 24 limbs, dnum=3 (%.1f s, single thread)" % dt}
+
+
+if __name__ == "__main__":
+    main()

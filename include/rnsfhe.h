@@ -1,0 +1,163 @@
+/*
+ * rnsfhe.h -- C ABI of the MI355X (gfx950) RNS-FHE hot path.
+ *
+ * What is computed (section numbers are those of the CAT paper, arXiv 2503.22227):
+ *   * RNS representation (II-B): a coefficient of R_Q, Q = q_0 ... q_l, is held
+ *     as its residues mod each word-sized prime q_i ("limbs");
+ *   * the negacyclic NTT and its inverse (III-A "NTT & INTT", butterfly form);
+ *   * CKKS multiply (the five-stage product of III-A.3 "Kernel Fusion") and
+ *     relinearize, rotate and rescale (the operator rows of Table "CKKS
+ *     operators"); the level concept of II-B (one prime dropped per rescale or
+ *     modulus switch).
+ * The paper does not define its key switching; this library implements hybrid
+ * key switching: digits of ``alpha`` consecutive Q-primes, fast base conversion
+ * to Q_l u P (ModUp), inner product with the evaluation key, and division by P
+ * with rounding (ModDown).
+ *
+ * Data layout (the limb-contiguous layout of III-A.4: the residues of one
+ * modulus are stored contiguously, one modulus after another):
+ *   a polynomial with n limbs is n * N uint64 values, limb i at [i * N, (i+1) * N);
+ *   a ciphertext is 2 such polynomials back to back: [poly][limb][N].
+ *   Every residue is in [0, q_i).  CKKS ciphertexts rest in the NTT domain;
+ *   NTT index k holds the evaluation at psi^(2 brv(k) + 1).
+ *   An evaluation key is [dnum][2][L + k][N]: limbs q_0..q_{L-1} then p_0..p_{k-1},
+ *   dnum = ceil(L / alpha); it serves every level by ignoring limbs q_l.. of Q.
+ *
+ * Memory and streams: every data pointer is DEVICE memory owned by the caller;
+ * the library never allocates device memory inside an operation.  Operations
+ * that need scratch space take a caller-owned device workspace whose size is
+ * given by rf_workspace_bytes().  Every operation is enqueued asynchronously on
+ * the caller's HIP stream (hipStream_t passed as void*; NULL = default stream);
+ * a fault inside a kernel shows up at the caller's next synchronisation.
+ * A context is immutable after creation: calls on different streams may share
+ * it.  Buffers passed to one call must not alias unless stated.
+ *
+ * Errors: every function returns RF_OK (0) or a negative RF_E* code and sets a
+ * thread-local message readable with rf_last_error().  No C++ exception crosses
+ * this interface.
+ */
+#ifndef RNSFHE_H
+#define RNSFHE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum rf_status {
+    RF_OK = 0,
+    RF_EINVAL = -1,       /* null pointer, bad size or shape */
+    RF_ELEVEL = -2,       /* limb count out of range or operands at different levels */
+    RF_EDOMAIN = -3,      /* operand in the wrong (NTT / coefficient) domain */
+    RF_EWORKSPACE = -4,   /* workspace missing or smaller than rf_workspace_bytes() */
+    RF_EHIP = -5,         /* a HIP runtime call or kernel launch failed */
+    RF_EUNSUPPORTED = -6  /* parameters outside what the kernels implement */
+};
+
+enum rf_scheme { RF_CKKS = 0, RF_BFV = 1, RF_BGV = 2 };
+
+/* Parameters of one RNS chain at one ring degree.  The context derives every
+ * table (roots, twiddles, Shoup and Barrett constants, base-conversion
+ * matrices) from these primes itself. */
+typedef struct rf_params {
+    int32_t scheme;          /* rf_scheme */
+    uint32_t log_n;          /* ring degree N = 2^log_n, 12 <= log_n <= 16 */
+    uint32_t log_nmax;       /* degree the roots refer to: psi_N = psi_max^(2^(log_nmax - log_n)),
+                                psi_max = g^((q-1)/2^(log_nmax+1)) for the smallest g >= 2 with
+                                psi_max^(2^log_nmax) = -1; every prime is 1 mod 2^(log_nmax+1) */
+    uint32_t n_q;            /* L: ciphertext primes q_0..q_{L-1}, 1 <= L */
+    const uint64_t *q;       /* host array of L primes, each < 2^61 */
+    uint32_t n_p;            /* k: special primes, 1 <= k */
+    const uint64_t *p;       /* host array of k primes, each < 2^61 */
+    uint32_t alpha;          /* Q-primes per key-switching digit, 1 <= alpha <= 8 */
+    uint64_t t;              /* plaintext modulus (BFV/BGV), 0 for CKKS */
+} rf_params;
+
+typedef struct rf_ctx rf_ctx;
+
+/* Create a context on HIP device `device`; uploads its tables with hipMalloc
+ * once.  Returns RF_EUNSUPPORTED for degrees or sizes outside the kernels'
+ * range, RF_EINVAL for a non-prime-like or non-NTT-friendly modulus. */
+int rf_ctx_create(const rf_params *params, int device, rf_ctx **out);
+void rf_ctx_destroy(rf_ctx *ctx);
+
+/* Operation ids for rf_workspace_bytes. */
+enum rf_op { RF_OP_HMULT_RELIN = 1, RF_OP_ROTATE = 2, RF_OP_RESCALE = 3, RF_OP_KEYSWITCH = 4 };
+
+/* Device workspace bytes an operation needs at a level with `n_limbs` Q-limbs
+ * (0 if the arguments are invalid). */
+size_t rf_workspace_bytes(const rf_ctx *ctx, int op, uint32_t n_limbs);
+
+/* Forward / inverse negacyclic NTT, in place, of `n_polys` polynomials of
+ * `n_limbs` limbs each, stored back to back; limb i of each polynomial is mod
+ * prime `first_limb + i` of the chain q_0..q_{L-1}, p_0..p_{k-1}.
+ * Input residues must be in [0, q); outputs are in [0, q). */
+int rf_ntt(const rf_ctx *ctx, uint64_t *data, uint32_t first_limb, uint32_t n_limbs,
+           uint32_t n_polys, void *stream);
+int rf_intt(const rf_ctx *ctx, uint64_t *data, uint32_t first_limb, uint32_t n_limbs,
+            uint32_t n_polys, void *stream);
+
+/* HMult+Relin (CKKS; the paper's multiply followed by relinearize):
+ * out = (d0 + KS_0(d2), d1 + KS_1(d2)) with (d0, d1, d2) the tensor product of
+ * a and b, all three ciphertexts with `n_limbs` Q-limbs in the NTT domain,
+ * rlk the relinearisation key.  out must not alias a or b. */
+int rf_hmult_relin(const rf_ctx *ctx, const uint64_t *a, const uint64_t *b, const uint64_t *rlk,
+                   uint64_t *out, uint32_t n_limbs, void *workspace, size_t workspace_bytes,
+                   void *stream);
+
+/* HRotate: out = (sigma_g(c0) + KS_0(sigma_g(c1)), KS_1(sigma_g(c1))) with
+ * sigma_g : a(X) -> a(X^g), g odd in [1, 2N), and gk the key from s(X^g) to s.
+ * g = 5^r mod 2N rotates the slots left by r; g = 2N - 1 conjugates.
+ * out must not alias in. */
+int rf_rotate(const rf_ctx *ctx, const uint64_t *in, uint32_t galois_elt, const uint64_t *gk,
+              uint64_t *out, uint32_t n_limbs, void *workspace, size_t workspace_bytes,
+              void *stream);
+
+/* Key switching of one NTT-domain polynomial d (n_limbs Q-limbs) under key evk:
+ * out = (KS_0(d), KS_1(d)), or out += when accumulate != 0. */
+int rf_keyswitch(const rf_ctx *ctx, const uint64_t *d, const uint64_t *evk, uint64_t *out,
+                 uint32_t n_limbs, int accumulate, void *workspace, size_t workspace_bytes,
+                 void *stream);
+
+/* Rescale (CKKS): out = round(in / q_l) with q_l = q_{n_limbs-1}, in with n_limbs
+ * >= 2 Q-limbs, out with n_limbs - 1 (out may equal in). */
+int rf_rescale(const rf_ctx *ctx, const uint64_t *in, uint64_t *out, uint32_t n_limbs,
+               void *workspace, size_t workspace_bytes, void *stream);
+
+/* Modulus switch (CKKS): drop the last limb; out holds n_limbs - 1 limbs per
+ * polynomial (out may equal in). */
+int rf_modswitch(const rf_ctx *ctx, const uint64_t *in, uint64_t *out, uint32_t n_limbs,
+                 void *stream);
+
+/* Tensor product only (the paper's CKKS multiply): d = (a0 b0, a0 b1 + a1 b0, a1 b1),
+ * d is [3][n_limbs][N]. */
+int rf_tensor(const rf_ctx *ctx, const uint64_t *a, const uint64_t *b, uint64_t *d,
+              uint32_t n_limbs, void *stream);
+
+/* Galois automorphism sigma_g of `n_polys` NTT-domain polynomials of n_limbs
+ * Q-limbs (out must not alias in). */
+int rf_automorphism(const rf_ctx *ctx, const uint64_t *in, uint64_t *out, uint32_t galois_elt,
+                    uint32_t n_limbs, uint32_t n_polys, void *stream);
+
+/* Measurement support.  While enabled, every kernel launch of the library is
+ * bracketed by two HIP events recorded on the launch's own stream (a few
+ * microseconds of overhead per launch).  rf_profile_read waits for the recorded
+ * events, writes one line "kernel_name launches total_ms" per kernel into buf
+ * (NUL-terminated, truncated to len), clears the records and returns the full
+ * text length (or a negative RF_E* code).  Process-wide, thread-safe. */
+int rf_profile_enable(int on);
+int rf_profile_read(char *buf, size_t len);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char *rf_last_error(void);
+
+/* Library version string. */
+const char *rf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RNSFHE_H */

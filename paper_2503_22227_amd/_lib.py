@@ -1,0 +1,95 @@
+"""ctypes declarations of librnsfhe.so (the C ABI of include/rnsfhe.h).
+
+Importing this module loads the library and raises if it is missing: there is
+no other implementation to fall back to.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librnsfhe.so")
+
+RF_OK, RF_EINVAL, RF_ELEVEL, RF_EDOMAIN, RF_EWORKSPACE, RF_EHIP, RF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+RF_CKKS, RF_BFV, RF_BGV = 0, 1, 2
+RF_OP_HMULT_RELIN, RF_OP_ROTATE, RF_OP_RESCALE, RF_OP_KEYSWITCH = 1, 2, 3, 4
+
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_vp = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_sz = ctypes.c_size_t
+
+
+class rf_params(ctypes.Structure):
+    _fields_ = [
+        ("scheme", ctypes.c_int32),
+        ("log_n", _u32),
+        ("log_nmax", _u32),
+        ("n_q", _u32),
+        ("q", _u64p),
+        ("n_p", _u32),
+        ("p", _u64p),
+        ("alpha", _u32),
+        ("t", ctypes.c_uint64),
+    ]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("librnsfhe.so is not built (run __graft_entry__.build() or "
+                      "python paper_2503_22227_amd/build.py): %s" % LIB_PATH)
+
+lib = ctypes.CDLL(LIB_PATH)
+
+_SIGS = {
+    "rf_ctx_create": (ctypes.c_int, [ctypes.POINTER(rf_params), ctypes.c_int, ctypes.POINTER(_vp)]),
+    "rf_ctx_destroy": (None, [_vp]),
+    "rf_workspace_bytes": (_sz, [_vp, ctypes.c_int, _u32]),
+    "rf_ntt": (ctypes.c_int, [_vp, _vp, _u32, _u32, _u32, _vp]),
+    "rf_intt": (ctypes.c_int, [_vp, _vp, _u32, _u32, _u32, _vp]),
+    "rf_hmult_relin": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _u32, _vp, _sz, _vp]),
+    "rf_rotate": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _u32, _vp, _sz, _vp]),
+    "rf_keyswitch": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32, ctypes.c_int, _vp, _sz, _vp]),
+    "rf_rescale": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _sz, _vp]),
+    "rf_modswitch": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp]),
+    "rf_tensor": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32, _vp]),
+    "rf_automorphism": (ctypes.c_int, [_vp, _vp, _vp, _u32, _u32, _u32, _vp]),
+    "rf_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+    "rf_profile_read": (ctypes.c_int, [ctypes.c_char_p, _sz]),
+    "rf_last_error": (ctypes.c_char_p, []),
+    "rf_version": (ctypes.c_char_p, []),
+}
+
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class RFError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = lib.rf_last_error().decode(errors="replace")
+        super().__init__("%s failed with code %d: %s" % (where, code, msg))
+        self.code = code
+
+
+def check(code: int, where: str) -> None:
+    if code != RF_OK:
+        raise RFError(code, where)
+
+
+def profile_enable(on: bool) -> None:
+    check(lib.rf_profile_enable(1 if on else 0), "rf_profile_enable")
+
+
+def profile_read() -> dict:
+    """{kernel: (launches, total_ms)} of the launches since the last read."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    n = lib.rf_profile_read(buf, len(buf))
+    if n < 0:
+        check(n, "rf_profile_read")
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, count, ms = line.split()
+        out[name] = (int(count), float(ms))
+    return out

@@ -1,0 +1,238 @@
+// C ABI entry points: argument checks, workspace layout and the kernel chains
+// of HMult+Relin, HRotate, key switching and rescale.
+#include <hip/hip_runtime.h>
+
+#include "rf_internal.hpp"
+
+using namespace rf;
+
+namespace {
+
+// Key-switching workspace at level nl, in limbs of N residues:
+//   d_coeff [nl] | ext [ext_limbs] | ip [2][nl+K] | conv [2][nl]
+struct KsLayout {
+    size_t d_coeff, ext, ip, conv, total;
+};
+
+KsLayout ks_layout(const rf_ctx *c, uint32_t nl) {
+    KsLayout l;
+    const size_t N = c->n;
+    l.d_coeff = 0;
+    l.ext = l.d_coeff + (size_t)nl * N;
+    l.ip = l.ext + (size_t)c->modup_levels[nl].ext_limbs * N;
+    l.conv = l.ip + 2 * (size_t)(nl + c->K) * N;
+    l.total = l.conv + 2 * (size_t)nl * N;
+    return l;
+}
+
+int check_level(const rf_ctx *c, uint32_t nl, uint32_t min_limbs = 1) {
+    if (!c) return fail(RF_EINVAL, "null context");
+    if (nl < min_limbs || nl > c->L) return fail(RF_ELEVEL, "limb count out of range for this chain");
+    return RF_OK;
+}
+
+int check_ws(const rf_ctx *c, int op, uint32_t nl, void *ws, size_t ws_bytes) {
+    size_t need = rf_workspace_bytes(c, op, nl);
+    if (!ws || ws_bytes < need)
+        return fail(RF_EWORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " + std::to_string(need));
+    return RF_OK;
+}
+
+// Set the context's device for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+NttBatch batch(const uint64_t *in, uint64_t *out, uint64_t in_stride, uint64_t out_stride, uint32_t per_poly,
+               uint32_t n_polys, uint32_t prime_base, const uint8_t *pmap) {
+    NttBatch b;
+    b.in = in;
+    b.out = out;
+    b.in_poly_stride = in_stride;
+    b.out_poly_stride = out_stride;
+    b.per_poly = per_poly;
+    b.n_polys = n_polys;
+    b.prime_base = prime_base;
+    b.pmap = pmap;
+    return b;
+}
+
+// (KS_0(d), KS_1(d)) into out [2][nl][N]; add0/add1 (nullable) are added.
+int keyswitch_core(const rf_ctx *c, const uint64_t *d, const uint64_t *evk, uint64_t *out, uint32_t nl,
+                   const uint64_t *add0, const uint64_t *add1, uint64_t *ws, hipStream_t s) {
+    const KsLayout l = ks_layout(c, nl);
+    const size_t N = c->n;
+    const ModupLevel &lv = c->modup_levels[nl];
+    uint64_t *d_coeff = ws + l.d_coeff, *ext = ws + l.ext, *ip = ws + l.ip, *conv = ws + l.conv;
+    int rc;
+    // ModUp: INTT of d, base conversion of each digit, NTT of the new limbs
+    if ((rc = launch_ntt(c, batch(d, d_coeff, 0, 0, nl, 1, 0, nullptr), false, s))) return rc;
+    if ((rc = launch_modup_bconv(c, d_coeff, ext, nl, s))) return rc;
+    if ((rc = launch_ntt(c, batch(ext, ext, 0, 0, lv.ext_limbs, 1, 0, c->d_pmaps + lv.pmap_off), true, s))) return rc;
+    // inner product with the key over Q_l u P
+    if ((rc = launch_inner_product(c, d, ext, evk, ip, nl, s))) return rc;
+    // ModDown: INTT of the P-limbs, base conversion to Q_l, NTT, subtract and scale by P^-1
+    const uint64_t ip_stride = (uint64_t)(nl + c->K) * N;
+    if ((rc = launch_ntt(c, batch(ip + (size_t)nl * N, ip + (size_t)nl * N, ip_stride, ip_stride, c->K, 2, c->L,
+                                  nullptr), false, s)))
+        return rc;
+    if ((rc = launch_moddown_bconv(c, ip, conv, nl, s))) return rc;
+    if ((rc = launch_ntt(c, batch(conv, conv, (uint64_t)nl * N, (uint64_t)nl * N, nl, 2, 0, nullptr), true, s)))
+        return rc;
+    return launch_moddown_tail(c, ip, conv, add0, add1, out, nl, s);
+}
+
+}  // namespace
+
+extern "C" size_t rf_workspace_bytes(const rf_ctx *c, int op, uint32_t nl) {
+    if (!c || nl < 1 || nl > c->L) return 0;
+    const size_t N = c->n;
+    switch (op) {
+        case RF_OP_KEYSWITCH: return ks_layout(c, nl).total * 8;
+        case RF_OP_HMULT_RELIN:
+        case RF_OP_ROTATE: return (ks_layout(c, nl).total + (size_t)nl * N) * 8;
+        case RF_OP_RESCALE: return nl < 2 ? 0 : (2 + 2 * (size_t)(nl - 1)) * N * 8;
+        default: return 0;
+    }
+}
+
+extern "C" int rf_ntt(const rf_ctx *c, uint64_t *data, uint32_t first, uint32_t nl, uint32_t np, void *stream) {
+    if (!c || !data) return fail(RF_EINVAL, "rf_ntt: null argument");
+    if (nl == 0 || np == 0 || first + nl > c->L + c->K) return fail(RF_ELEVEL, "rf_ntt: limb range");
+    DeviceGuard g(c->device);
+    const uint64_t stride = (uint64_t)nl * c->n;
+    return launch_ntt(c, batch(data, data, stride, stride, nl, np, first, nullptr), true, (hipStream_t)stream);
+}
+
+extern "C" int rf_intt(const rf_ctx *c, uint64_t *data, uint32_t first, uint32_t nl, uint32_t np, void *stream) {
+    if (!c || !data) return fail(RF_EINVAL, "rf_intt: null argument");
+    if (nl == 0 || np == 0 || first + nl > c->L + c->K) return fail(RF_ELEVEL, "rf_intt: limb range");
+    DeviceGuard g(c->device);
+    const uint64_t stride = (uint64_t)nl * c->n;
+    return launch_ntt(c, batch(data, data, stride, stride, nl, np, first, nullptr), false, (hipStream_t)stream);
+}
+
+extern "C" int rf_tensor(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *d, uint32_t nl,
+                         void *stream) {
+    int rc;
+    if ((rc = check_level(c, nl))) return rc;
+    if (!a || !b || !d) return fail(RF_EINVAL, "rf_tensor: null argument");
+    DeviceGuard g(c->device);
+    return launch_tensor(c, a, b, d, d + 2 * (size_t)nl * c->n, nl, (hipStream_t)stream);
+}
+
+extern "C" int rf_keyswitch(const rf_ctx *c, const uint64_t *d, const uint64_t *evk, uint64_t *out, uint32_t nl,
+                            int accumulate, void *ws, size_t ws_bytes, void *stream) {
+    int rc;
+    if ((rc = check_level(c, nl))) return rc;
+    if (!d || !evk || !out) return fail(RF_EINVAL, "rf_keyswitch: null argument");
+    if ((rc = check_ws(c, RF_OP_KEYSWITCH, nl, ws, ws_bytes))) return rc;
+    DeviceGuard g(c->device);
+    const size_t poly = (size_t)nl * c->n;
+    return keyswitch_core(c, d, evk, out, nl, accumulate ? out : nullptr, accumulate ? out + poly : nullptr,
+                          (uint64_t *)ws, (hipStream_t)stream);
+}
+
+extern "C" int rf_hmult_relin(const rf_ctx *c, const uint64_t *a, const uint64_t *b, const uint64_t *rlk,
+                              uint64_t *out, uint32_t nl, void *ws, size_t ws_bytes, void *stream) {
+    int rc;
+    if ((rc = check_level(c, nl))) return rc;
+    if (!a || !b || !rlk || !out) return fail(RF_EINVAL, "rf_hmult_relin: null argument");
+    if (out == a || out == b) return fail(RF_EINVAL, "rf_hmult_relin: out aliases an input");
+    if ((rc = check_ws(c, RF_OP_HMULT_RELIN, nl, ws, ws_bytes))) return rc;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t poly = (size_t)nl * c->n;
+    uint64_t *d2 = (uint64_t *)ws;
+    uint64_t *ks_ws = d2 + poly;
+    if ((rc = launch_tensor(c, a, b, out, d2, nl, s))) return rc;
+    return keyswitch_core(c, d2, rlk, out, nl, out, out + poly, ks_ws, s);
+}
+
+extern "C" int rf_rotate(const rf_ctx *c, const uint64_t *in, uint32_t galois, const uint64_t *gk, uint64_t *out,
+                         uint32_t nl, void *ws, size_t ws_bytes, void *stream) {
+    int rc;
+    if ((rc = check_level(c, nl))) return rc;
+    if (!in || !gk || !out) return fail(RF_EINVAL, "rf_rotate: null argument");
+    if (out == in) return fail(RF_EINVAL, "rf_rotate: out aliases in");
+    if ((galois & 1u) == 0 || galois >= 2u * c->n) return fail(RF_EINVAL, "rf_rotate: Galois element must be odd and < 2N");
+    if ((rc = check_ws(c, RF_OP_ROTATE, nl, ws, ws_bytes))) return rc;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t poly = (size_t)nl * c->n;
+    uint64_t *d = (uint64_t *)ws;
+    uint64_t *ks_ws = d + poly;
+    if ((rc = launch_automorphism(c, in, out, galois, nl, 1, s))) return rc;
+    if ((rc = launch_automorphism(c, in + poly, d, galois, nl, 1, s))) return rc;
+    return keyswitch_core(c, d, gk, out, nl, out, nullptr, ks_ws, s);
+}
+
+extern "C" int rf_automorphism(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint32_t galois, uint32_t nl,
+                               uint32_t np, void *stream) {
+    int rc;
+    if ((rc = check_level(c, nl))) return rc;
+    if (!in || !out || np == 0) return fail(RF_EINVAL, "rf_automorphism: bad argument");
+    if (out == in) return fail(RF_EINVAL, "rf_automorphism: out aliases in");
+    if ((galois & 1u) == 0 || galois >= 2u * c->n) return fail(RF_EINVAL, "Galois element must be odd and < 2N");
+    DeviceGuard g(c->device);
+    return launch_automorphism(c, in, out, galois, nl, np, (hipStream_t)stream);
+}
+
+extern "C" int rf_rescale(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint32_t nl, void *ws, size_t ws_bytes,
+                          void *stream) {
+    int rc;
+    if ((rc = check_level(c, nl, 2))) return rc;
+    if (!in || !out) return fail(RF_EINVAL, "rf_rescale: null argument");
+    if ((rc = check_ws(c, RF_OP_RESCALE, nl, ws, ws_bytes))) return rc;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t N = c->n;
+    uint64_t *last = (uint64_t *)ws;         // [2][N]
+    uint64_t *lift = last + 2 * N;           // [2][nl-1][N]
+    const uint64_t in_stride = (uint64_t)nl * N;
+    if ((rc = launch_ntt(c, batch(in + (size_t)(nl - 1) * N, last, in_stride, N, 1, 2, nl - 1, nullptr), false, s)))
+        return rc;
+    if ((rc = launch_rescale_lift(c, last, lift, nl, s))) return rc;
+    if ((rc = launch_ntt(c, batch(lift, lift, (uint64_t)(nl - 1) * N, (uint64_t)(nl - 1) * N, nl - 1, 2, 0, nullptr),
+                         true, s)))
+        return rc;
+    // out has a smaller polynomial stride than in: when they overlap, compute in
+    // the workspace and copy the result over.
+    const bool overlap = (const void *)out < (const void *)(in + 2 * (size_t)nl * N) &&
+                         (const void *)in < (const void *)(out + 2 * (size_t)(nl - 1) * N);
+    if (!overlap) return launch_rescale_tail(c, in, lift, out, nl, s);
+    if ((rc = launch_rescale_tail(c, in, lift, lift, nl, s))) return rc;
+    if (hipMemcpyAsync(out, lift, 2 * (size_t)(nl - 1) * N * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return fail(RF_EHIP, "rf_rescale: copy");
+    return RF_OK;
+}
+
+extern "C" int rf_modswitch(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint32_t nl, void *stream) {
+    int rc;
+    if ((rc = check_level(c, nl, 2))) return rc;
+    if (!in || !out) return fail(RF_EINVAL, "rf_modswitch: null argument");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t N = c->n;
+    const size_t limb = N * 8;
+    // limb by limb in increasing address order: each copy moves data to a lower
+    // address, so with out == in no limb is overwritten before it is read
+    for (uint32_t p = 0; p < 2; ++p)
+        for (uint32_t i = 0; i + 1 < nl; ++i) {
+            const uint64_t *src = in + ((size_t)p * nl + i) * N;
+            uint64_t *dst = out + ((size_t)p * (nl - 1) + i) * N;
+            if (src == dst) continue;
+            if (hipMemcpyAsync(dst, src, limb, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return fail(RF_EHIP, "rf_modswitch: copy");
+        }
+    return RF_OK;
+}

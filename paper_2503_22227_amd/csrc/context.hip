@@ -1,0 +1,304 @@
+// Context creation: every table the kernels read is derived here, on the host,
+// from the primes the caller passes (the paper's "pre-computed elements" of the
+// middle tier, section III), and uploaded once.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rf_internal.hpp"
+
+namespace {
+
+typedef unsigned __int128 u128h;
+
+uint64_t mulmod_h(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)(((u128h)a * b) % q); }
+
+uint64_t powmod_h(uint64_t b, uint64_t e, uint64_t q) {
+    uint64_t r = 1 % q;
+    b %= q;
+    while (e) {
+        if (e & 1) r = mulmod_h(r, b, q);
+        b = mulmod_h(b, b, q);
+        e >>= 1;
+    }
+    return r;
+}
+
+uint64_t inv_h(uint64_t a, uint64_t q) { return powmod_h(a % q, q - 2, q); }  // q prime
+
+// Deterministic Miller-Rabin for 64-bit integers (bases 2..37).
+bool is_prime_h(uint64_t n) {
+    if (n < 2) return false;
+    static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+    for (uint64_t p : bases)
+        if (n % p == 0) return n == p;
+    uint64_t d = n - 1;
+    int s = 0;
+    while ((d & 1) == 0) {
+        d >>= 1;
+        ++s;
+    }
+    for (uint64_t a : bases) {
+        uint64_t x = powmod_h(a, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool comp = true;
+        for (int r = 1; r < s; ++r) {
+            x = mulmod_h(x, x, n);
+            if (x == n - 1) {
+                comp = false;
+                break;
+            }
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+
+uint64_t shoup_companion(uint64_t w, uint64_t q) { return (uint64_t)(((u128h)w << 64) / q); }
+
+uint32_t bitrev_h(uint32_t x, int bits) {
+    uint32_t r = 0;
+    for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1u) << (bits - 1 - i);
+    return r;
+}
+
+// psi_max = g^((q-1)/(2 nmax)) for the smallest g >= 2 with psi_max^nmax = -1.
+uint64_t root_2n(uint64_t q, uint64_t nmax) {
+    for (uint64_t g = 2;; ++g) {
+        uint64_t psi = powmod_h(g, (q - 1) / (2 * nmax), q);
+        if (powmod_h(psi, nmax, q) == q - 1) return psi;
+    }
+}
+
+template <typename T>
+int upload(T **dst, const std::vector<T> &src) {
+    size_t bytes = src.size() * sizeof(T);
+    if (bytes == 0) bytes = sizeof(T);
+    if (hipMalloc((void **)dst, bytes) != hipSuccess) return rf::fail(RF_EHIP, "hipMalloc of a context table failed");
+    if (!src.empty() && hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return rf::fail(RF_EHIP, "hipMemcpy of a context table failed");
+    return RF_OK;
+}
+
+}  // namespace
+
+namespace rf {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+const char *last_error() { return g_last_error.c_str(); }
+
+}  // namespace rf
+
+static void free_tables(rf_ctx *c) {
+    (void)hipFree(c->d_pc);
+    (void)hipFree(c->d_tw_fwd);
+    (void)hipFree(c->d_tw_inv);
+    (void)hipFree(c->d_modup);
+    (void)hipFree(c->d_moddown);
+    (void)hipFree(c->d_rescale);
+    (void)hipFree(c->d_pmaps);
+}
+
+extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
+    using namespace rf;
+    if (!p || !out) return fail(RF_EINVAL, "rf_ctx_create: null argument");
+    *out = nullptr;
+    if (p->scheme < RF_CKKS || p->scheme > RF_BGV) return fail(RF_EINVAL, "unknown scheme");
+    if (p->log_n < 12 || p->log_n > 16) return fail(RF_EUNSUPPORTED, "log_n must be in [12, 16]");
+    if (p->log_nmax < p->log_n || p->log_nmax > 20) return fail(RF_EINVAL, "log_nmax must be in [log_n, 20]");
+    if (p->n_q < 1 || p->n_p < 1 || !p->q || !p->p) return fail(RF_EINVAL, "need at least one q and one p prime");
+    if (p->n_q + p->n_p > (uint32_t)kMaxPrimes) return fail(RF_EUNSUPPORTED, "too many primes");
+    if (p->alpha < 1 || p->alpha > (uint32_t)kMaxAlpha) return fail(RF_EUNSUPPORTED, "alpha must be in [1, 8]");
+    if (p->n_p > 8) return fail(RF_EUNSUPPORTED, "at most 8 special primes");
+
+    rf_ctx *c = new rf_ctx();
+    c->device = device;
+    c->scheme = p->scheme;
+    c->log_n = p->log_n;
+    c->log_nmax = p->log_nmax;
+    c->n = 1u << p->log_n;
+    c->L = p->n_q;
+    c->K = p->n_p;
+    c->alpha = p->alpha;
+    c->dnum = (c->L + c->alpha - 1) / c->alpha;
+    c->t = p->t;
+    for (uint32_t i = 0; i < c->L; ++i) c->primes.push_back(p->q[i]);
+    for (uint32_t i = 0; i < c->K; ++i) c->primes.push_back(p->p[i]);
+    const uint64_t nmax = 1ull << c->log_nmax;
+    const uint32_t N = c->n;
+    const uint32_t NP = c->L + c->K;
+    for (uint32_t g = 0; g < NP; ++g) {
+        uint64_t q = c->primes[g];
+        if (q >= (1ull << 61) || q < 3 || (q - 1) % (2 * nmax) != 0 || !is_prime_h(q)) {
+            delete c;
+            return fail(RF_EINVAL, "prime " + std::to_string(g) + " is not an NTT-friendly prime below 2^61");
+        }
+        for (uint32_t h = 0; h < g; ++h)
+            if (c->primes[h] == q) {
+                delete c;
+                return fail(RF_EINVAL, "primes must be distinct");
+            }
+        uint64_t psi_max = root_2n(q, nmax);
+        c->psi.push_back(powmod_h(psi_max, nmax / N, q));
+    }
+
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return fail(RF_EHIP, "hipSetDevice failed");
+    }
+
+    // per-prime constants and twiddle tables
+    std::vector<PrimeConst> pc(NP);
+    std::vector<TwPair> twf((size_t)NP * N), twi((size_t)NP * N);
+    std::vector<uint64_t> pw(N), pwi(N);
+    for (uint32_t g = 0; g < NP; ++g) {
+        uint64_t q = c->primes[g];
+        u128h mu = (~(u128h)0) / q;  // floor((2^128 - 1) / q) = floor(2^128 / q) for q not a power of 2
+        pc[g].q = q;
+        pc[g].mu1 = (uint64_t)(mu >> 64);
+        pc[g].mu0 = (uint64_t)mu;
+        uint64_t ninv = inv_h(N, q);
+        pc[g].ninv = ninv;
+        pc[g].ninv_p = shoup_companion(ninv, q);
+        uint64_t psi = c->psi[g], psi_inv = inv_h(psi, q);
+        pw[0] = pwi[0] = 1;
+        for (uint32_t e = 1; e < N; ++e) {
+            pw[e] = mulmod_h(pw[e - 1], psi, q);
+            pwi[e] = mulmod_h(pwi[e - 1], psi_inv, q);
+        }
+        for (uint32_t k = 0; k < N; ++k) {
+            uint32_t r = bitrev_h(k, c->log_n);
+            TwPair &f = twf[(size_t)g * N + k];
+            f.w = pw[r];
+            f.wp = shoup_companion(f.w, q);
+            TwPair &b = twi[(size_t)g * N + k];
+            b.w = pwi[r];
+            b.wp = shoup_companion(b.w, q);
+        }
+        uint64_t wl = mulmod_h(twi[(size_t)g * N + 1].w, ninv, q);
+        pc[g].wlast = wl;
+        pc[g].wlast_p = shoup_companion(wl, q);
+        pc[g].pad = 0;
+    }
+
+    // ModUp: for every digit j and every digit size s (a truncated last digit at a lower level)
+    const uint32_t A = c->alpha;
+    c->modup_stride = 2 * (size_t)A + (size_t)A * NP;
+    std::vector<uint64_t> mu((size_t)c->dnum * A * c->modup_stride, 0);
+    for (uint32_t j = 0; j < c->dnum; ++j) {
+        for (uint32_t s = 1; s <= A; ++s) {
+            uint32_t start = j * A;
+            if (start + s > c->L) continue;
+            uint64_t *blk = mu.data() + modup_block(c, j, s);
+            for (uint32_t i = 0; i < s; ++i) {
+                uint64_t qi = c->primes[start + i];
+                uint64_t prod = 1;  // (Q_j / q_i) mod q_i
+                for (uint32_t h = 0; h < s; ++h)
+                    if (h != i) prod = mulmod_h(prod, c->primes[start + h] % qi, qi);
+                uint64_t f = inv_h(prod, qi);
+                blk[2 * i] = f;
+                blk[2 * i + 1] = shoup_companion(f, qi);
+                for (uint32_t g = 0; g < NP; ++g) {
+                    uint64_t m = c->primes[g];
+                    uint64_t v = 1;
+                    for (uint32_t h = 0; h < s; ++h)
+                        if (h != i) v = mulmod_h(v, c->primes[start + h] % m, m);
+                    blk[2 * A + (size_t)i * NP + g] = v;
+                }
+            }
+        }
+    }
+
+    // ModDown: P = p_0 ... p_{k-1} to every q_i
+    std::vector<uint64_t> md(moddown_negp_off(c) + c->L, 0);
+    for (uint32_t a = 0; a < c->K; ++a) {
+        uint64_t pa = c->primes[c->L + a];
+        uint64_t prod = 1;
+        for (uint32_t h = 0; h < c->K; ++h)
+            if (h != a) prod = mulmod_h(prod, c->primes[c->L + h] % pa, pa);
+        uint64_t f = inv_h(prod, pa);
+        md[2 * a] = f;
+        md[2 * a + 1] = shoup_companion(f, pa);
+        for (uint32_t i = 0; i < c->L; ++i) {
+            uint64_t qi = c->primes[i];
+            uint64_t v = 1;
+            for (uint32_t h = 0; h < c->K; ++h)
+                if (h != a) v = mulmod_h(v, c->primes[c->L + h] % qi, qi);
+            md[moddown_cross_off(c) + (size_t)a * c->L + i] = v;
+        }
+    }
+    for (uint32_t i = 0; i < c->L; ++i) {
+        uint64_t qi = c->primes[i];
+        uint64_t P = 1;
+        for (uint32_t h = 0; h < c->K; ++h) P = mulmod_h(P, c->primes[c->L + h] % qi, qi);
+        uint64_t pinv = inv_h(P, qi);
+        md[moddown_pinv_off(c) + 2 * i] = pinv;
+        md[moddown_pinv_off(c) + 2 * i + 1] = shoup_companion(pinv, qi);
+        md[moddown_negp_off(c) + i] = (qi - P) % qi;
+    }
+
+    // Rescale: drop q_l (l >= 1) into every q_i, i < l
+    std::vector<uint64_t> rs((size_t)c->L * c->L * 3, 0);
+    for (uint32_t l = 1; l < c->L; ++l) {
+        uint64_t ql = c->primes[l];
+        for (uint32_t i = 0; i < l; ++i) {
+            uint64_t qi = c->primes[i];
+            uint64_t inv = inv_h(ql % qi, qi);
+            rs[rescale_off(c, l, i)] = inv;
+            rs[rescale_off(c, l, i) + 1] = shoup_companion(inv, qi);
+            rs[rescale_off(c, l, i) + 2] = (qi - ql % qi) % qi;
+        }
+    }
+
+    // ModUp extension prime maps per level nl: for each digit, the basis Q_l u P minus the digit
+    std::vector<uint8_t> pm;
+    c->modup_levels.assign(c->L + 1, ModupLevel{0, 0, 0});
+    for (uint32_t nl = 1; nl <= c->L; ++nl) {
+        ModupLevel lv;
+        lv.dnum = (nl + A - 1) / A;
+        lv.pmap_off = (uint32_t)pm.size();
+        for (uint32_t j = 0; j < lv.dnum; ++j) {
+            uint32_t start = j * A, s = std::min(A, nl - start);
+            for (uint32_t g = 0; g < nl; ++g)
+                if (g < start || g >= start + s) pm.push_back((uint8_t)g);
+            for (uint32_t g = 0; g < c->K; ++g) pm.push_back((uint8_t)(c->L + g));
+        }
+        lv.ext_limbs = (uint32_t)pm.size() - lv.pmap_off;
+        c->modup_levels[nl] = lv;
+    }
+
+    int rc = RF_OK;
+    if ((rc = upload(&c->d_pc, pc)) || (rc = upload(&c->d_tw_fwd, twf)) || (rc = upload(&c->d_tw_inv, twi)) ||
+        (rc = upload(&c->d_modup, mu)) || (rc = upload(&c->d_moddown, md)) || (rc = upload(&c->d_rescale, rs)) ||
+        (rc = upload(&c->d_pmaps, pm))) {
+        free_tables(c);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return RF_OK;
+}
+
+extern "C" void rf_ctx_destroy(rf_ctx *c) {
+    if (!c) return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(c->device);
+    free_tables(c);
+    (void)hipSetDevice(prev);
+    delete c;
+}
+
+extern "C" const char *rf_last_error(void) { return rf::last_error(); }
+
+extern "C" const char *rf_version(void) { return "rnsfhe 0.1 gfx950"; }

@@ -1,0 +1,126 @@
+// Internal structures of the RNS-FHE library shared by the host runtime and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/rnsfhe.h"
+
+namespace rf {
+
+constexpr int kMaxAlpha = 8;
+constexpr int kMaxPrimes = 250;  // L + k, prime indices fit in a byte
+
+// Per-prime constants, device resident.  Prime index g < L is q_g, g >= L is p_{g-L}.
+struct PrimeConst {
+    uint64_t q;
+    uint64_t mu1, mu0;       // floor(2^128 / q) = mu1 * 2^64 + mu0
+    uint64_t ninv, ninv_p;   // N^-1 mod q and its Shoup companion
+    uint64_t wlast, wlast_p; // psi^-brv(1) * N^-1 (last inverse stage) and companion
+    uint64_t pad;
+};
+
+struct __align__(16) TwPair {
+    uint64_t w, wp;  // twiddle and floor(w 2^64 / q)
+};
+
+// Launch description of a batched (I)NTT over limbs laid out as
+// [n_polys][per_poly][N]; limb i of a polynomial uses prime pmap[i] (or prime_base + i).
+struct NttBatch {
+    const uint64_t *in;
+    uint64_t *out;
+    uint64_t in_poly_stride;   // elements between polynomials
+    uint64_t out_poly_stride;
+    uint32_t per_poly;
+    uint32_t n_polys;
+    uint32_t prime_base;
+    const uint8_t *pmap;       // device array [per_poly] or nullptr
+};
+
+// Host-side layout of the ModUp extension basis at one level.
+struct ModupLevel {
+    uint32_t dnum;        // digits at this level
+    uint32_t ext_limbs;   // sum over digits of (nl - alpha_j + k)
+    uint32_t pmap_off;    // offset of this level's prime map in Context::d_pmaps
+};
+
+}  // namespace rf
+
+struct rf_ctx {
+    int device;
+    int scheme;
+    uint32_t log_n, log_nmax, n;
+    uint32_t L, K, alpha, dnum;
+    uint64_t t;
+    std::vector<uint64_t> primes;  // L + K: q_0..q_{L-1}, p_0..p_{k-1}
+    std::vector<uint64_t> psi;     // primitive 2N-th roots
+    std::vector<rf::ModupLevel> modup_levels;  // index nl in [1, L]
+
+    // device tables (owned)
+    rf::PrimeConst *d_pc = nullptr;        // [L+K]
+    rf::TwPair *d_tw_fwd = nullptr;        // [L+K][N]: psi^brv(k)
+    rf::TwPair *d_tw_inv = nullptr;        // [L+K][N]: psi^-brv(k)
+    uint64_t *d_modup = nullptr;           // ModUp base-conversion constants, see context.hip
+    uint64_t *d_moddown = nullptr;         // ModDown constants
+    uint64_t *d_rescale = nullptr;         // rescale constants
+    uint8_t *d_pmaps = nullptr;            // ModUp extension prime maps for every level
+    size_t modup_stride = 0;               // uint64 entries per (digit, size) block
+};
+
+namespace rf {
+
+// Offsets (in uint64 entries) inside the ModUp table block of (digit j, digit size s):
+//   [0, 2*alpha):            factor pairs (w, w') of [(Q_j/q_i)^-1]_{q_i}, i' < s
+//   [2*alpha, ...):          cross[i'][g] = [Q_j/q_i]_{prime g}, g in [0, L+K)
+inline size_t modup_block(const rf_ctx *c, uint32_t j, uint32_t s) {
+    return ((size_t)j * c->alpha + (s - 1)) * c->modup_stride;
+}
+// ModDown table: [K] factor pairs (w, w') of [(P/p)^-1]_p; [K][L] cross [P/p]_{q_i};
+// [L] pairs P^-1 mod q_i; [L] (q_i - [P]_{q_i}).
+inline size_t moddown_cross_off(const rf_ctx *c) { return 2 * (size_t)c->K; }
+inline size_t moddown_pinv_off(const rf_ctx *c) { return 2 * (size_t)c->K + (size_t)c->K * c->L; }
+inline size_t moddown_negp_off(const rf_ctx *c) { return moddown_pinv_off(c) + 2 * (size_t)c->L; }
+// Rescale table, per dropped prime index l in [1, L) and i < l:
+//   entry (l * L + i) * 3 + {0,1,2} = q_l^-1 mod q_i, its companion, q_i - [q_l]_{q_i}.
+inline size_t rescale_off(const rf_ctx *c, uint32_t l, uint32_t i) {
+    return ((size_t)l * c->L + i) * 3;
+}
+
+// Brackets one kernel launch with HIP events on its stream while profiling is
+// enabled (rf_profile_enable); a no-op otherwise.
+class ProfScope {
+  public:
+    ProfScope(const char *name, hipStream_t s);
+    ~ProfScope();
+
+  private:
+    int idx_;
+    hipStream_t s_;
+};
+
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+// kernel launchers (kernels.hip)
+int launch_ntt(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s);
+int launch_tensor(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *d01,
+                  uint64_t *d2, uint32_t nl, hipStream_t s);
+int launch_modup_bconv(const rf_ctx *c, const uint64_t *x, uint64_t *ext, uint32_t nl,
+                       hipStream_t s);
+int launch_inner_product(const rf_ctx *c, const uint64_t *d_ntt, const uint64_t *ext,
+                         const uint64_t *evk, uint64_t *ip, uint32_t nl, hipStream_t s);
+int launch_moddown_bconv(const rf_ctx *c, const uint64_t *ip, uint64_t *conv, uint32_t nl,
+                         hipStream_t s);
+int launch_moddown_tail(const rf_ctx *c, const uint64_t *ip, const uint64_t *conv,
+                        const uint64_t *add0, const uint64_t *add1, uint64_t *out, uint32_t nl,
+                        hipStream_t s);
+int launch_rescale_lift(const rf_ctx *c, const uint64_t *last, uint64_t *lift, uint32_t nl,
+                        hipStream_t s);
+int launch_rescale_tail(const rf_ctx *c, const uint64_t *in, const uint64_t *lift, uint64_t *out,
+                        uint32_t nl, hipStream_t s);
+int launch_automorphism(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint32_t galois,
+                        uint32_t nl, uint32_t n_polys, hipStream_t s);
+
+}  // namespace rf

@@ -1,0 +1,157 @@
+"""Python binding of the C ABI: argument marshalling only.
+
+Ciphertexts, keys and workspaces are torch int64 tensors on a HIP device that
+hold uint64 residues; every operation runs in the library's kernels on the
+current torch stream (torch supplies device memory and streams, nothing else).
+Layouts: a ciphertext with l Q-limbs is [2, l, N]; a key is [dnum, 2, L + k, N].
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+SCHEMES = {"ckks": _lib.RF_CKKS, "bfv": _lib.RF_BFV, "bgv": _lib.RF_BGV}
+
+
+def _ptr(t: torch.Tensor) -> int:
+    if not t.is_cuda:
+        raise ValueError("tensor must be on a HIP device")
+    if t.dtype not in (torch.int64, torch.uint64):
+        raise ValueError("tensor must hold 64-bit residues")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Context:
+    """An RNS chain q_0..q_{L-1} | p_0..p_{k-1} at ring degree 2^log_n on one device."""
+
+    def __init__(self, q: Sequence[int], p: Sequence[int], log_n: int, alpha: int,
+                 log_nmax: Optional[int] = None, scheme: str = "ckks", t: int = 0,
+                 device: int = 0):
+        self.q = [int(x) for x in q]
+        self.p = [int(x) for x in p]
+        self.log_n = int(log_n)
+        self.n = 1 << self.log_n
+        self.log_nmax = int(log_nmax if log_nmax is not None else log_n)
+        self.alpha = int(alpha)
+        self.L = len(self.q)
+        self.k = len(self.p)
+        self.dnum = (self.L + self.alpha - 1) // self.alpha
+        self.device = torch.device("cuda", device)
+        qa = (ctypes.c_uint64 * self.L)(*self.q)
+        pa = (ctypes.c_uint64 * self.k)(*self.p)
+        prm = _lib.rf_params(SCHEMES[scheme], self.log_n, self.log_nmax, self.L,
+                             ctypes.cast(qa, ctypes.POINTER(ctypes.c_uint64)), self.k,
+                             ctypes.cast(pa, ctypes.POINTER(ctypes.c_uint64)), self.alpha, int(t))
+        h = ctypes.c_void_p()
+        check(lib.rf_ctx_create(ctypes.byref(prm), device, ctypes.byref(h)), "rf_ctx_create")
+        self._h = h
+        self._ws = {}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib.rf_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- memory
+    def empty(self, *shape) -> torch.Tensor:
+        return torch.empty(shape, dtype=torch.int64, device=self.device)
+
+    def workspace_bytes(self, op: int, nlimbs: int) -> int:
+        return int(lib.rf_workspace_bytes(self._h, op, nlimbs))
+
+    def workspace(self, op: int, nlimbs: int) -> torch.Tensor:
+        """A cached device workspace for (op, nlimbs); allocated once, reused by every call."""
+        key = (op, nlimbs)
+        ws = self._ws.get(key)
+        if ws is None:
+            nbytes = self.workspace_bytes(op, nlimbs)
+            if nbytes == 0:
+                raise ValueError("no workspace size for op %d at %d limbs" % (op, nlimbs))
+            ws = torch.empty((nbytes + 7) // 8, dtype=torch.int64, device=self.device)
+            self._ws[key] = ws
+        return ws
+
+    # ---------------------------------------------------------------- operations
+    def ntt(self, data: torch.Tensor, first_limb: int, n_limbs: int, n_polys: int = 1) -> torch.Tensor:
+        check(lib.rf_ntt(self._h, _ptr(data), first_limb, n_limbs, n_polys, _stream()), "rf_ntt")
+        return data
+
+    def intt(self, data: torch.Tensor, first_limb: int, n_limbs: int, n_polys: int = 1) -> torch.Tensor:
+        check(lib.rf_intt(self._h, _ptr(data), first_limb, n_limbs, n_polys, _stream()), "rf_intt")
+        return data
+
+    def tensor(self, a: torch.Tensor, b: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        nl = a.shape[1]
+        out = self.empty(3, nl, self.n) if out is None else out
+        check(lib.rf_tensor(self._h, _ptr(a), _ptr(b), _ptr(out), nl, _stream()), "rf_tensor")
+        return out
+
+    def hmult_relin(self, a: torch.Tensor, b: torch.Tensor, rlk: torch.Tensor,
+                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        nl = a.shape[1]
+        out = self.empty(2, nl, self.n) if out is None else out
+        ws = self.workspace(_lib.RF_OP_HMULT_RELIN, nl)
+        check(lib.rf_hmult_relin(self._h, _ptr(a), _ptr(b), _ptr(rlk), _ptr(out), nl, _ptr(ws),
+                                 ws.numel() * 8, _stream()), "rf_hmult_relin")
+        return out
+
+    def rotate(self, ct: torch.Tensor, galois: int, gk: torch.Tensor,
+               out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        nl = ct.shape[1]
+        out = self.empty(2, nl, self.n) if out is None else out
+        ws = self.workspace(_lib.RF_OP_ROTATE, nl)
+        check(lib.rf_rotate(self._h, _ptr(ct), galois, _ptr(gk), _ptr(out), nl, _ptr(ws),
+                            ws.numel() * 8, _stream()), "rf_rotate")
+        return out
+
+    def keyswitch(self, d: torch.Tensor, evk: torch.Tensor, out: torch.Tensor,
+                  accumulate: bool = False) -> torch.Tensor:
+        nl = d.shape[-2]
+        ws = self.workspace(_lib.RF_OP_KEYSWITCH, nl)
+        check(lib.rf_keyswitch(self._h, _ptr(d), _ptr(evk), _ptr(out), nl, 1 if accumulate else 0,
+                               _ptr(ws), ws.numel() * 8, _stream()), "rf_keyswitch")
+        return out
+
+    def rescale(self, ct: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        nl = ct.shape[1]
+        out = self.empty(2, nl - 1, self.n) if out is None else out
+        ws = self.workspace(_lib.RF_OP_RESCALE, nl)
+        check(lib.rf_rescale(self._h, _ptr(ct), _ptr(out), nl, _ptr(ws), ws.numel() * 8, _stream()),
+              "rf_rescale")
+        return out
+
+    def modswitch(self, ct: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        nl = ct.shape[1]
+        out = self.empty(2, nl - 1, self.n) if out is None else out
+        check(lib.rf_modswitch(self._h, _ptr(ct), _ptr(out), nl, _stream()), "rf_modswitch")
+        return out
+
+    def automorphism(self, x: torch.Tensor, galois: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """sigma_g of a [polys, limbs, N] NTT-domain tensor."""
+        npolys, nl = x.shape[0], x.shape[1]
+        out = torch.empty_like(x) if out is None else out
+        check(lib.rf_automorphism(self._h, _ptr(x), _ptr(out), galois, nl, npolys, _stream()),
+              "rf_automorphism")
+        return out
+
+
+def galois_element(r: int, n: int) -> int:
+    """5^r mod 2N: the automorphism that rotates CKKS slots left by r."""
+    return pow(5, r, 2 * n)
