@@ -38,7 +38,21 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="ckks_n16_l24")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy three times (HBM counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain copy kernel of known size, to scale FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    nbytes = 256 << 20
+    src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_launch": nbytes, "launches": 3}), flush=True)
 
 
 def algorithmic_bytes(kernel: str, nl: int, K: int, alpha: int, n: int, op: str) -> float:
@@ -64,6 +78,9 @@ def main():
         print("bench.py measures one GPU: this build runs on a single MI355X; "
               "--gpus %d is not supported (the multi-GPU design is described, not built)" % args.gpus)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import numpy as np
     import torch
@@ -144,23 +161,26 @@ def main():
     # roofline of the dominant kernel
     roof = None
     kd = kernels[dominant]
+    traffic = _counter_traffic(dominant)
     if dominant.startswith("ntt"):
         # one pass of the two-pass NTT: half of the log2(N) stages of N/2 butterflies per limb;
         # average limbs per launch over the step's launches of this pass
         limbs_per_launch = _ntt_limbs_per_launch(dominant, L, K, alpha)
         bfly = limbs_per_launch * (n // 2) * (w["log_n"] // 2)
-        slots = bfly * BFLY_SLOTS
-        achieved = slots / (kd["avg_us"] * 1e-6) / 1e12
+        ops = bfly * BFLY_OPS
+        achieved = ops / (kd["avg_us"] * 1e-6) / 1e12
         peak = VALU_SLOTS_PER_S / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "Tslot/s", "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": dominant, "work_per_launch": "%d butterflies x %d VALU slots" % (bfly, BFLY_SLOTS)}
+                "unit": "Tops/s", "frac": round(achieved / peak, 4), "traffic": traffic,
+                "kernel": dominant, "avg_us": round(kd["avg_us"], 3),
+                "work_per_launch": "%.0f butterflies x %d int32 VALU ops" % (bfly, BFLY_OPS)}
     else:
         op = "rotate" if dominant == "automorphism" else "hmult"
         by = algorithmic_bytes(dominant, L, K, alpha, n, op)
         achieved = by / (kd["avg_us"] * 1e-6) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dominant}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dominant,
+                "avg_us": round(kd["avg_us"], 3)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -193,10 +213,35 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-# VALU issue slots of one Harvey/Shoup butterfly with 64-bit words built from
-# 32-bit operations (10 quarter-rate multiplies = 40 slots, 24 full-rate adds,
-# compares and selects); see the roofline notes of the design document.
-BFLY_SLOTS = 64
+# Algorithmic integer work of one Harvey butterfly with a Shoup product on
+# 64-bit words, counted as the fewest gfx950 VALU instructions that compute it:
+# 64x64 high product 6, two 64-bit low products 4 + 4, their difference 2,
+# the lazy [0, 2q) correction 4, the two outputs 1 + 3.
+BFLY_OPS = 24
+
+
+def _counter_traffic(kernel: str):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter table,
+    or None when the table is missing or was taken on different kernel sources."""
+    from paper_2503_22227_amd.profsum import source_digest
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_ckks_n16_l24.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if ("source-sha1: %s" % source_digest()) not in text:
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 7 and cells[0].startswith(_kernel_symbol(kernel)):
+            return round(float(cells[6]) * 1e6)
+    return None
+
+
+def _kernel_symbol(name: str) -> str:
+    """Profiler name of a kernel as it appears in rocprofv3 tables."""
+    table = {"ntt_fwd_cols": "ntt_cols_kernel<8, 8, true>", "ntt_fwd_rows": "ntt_rows_kernel<8, 8, true>",
+             "ntt_inv_cols": "ntt_cols_kernel<8, 8, false>", "ntt_inv_rows": "ntt_rows_kernel<8, 8, false>"}
+    return table.get(name, name + "_kernel")
 
 
 def _ntt_limbs_per_launch(name: str, L: int, K: int, alpha: int) -> float:

@@ -1,0 +1,124 @@
+"""Summarise rocprofv3 result databases (``*_results.db``) as short text tables.
+
+    python -m paper_2503_22227_amd.profsum stats  <results.db>
+    python -m paper_2503_22227_amd.profsum pmc    <results.db>
+    python -m paper_2503_22227_amd.profsum traffic <fetch.db> <write.db> <copy_fetch.db> <copy_write.db> <copy_bytes>
+
+``stats``: per kernel, launches and average / min / max duration.
+``pmc``: per kernel, launches and the average value of every collected counter.
+``traffic``: per kernel, HBM bytes per launch from FETCH_SIZE and WRITE_SIZE
+(KiB per dispatch), each scaled by what the same counter reads for a plain
+device copy of ``copy_bytes`` bytes (expected: copy_bytes read and written).
+"""
+from __future__ import annotations
+
+import re
+import sqlite3
+import sys
+from collections import defaultdict
+
+
+def short(name: str) -> str:
+    name = re.sub(r"\(.*\)$", "", name)
+    name = name.replace("void ", "").replace("rf::", "")
+    return name.strip()
+
+
+def dispatches(db: str):
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, duration from kernels").fetchall()
+    con.close()
+    return [(short(n), d) for n, d in rows]
+
+
+def counters(db: str):
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, dispatch_id, counter_name, counter_value from pmc_events").fetchall()
+    con.close()
+    per = defaultdict(lambda: defaultdict(list))
+    for n, did, cname, v in rows:
+        per[short(n)][cname].append(v)
+    return per
+
+
+def stats(db: str) -> str:
+    acc = defaultdict(list)
+    for n, d in dispatches(db):
+        acc[n].append(d)
+    total = sum(sum(v) for v in acc.values())
+    lines = ["| kernel | launches | avg us | min us | max us | share |", "|---|---|---|---|---|---|"]
+    for n, v in sorted(acc.items(), key=lambda kv: -sum(kv[1])):
+        lines.append("| %s | %d | %.2f | %.2f | %.2f | %.1f%% |" % (
+            n, len(v), sum(v) / len(v) / 1e3, min(v) / 1e3, max(v) / 1e3, 100.0 * sum(v) / total))
+    return "\n".join(lines)
+
+
+def pmc(db: str) -> str:
+    per = counters(db)
+    names = sorted({c for v in per.values() for c in v})
+    lines = ["| kernel | launches | " + " | ".join("avg %s" % c for c in names) + " |",
+             "|---|---|" + "---|" * len(names)]
+    for n, cs in sorted(per.items()):
+        cnt = max(len(x) for x in cs.values())
+        lines.append("| %s | %d | " % (n, cnt) + " | ".join(
+            "%.1f" % (sum(cs[c]) / len(cs[c])) if cs.get(c) else "-" for c in names) + " |")
+    return "\n".join(lines)
+
+
+def _avg(per, kernel_pred, cname):
+    vals = [v for n, cs in per.items() if kernel_pred(n) for v in cs.get(cname, [])]
+    return sum(vals) / len(vals) if vals else float("nan")
+
+
+def traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, copy_bytes) -> str:
+    f, w = counters(fetch_db), counters(write_db)
+    cf, cw = counters(copy_fetch_db), counters(copy_write_db)
+    copy_kernel = lambda n: "copybuffer" in n.lower()  # noqa: E731
+    kf = _avg(cf, copy_kernel, "FETCH_SIZE")
+    kw = _avg(cw, copy_kernel, "WRITE_SIZE")
+    sf = copy_bytes / (kf * 1024.0)
+    sw = copy_bytes / (kw * 1024.0)
+    lines = ["copy calibration: %d B per launch read FETCH_SIZE %.1f KiB (scale %.4f), "
+             "WRITE_SIZE %.1f KiB (scale %.4f)" % (copy_bytes, kf, sf, kw, sw), "",
+             "| kernel | launches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM read MB | HBM write MB | total MB |",
+             "|---|---|---|---|---|---|---|"]
+    for n in sorted(set(f) | set(w)):
+        fv = f.get(n, {}).get("FETCH_SIZE", [])
+        wv = w.get(n, {}).get("WRITE_SIZE", [])
+        if not fv or not wv:
+            continue
+        af, aw = sum(fv) / len(fv), sum(wv) / len(wv)
+        rd, wr = af * 1024 * sf / 1e6, aw * 1024 * sw / 1e6
+        lines.append("| %s | %d | %.1f | %.1f | %.2f | %.2f | %.2f |" % (n, len(fv), af, aw, rd, wr, rd + wr))
+    return "\n".join(lines)
+
+
+def source_digest() -> str:
+    """sha1 over the library's HIP sources: a counter table is valid only for the code it measured."""
+    import hashlib
+    import os
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha1()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def main(argv):
+    mode = argv[1]
+    if mode == "stats":
+        print(stats(argv[2]))
+    elif mode == "pmc":
+        print(pmc(argv[2]))
+    elif mode == "traffic":
+        print(traffic(argv[2], argv[3], argv[4], argv[5], int(argv[6])))
+        print()
+        print("source-sha1: %s" % source_digest())
+    else:
+        raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main(sys.argv)
