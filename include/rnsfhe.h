@@ -84,7 +84,13 @@ int rf_ctx_create(const rf_params *params, int device, rf_ctx **out);
 void rf_ctx_destroy(rf_ctx *ctx);
 
 /* Operation ids for rf_workspace_bytes. */
-enum rf_op { RF_OP_HMULT_RELIN = 1, RF_OP_ROTATE = 2, RF_OP_RESCALE = 3, RF_OP_KEYSWITCH = 4 };
+enum rf_op {
+    RF_OP_HMULT_RELIN = 1,
+    RF_OP_ROTATE = 2,
+    RF_OP_RESCALE = 3,
+    RF_OP_KEYSWITCH = 4,
+    RF_OP_MODSWITCH = 5  /* BGV only; a CKKS modulus switch needs no workspace (size 0) */
+};
 
 /* Device workspace bytes an operation needs at a level with `n_limbs` Q-limbs
  * (0 if the arguments are invalid). */
@@ -122,14 +128,21 @@ int rf_keyswitch(const rf_ctx *ctx, const uint64_t *d, const uint64_t *evk, uint
                  void *stream);
 
 /* Rescale (CKKS): out = round(in / q_l) with q_l = q_{n_limbs-1}, in with n_limbs
- * >= 2 Q-limbs, out with n_limbs - 1 (out may equal in). */
+ * >= 2 Q-limbs, out with n_limbs - 1 (out may equal in).  RF_EUNSUPPORTED on a
+ * BFV/BGV context. */
 int rf_rescale(const rf_ctx *ctx, const uint64_t *in, uint64_t *out, uint32_t n_limbs,
                void *workspace, size_t workspace_bytes, void *stream);
 
-/* Modulus switch (CKKS): drop the last limb; out holds n_limbs - 1 limbs per
- * polynomial (out may equal in). */
+/* Modulus switch (the level concept of II-B), out with n_limbs - 1 limbs per
+ * polynomial (out may equal in):
+ *   CKKS: drop the last limb (workspace unused, may be NULL);
+ *   BGV:  out = (in - delta) / q_l with delta = t [in t^-1]_{q_l} (centred), so
+ *         the plaintext is kept mod t up to the factor q_l^-1 mod t, which the
+ *         caller multiplies into the ciphertext's correction factor.
+ * With a BGV context, rf_hmult_relin / rf_rotate / rf_keyswitch use the
+ * matching ModDown out = (y - delta)/P with delta = t [y t^-1]_P (centred). */
 int rf_modswitch(const rf_ctx *ctx, const uint64_t *in, uint64_t *out, uint32_t n_limbs,
-                 void *stream);
+                 void *workspace, size_t workspace_bytes, void *stream);
 
 /* Tensor product only (the paper's CKKS multiply): d = (a0 b0, a0 b1 + a1 b0, a1 b1),
  * d is [3][n_limbs][N]. */

@@ -144,9 +144,10 @@ def automorphism_coeffs(s: np.ndarray, g: int) -> np.ndarray:
     return out
 
 
-def switch_key(params: Params, s: np.ndarray, s_from: np.ndarray, rng) -> np.ndarray:
+def switch_key(params: Params, s: np.ndarray, s_from: np.ndarray, rng, err_mult: int = 1) -> np.ndarray:
     """Key switching key from ``s_from`` to ``s`` over Q_L u P, NTT domain,
-    shape [dnum][2][L+k][N]:  evk_j = (-a_j s + e_j + P [i in D_j] s_from, a_j).
+    shape [dnum][2][L+k][N]:  evk_j = (-a_j s + err_mult e_j + P [i in D_j] s_from, a_j)
+    (err_mult = t for BGV, 1 otherwise).
 
     [i in D_j] is 1 on the limbs of digit j and 0 on every other Q-limb (and the
     P term vanishes on the P-limbs), so one key serves every level."""
@@ -158,7 +159,7 @@ def switch_key(params: Params, s: np.ndarray, s_from: np.ndarray, rng) -> np.nda
     out = np.empty((len(digits), 2, len(qp), params.n), dtype=np.uint64)
     for j, dj in enumerate(digits):
         a = synthetic.uniform_residues(rng, qp, params.n)
-        e = small_to_ntt(synthetic.gaussian(rng, params.n), qp, params)
+        e = small_to_ntt(synthetic.gaussian(rng, params.n) * err_mult, qp, params)
         b = poly_add(poly_neg(poly_mul(a, s_hat, qp), qp), e, qp)
         for i in dj:
             q = params.q[i]
@@ -300,11 +301,12 @@ def moddown(y: np.ndarray, params: Params, nlimbs: int) -> np.ndarray:
     return out
 
 
-def keyswitch(d_ntt: np.ndarray, evk: np.ndarray, params: Params):
+def keyswitch(d_ntt: np.ndarray, evk: np.ndarray, params: Params, moddown_fn=None):
     nl = d_ntt.shape[0]
+    md = moddown if moddown_fn is None else moddown_fn
     ext = modup(d_ntt, params)
     ip = inner_product(ext, evk, params, nl)
-    return moddown(ip[0], params, nl), moddown(ip[1], params, nl)
+    return md(ip[0], params, nl), md(ip[1], params, nl)
 
 
 def hmult_relin(a: Ciphertext, b: Ciphertext, rlk: np.ndarray, params: Params) -> Ciphertext:

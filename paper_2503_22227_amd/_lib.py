@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_PKG, "librnsfhe.so")
 
 RF_OK, RF_EINVAL, RF_ELEVEL, RF_EDOMAIN, RF_EWORKSPACE, RF_EHIP, RF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 RF_CKKS, RF_BFV, RF_BGV = 0, 1, 2
-RF_OP_HMULT_RELIN, RF_OP_ROTATE, RF_OP_RESCALE, RF_OP_KEYSWITCH = 1, 2, 3, 4
+RF_OP_HMULT_RELIN, RF_OP_ROTATE, RF_OP_RESCALE, RF_OP_KEYSWITCH, RF_OP_MODSWITCH = 1, 2, 3, 4, 5
 
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _vp = ctypes.c_void_p
@@ -51,7 +51,7 @@ _SIGS = {
     "rf_rotate": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _u32, _vp, _sz, _vp]),
     "rf_keyswitch": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32, ctypes.c_int, _vp, _sz, _vp]),
     "rf_rescale": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _sz, _vp]),
-    "rf_modswitch": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp]),
+    "rf_modswitch": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _sz, _vp]),
     "rf_tensor": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32, _vp]),
     "rf_automorphism": (ctypes.c_int, [_vp, _vp, _vp, _u32, _u32, _u32, _vp]),
     "rf_profile_enable": (ctypes.c_int, [ctypes.c_int]),

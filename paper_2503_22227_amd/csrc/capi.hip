@@ -101,6 +101,7 @@ extern "C" size_t rf_workspace_bytes(const rf_ctx *c, int op, uint32_t nl) {
         case RF_OP_HMULT_RELIN:
         case RF_OP_ROTATE: return (ks_layout(c, nl).total + (size_t)nl * N) * 8;
         case RF_OP_RESCALE: return nl < 2 ? 0 : (2 + 2 * (size_t)(nl - 1)) * N * 8;
+        case RF_OP_MODSWITCH: return (nl < 2 || c->scheme != RF_BGV) ? 0 : (2 + 2 * (size_t)(nl - 1)) * N * 8;
         default: return 0;
     }
 }
@@ -187,21 +188,18 @@ extern "C" int rf_automorphism(const rf_ctx *c, const uint64_t *in, uint64_t *ou
     return launch_automorphism(c, in, out, galois, nl, np, (hipStream_t)stream);
 }
 
-extern "C" int rf_rescale(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint32_t nl, void *ws, size_t ws_bytes,
-                          void *stream) {
+// Divide by the last prime q_l with rounding, keeping the message mod t when
+// keep_t (BGV modulus switch): out = (in - lift(last limb)) * q_l^-1.
+static int divide_last(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint32_t nl, void *ws, bool keep_t,
+                       hipStream_t s) {
     int rc;
-    if ((rc = check_level(c, nl, 2))) return rc;
-    if (!in || !out) return fail(RF_EINVAL, "rf_rescale: null argument");
-    if ((rc = check_ws(c, RF_OP_RESCALE, nl, ws, ws_bytes))) return rc;
-    DeviceGuard g(c->device);
-    hipStream_t s = (hipStream_t)stream;
     const size_t N = c->n;
     uint64_t *last = (uint64_t *)ws;         // [2][N]
     uint64_t *lift = last + 2 * N;           // [2][nl-1][N]
     const uint64_t in_stride = (uint64_t)nl * N;
     if ((rc = launch_ntt(c, batch(in + (size_t)(nl - 1) * N, last, in_stride, N, 1, 2, nl - 1, nullptr), false, s)))
         return rc;
-    if ((rc = launch_rescale_lift(c, last, lift, nl, s))) return rc;
+    if ((rc = launch_rescale_lift(c, last, lift, nl, keep_t, s))) return rc;
     if ((rc = launch_ntt(c, batch(lift, lift, (uint64_t)(nl - 1) * N, (uint64_t)(nl - 1) * N, nl - 1, 2, 0, nullptr),
                          true, s)))
         return rc;
@@ -212,16 +210,33 @@ extern "C" int rf_rescale(const rf_ctx *c, const uint64_t *in, uint64_t *out, ui
     if (!overlap) return launch_rescale_tail(c, in, lift, out, nl, s);
     if ((rc = launch_rescale_tail(c, in, lift, lift, nl, s))) return rc;
     if (hipMemcpyAsync(out, lift, 2 * (size_t)(nl - 1) * N * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return fail(RF_EHIP, "rf_rescale: copy");
+        return fail(RF_EHIP, "copy of the divided ciphertext");
     return RF_OK;
 }
 
-extern "C" int rf_modswitch(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint32_t nl, void *stream) {
+extern "C" int rf_rescale(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint32_t nl, void *ws, size_t ws_bytes,
+                          void *stream) {
+    int rc;
+    if ((rc = check_level(c, nl, 2))) return rc;
+    if (c->scheme != RF_CKKS) return fail(RF_EUNSUPPORTED, "rf_rescale: CKKS only (use rf_modswitch for BGV)");
+    if (!in || !out) return fail(RF_EINVAL, "rf_rescale: null argument");
+    if ((rc = check_ws(c, RF_OP_RESCALE, nl, ws, ws_bytes))) return rc;
+    DeviceGuard g(c->device);
+    return divide_last(c, in, out, nl, ws, false, (hipStream_t)stream);
+}
+
+extern "C" int rf_modswitch(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint32_t nl, void *ws,
+                            size_t ws_bytes, void *stream) {
     int rc;
     if ((rc = check_level(c, nl, 2))) return rc;
     if (!in || !out) return fail(RF_EINVAL, "rf_modswitch: null argument");
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
+    if (c->scheme == RF_BGV) {
+        if ((rc = check_ws(c, RF_OP_MODSWITCH, nl, ws, ws_bytes))) return rc;
+        return divide_last(c, in, out, nl, ws, true, s);
+    }
+    if (c->scheme != RF_CKKS) return fail(RF_EUNSUPPORTED, "rf_modswitch: CKKS or BGV");
     const size_t N = c->n;
     const size_t limb = N * 8;
     // limb by limb in increasing address order: each copy moves data to a lower

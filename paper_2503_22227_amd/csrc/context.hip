@@ -105,6 +105,7 @@ static void free_tables(rf_ctx *c) {
     (void)hipFree(c->d_tw_inv);
     (void)hipFree(c->d_modup);
     (void)hipFree(c->d_moddown);
+    (void)hipFree(c->d_moddown_t);
     (void)hipFree(c->d_rescale);
     (void)hipFree(c->d_pmaps);
 }
@@ -120,6 +121,8 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
     if (p->n_q + p->n_p > (uint32_t)kMaxPrimes) return fail(RF_EUNSUPPORTED, "too many primes");
     if (p->alpha < 1 || p->alpha > (uint32_t)kMaxAlpha) return fail(RF_EUNSUPPORTED, "alpha must be in [1, 8]");
     if (p->n_p > 8) return fail(RF_EUNSUPPORTED, "at most 8 special primes");
+    if (p->scheme != RF_CKKS && (p->t < 2 || p->t >= (1ull << 32)))
+        return fail(RF_EINVAL, "BFV/BGV need a plaintext modulus 2 <= t < 2^32");
 
     rf_ctx *c = new rf_ctx();
     c->device = device;
@@ -188,7 +191,13 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
         uint64_t wl = mulmod_h(twi[(size_t)g * N + 1].w, ninv, q);
         pc[g].wlast = wl;
         pc[g].wlast_p = shoup_companion(wl, q);
-        pc[g].pad = 0;
+        pc[g].tmod = pc[g].tmod_p = pc[g].tinv = pc[g].tinv_p = 0;
+        if (c->t > 1) {
+            pc[g].tmod = c->t % q;
+            pc[g].tmod_p = shoup_companion(pc[g].tmod, q);
+            pc[g].tinv = inv_h(c->t, q);
+            pc[g].tinv_p = shoup_companion(pc[g].tinv, q);
+        }
     }
 
     // ModUp: for every digit j and every digit size s (a truncated last digit at a lower level)
@@ -247,6 +256,30 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
         md[moddown_negp_off(c) + i] = (qi - P) % qi;
     }
 
+    // ModDown that keeps the message mod t: delta = t * conv(centred [y t^-1 (P/p)^-1]_p), folded
+    // into the same table layout (factor * t^-1, cross * t, (q_i - [t P]_{q_i}))
+    std::vector<uint64_t> mdt;
+    if (c->t > 1) {
+        mdt = md;
+        for (uint32_t a = 0; a < c->K; ++a) {
+            uint64_t pa = c->primes[c->L + a];
+            uint64_t f = mulmod_h(md[2 * a], inv_h(c->t % pa, pa), pa);
+            mdt[2 * a] = f;
+            mdt[2 * a + 1] = shoup_companion(f, pa);
+            for (uint32_t i = 0; i < c->L; ++i) {
+                uint64_t qi = c->primes[i];
+                size_t o = moddown_cross_off(c) + (size_t)a * c->L + i;
+                mdt[o] = mulmod_h(md[o], c->t % qi, qi);
+            }
+        }
+        for (uint32_t i = 0; i < c->L; ++i) {
+            uint64_t qi = c->primes[i];
+            uint64_t P = 1;
+            for (uint32_t h = 0; h < c->K; ++h) P = mulmod_h(P, c->primes[c->L + h] % qi, qi);
+            mdt[moddown_negp_off(c) + i] = (qi - mulmod_h(P, c->t % qi, qi)) % qi;
+        }
+    }
+
     // Rescale: drop q_l (l >= 1) into every q_i, i < l
     std::vector<uint64_t> rs((size_t)c->L * c->L * 3, 0);
     for (uint32_t l = 1; l < c->L; ++l) {
@@ -279,7 +312,8 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
 
     int rc = RF_OK;
     if ((rc = upload(&c->d_pc, pc)) || (rc = upload(&c->d_tw_fwd, twf)) || (rc = upload(&c->d_tw_inv, twi)) ||
-        (rc = upload(&c->d_modup, mu)) || (rc = upload(&c->d_moddown, md)) || (rc = upload(&c->d_rescale, rs)) ||
+        (rc = upload(&c->d_modup, mu)) || (rc = upload(&c->d_moddown, md)) ||
+        (!mdt.empty() && (rc = upload(&c->d_moddown_t, mdt))) || (rc = upload(&c->d_rescale, rs)) ||
         (rc = upload(&c->d_pmaps, pm))) {
         free_tables(c);
         delete c;

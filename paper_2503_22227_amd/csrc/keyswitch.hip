@@ -165,8 +165,11 @@ __global__ __launch_bounds__(kEw) void moddown_tail_kernel(const uint64_t *__res
     out[off] = r;
 }
 
-// Rescale, step 1: the last limb (coefficient domain, [2][N]) lifted from its
-// centred representative into every remaining prime: lift = [2][nl-1][N].
+// Rescale / modulus switch, step 1: the last limb (coefficient domain, [2][N])
+// lifted from its centred representative into every remaining prime:
+// lift = [2][nl-1][N].  KEEP_T (BGV): the lifted value is t [x t^-1]_{q_l}, so
+// that the difference is 0 mod t as well as mod q_l.
+template <bool KEEP_T>
 __global__ __launch_bounds__(kEw) void rescale_lift_kernel(const uint64_t *__restrict__ last, uint64_t *__restrict__ lift,
                                                            const PrimeConst *__restrict__ pcs,
                                                            const uint64_t *__restrict__ tab, uint32_t log_n,
@@ -174,11 +177,13 @@ __global__ __launch_bounds__(kEw) void rescale_lift_kernel(const uint64_t *__res
     const uint32_t l = nl - 1;
     const uint32_t c = blockIdx.y / l, i = blockIdx.y - c * l;
     const size_t n = (size_t)blockIdx.x * kEw + threadIdx.x;
-    const uint64_t ql = pcs[l].q;
+    const PrimeConst pl = pcs[l];
     const PrimeConst pc = pcs[i];
-    const uint64_t x = last[((size_t)c << log_n) + n];
+    uint64_t x = last[((size_t)c << log_n) + n];
+    if (KEEP_T) x = shoup(x, pl.tinv, pl.tinv_p, pl.q);
     uint64_t r = barrett64(x, pc.mu1, pc.mu0, pc.q);
-    if (x > (ql >> 1)) r = addmod(r, tab[((size_t)l * L + i) * 3 + 2], pc.q);
+    if (x > (pl.q >> 1)) r = addmod(r, tab[((size_t)l * L + i) * 3 + 2], pc.q);
+    if (KEEP_T) r = shoup(r, pc.tmod, pc.tmod_p, pc.q);
     lift[(((size_t)c * l + i) << log_n) + n] = r;
 }
 
@@ -244,7 +249,8 @@ int launch_inner_product(const rf_ctx *c, const uint64_t *d, const uint64_t *ext
 
 int launch_moddown_bconv(const rf_ctx *c, const uint64_t *ip, uint64_t *conv, uint32_t nl, hipStream_t s) {
     ProfScope prof("moddown_bconv", s);
-    hipLaunchKernelGGL(moddown_bconv_kernel, ew_grid(c, 2), dim3(kEw), 0, s, ip, conv, c->d_pc, c->d_moddown,
+    const uint64_t *tab = c->scheme == RF_BGV ? c->d_moddown_t : c->d_moddown;
+    hipLaunchKernelGGL(moddown_bconv_kernel, ew_grid(c, 2), dim3(kEw), 0, s, ip, conv, c->d_pc, tab,
                        c->log_n, nl, c->L, c->K);
     return check_launch("moddown_bconv");
 }
@@ -257,10 +263,15 @@ int launch_moddown_tail(const rf_ctx *c, const uint64_t *ip, const uint64_t *con
     return check_launch("moddown_tail");
 }
 
-int launch_rescale_lift(const rf_ctx *c, const uint64_t *last, uint64_t *lift, uint32_t nl, hipStream_t s) {
+int launch_rescale_lift(const rf_ctx *c, const uint64_t *last, uint64_t *lift, uint32_t nl, bool keep_t,
+                        hipStream_t s) {
     ProfScope prof("rescale_lift", s);
-    hipLaunchKernelGGL(rescale_lift_kernel, ew_grid(c, 2 * (nl - 1)), dim3(kEw), 0, s, last, lift, c->d_pc,
-                       c->d_rescale, c->log_n, nl, c->L);
+    if (keep_t)
+        hipLaunchKernelGGL(rescale_lift_kernel<true>, ew_grid(c, 2 * (nl - 1)), dim3(kEw), 0, s, last, lift, c->d_pc,
+                           c->d_rescale, c->log_n, nl, c->L);
+    else
+        hipLaunchKernelGGL(rescale_lift_kernel<false>, ew_grid(c, 2 * (nl - 1)), dim3(kEw), 0, s, last, lift,
+                           c->d_pc, c->d_rescale, c->log_n, nl, c->L);
     return check_launch("rescale_lift");
 }
 

@@ -19,7 +19,8 @@ struct PrimeConst {
     uint64_t mu1, mu0;       // floor(2^128 / q) = mu1 * 2^64 + mu0
     uint64_t ninv, ninv_p;   // N^-1 mod q and its Shoup companion
     uint64_t wlast, wlast_p; // psi^-brv(1) * N^-1 (last inverse stage) and companion
-    uint64_t pad;
+    uint64_t tmod, tmod_p;   // plaintext modulus t mod q and companion (BGV/BFV; 0 for CKKS)
+    uint64_t tinv, tinv_p;   // t^-1 mod q and companion
 };
 
 struct __align__(16) TwPair {
@@ -64,6 +65,7 @@ struct rf_ctx {
     rf::TwPair *d_tw_inv = nullptr;        // [L+K][N]: psi^-brv(k)
     uint64_t *d_modup = nullptr;           // ModUp base-conversion constants, see context.hip
     uint64_t *d_moddown = nullptr;         // ModDown constants
+    uint64_t *d_moddown_t = nullptr;       // ModDown constants keeping the message mod t (BGV)
     uint64_t *d_rescale = nullptr;         // rescale constants
     uint8_t *d_pmaps = nullptr;            // ModUp extension prime maps for every level
     size_t modup_stride = 0;               // uint64 entries per (digit, size) block
@@ -112,12 +114,12 @@ int launch_modup_bconv(const rf_ctx *c, const uint64_t *x, uint64_t *ext, uint32
 int launch_inner_product(const rf_ctx *c, const uint64_t *d_ntt, const uint64_t *ext,
                          const uint64_t *evk, uint64_t *ip, uint32_t nl, hipStream_t s);
 int launch_moddown_bconv(const rf_ctx *c, const uint64_t *ip, uint64_t *conv, uint32_t nl,
-                         hipStream_t s);
+                         hipStream_t s);  // uses the t-preserving table for BGV contexts
 int launch_moddown_tail(const rf_ctx *c, const uint64_t *ip, const uint64_t *conv,
                         const uint64_t *add0, const uint64_t *add1, uint64_t *out, uint32_t nl,
                         hipStream_t s);
 int launch_rescale_lift(const rf_ctx *c, const uint64_t *last, uint64_t *lift, uint32_t nl,
-                        hipStream_t s);
+                        bool keep_t, hipStream_t s);
 int launch_rescale_tail(const rf_ctx *c, const uint64_t *in, const uint64_t *lift, uint64_t *out,
                         uint32_t nl, hipStream_t s);
 int launch_automorphism(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint32_t galois,

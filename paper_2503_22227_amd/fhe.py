@@ -38,6 +38,8 @@ class Context:
     def __init__(self, q: Sequence[int], p: Sequence[int], log_n: int, alpha: int,
                  log_nmax: Optional[int] = None, scheme: str = "ckks", t: int = 0,
                  device: int = 0):
+        self.scheme = scheme
+        self.t = int(t)
         self.q = [int(x) for x in q]
         self.p = [int(x) for x in p]
         self.log_n = int(log_n)
@@ -138,9 +140,16 @@ class Context:
         return out
 
     def modswitch(self, ct: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """CKKS: drop the last limb.  BGV: (c - delta)/q_l keeping the message mod t; the
+        caller multiplies the ciphertext's correction factor by q_l^-1 mod t."""
         nl = ct.shape[1]
         out = self.empty(2, nl - 1, self.n) if out is None else out
-        check(lib.rf_modswitch(self._h, _ptr(ct), _ptr(out), nl, _stream()), "rf_modswitch")
+        if self.scheme == "bgv":
+            ws = self.workspace(_lib.RF_OP_MODSWITCH, nl)
+            wp, wb = _ptr(ws), ws.numel() * 8
+        else:
+            wp, wb = None, 0
+        check(lib.rf_modswitch(self._h, _ptr(ct), _ptr(out), nl, wp, wb, _stream()), "rf_modswitch")
         return out
 
     def automorphism(self, x: torch.Tensor, galois: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
