@@ -16,204 +16,67 @@
 // Sums of products are accumulated exactly in 128 bits and reduced once.
 #include <hip/hip_runtime.h>
 
-#include "modarith.hpp"
-#include "rf_internal.hpp"
+#include "ks_dev.hpp"
 
 namespace rf {
 
-constexpr int kEw = 256;  // threads per block of the element-wise kernels
-
-// d0 = a0 b0, d1 = a0 b1 + a1 b0 (into d01 = [2][nl][N]), d2 = a1 b1 (into d2 = [nl][N]).
 __global__ __launch_bounds__(kEw) void tensor_kernel(const uint64_t *__restrict__ a, const uint64_t *__restrict__ b,
                                                      uint64_t *__restrict__ d01, uint64_t *__restrict__ d2,
                                                      const PrimeConst *__restrict__ pcs, uint32_t log_n, uint32_t nl) {
-    const uint32_t i = blockIdx.y;
-    const size_t n = (size_t)blockIdx.x * kEw + threadIdx.x;
-    const size_t poly = (size_t)nl << log_n;
-    const size_t off = ((size_t)i << log_n) + n;
-    const PrimeConst pc = pcs[i];
-    const uint64_t a0 = a[off], a1 = a[poly + off], b0 = b[off], b1 = b[poly + off];
-    u128 acc = mul_wide(a0, b1);
-    mac(acc, a1, b0);
-    d01[off] = barrett128(mul_wide(a0, b0), pc.mu1, pc.mu0, pc.q);
-    d01[poly + off] = barrett128(acc, pc.mu1, pc.mu0, pc.q);
-    d2[off] = barrett128(mul_wide(a1, b1), pc.mu1, pc.mu0, pc.q);
+    tensor_unit(a, b, d01, d2, pcs, log_n, nl, blockIdx.x, blockIdx.y);
 }
 
-// ModUp base conversion of every digit at level nl: x = [nl][N] coefficient
-// domain; ext = digits back to back, digit j holding nl - s_j + K limbs ordered
-// as the basis Q_l u P without the digit's own primes.  grid.y = digit.
 __global__ __launch_bounds__(kEw) void modup_bconv_kernel(const uint64_t *__restrict__ x, uint64_t *__restrict__ ext,
                                                           const PrimeConst *__restrict__ pcs,
                                                           const uint64_t *__restrict__ tab, size_t tab_stride,
                                                           uint32_t log_n, uint32_t nl, uint32_t L, uint32_t K,
                                                           uint32_t alpha) {
-    const uint32_t j = blockIdx.y;
-    const uint32_t start = j * alpha;
-    const uint32_t s = min(alpha, nl - start);
-    const size_t n = (size_t)blockIdx.x * kEw + threadIdx.x;
-    const uint64_t *blk = tab + ((size_t)j * alpha + (s - 1)) * tab_stride;
-    const uint64_t *cross = blk + 2 * alpha;
-    const uint32_t NP = L + K;
-    uint64_t y[kMaxAlpha];
-#pragma unroll
-    for (int i = 0; i < kMaxAlpha; ++i) {
-        y[i] = 0;
-        if (i < (int)s) {
-            const uint64_t q = pcs[start + i].q;
-            y[i] = shoup(x[((size_t)(start + i) << log_n) + n], blk[2 * i], blk[2 * i + 1], q);
-        }
-    }
-    const uint32_t ntarget = nl - s + K;
-    uint64_t *dst = ext + (((size_t)j * (nl + K - alpha)) << log_n) + n;
-    for (uint32_t tt = 0; tt < ntarget; ++tt) {
-        const uint32_t g = tt < start ? tt : (tt < nl - s ? tt + s : L + (tt - (nl - s)));
-        const PrimeConst pc = pcs[g];
-        u128 acc = {0, 0};
-#pragma unroll
-        for (int i = 0; i < kMaxAlpha; ++i)
-            if (i < (int)s) mac(acc, y[i], cross[(size_t)i * NP + g]);
-        dst[(size_t)tt << log_n] = barrett128(acc, pc.mu1, pc.mu0, pc.q);
-    }
+    modup_bconv_unit(x, ext, pcs, tab, tab_stride, log_n, nl, L, K, alpha, blockIdx.x, blockIdx.y);
 }
 
-// Inner product with the key on every limb m of Q_l u P (grid.y = m):
-// ip[c][m] = sum_j src_j(m) * evk[j][c][g(m)], src_j(m) = d[m] if m is in digit j,
-// else the ModUp output of digit j.
 __global__ __launch_bounds__(kEw) void inner_product_kernel(const uint64_t *__restrict__ d,
                                                             const uint64_t *__restrict__ ext,
                                                             const uint64_t *__restrict__ evk,
                                                             uint64_t *__restrict__ ip,
                                                             const PrimeConst *__restrict__ pcs, uint32_t log_n,
                                                             uint32_t nl, uint32_t L, uint32_t K, uint32_t alpha) {
-    const uint32_t m = blockIdx.y;
-    const size_t n = (size_t)blockIdx.x * kEw + threadIdx.x;
-    const uint32_t g = m < nl ? m : L + (m - nl);
-    const PrimeConst pc = pcs[g];
-    const uint32_t dn = (nl + alpha - 1) / alpha;
-    const size_t key_poly = (size_t)(L + K) << log_n;
-    u128 acc0 = {0, 0}, acc1 = {0, 0};
-    for (uint32_t j = 0; j < dn; ++j) {
-        const uint32_t start = j * alpha;
-        const uint32_t s = min(alpha, nl - start);
-        uint64_t src;
-        if (m >= start && m < start + s) {
-            src = d[((size_t)m << log_n) + n];
-        } else {
-            const uint32_t tt = m < start ? m : m - s;
-            src = ext[(((size_t)j * (nl + K - alpha) + tt) << log_n) + n];
-        }
-        const uint64_t *kj = evk + (size_t)(2 * j) * key_poly + ((size_t)g << log_n) + n;
-        mac(acc0, src, kj[0]);
-        mac(acc1, src, kj[key_poly]);
-    }
-    const size_t out_poly = (size_t)(nl + K) << log_n;
-    ip[((size_t)m << log_n) + n] = barrett128(acc0, pc.mu1, pc.mu0, pc.q);
-    ip[out_poly + ((size_t)m << log_n) + n] = barrett128(acc1, pc.mu1, pc.mu0, pc.q);
+    inner_product_unit(d, ext, evk, ip, pcs, log_n, nl, L, K, alpha, blockIdx.x, blockIdx.y);
 }
 
-// ModDown base conversion P -> Q_l with centred digits, grid.y = polynomial (2).
-// ip = [2][nl + K][N] with the K P-limbs already in the coefficient domain;
-// conv = [2][nl][N] coefficient domain.
 __global__ __launch_bounds__(kEw) void moddown_bconv_kernel(const uint64_t *__restrict__ ip, uint64_t *__restrict__ conv,
                                                             const PrimeConst *__restrict__ pcs,
                                                             const uint64_t *__restrict__ tab, uint32_t log_n,
                                                             uint32_t nl, uint32_t L, uint32_t K) {
-    const uint32_t c = blockIdx.y;
-    const size_t n = (size_t)blockIdx.x * kEw + threadIdx.x;
-    const uint64_t *src = ip + (((size_t)c * (nl + K) + nl) << log_n) + n;
-    const uint64_t *cross = tab + 2 * (size_t)K;
-    const uint64_t *negp = tab + 2 * (size_t)K + (size_t)K * L + 2 * (size_t)L;
-    uint64_t y[8];
-    uint64_t cnt = 0;
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-        y[a] = 0;
-        if (a < (int)K) {
-            const uint64_t p = pcs[L + a].q;
-            y[a] = shoup(src[(size_t)a << log_n], tab[2 * a], tab[2 * a + 1], p);
-            cnt += y[a] > (p >> 1) ? 1u : 0u;
-        }
-    }
-    uint64_t *dst = conv + (((size_t)c * nl) << log_n) + n;
-    for (uint32_t i = 0; i < nl; ++i) {
-        const PrimeConst pc = pcs[i];
-        u128 acc = mul_wide(cnt, negp[i]);
-#pragma unroll
-        for (int a = 0; a < 8; ++a)
-            if (a < (int)K) mac(acc, y[a], cross[(size_t)a * L + i]);
-        dst[(size_t)i << log_n] = barrett128(acc, pc.mu1, pc.mu0, pc.q);
-    }
+    moddown_bconv_unit(ip, conv, pcs, tab, log_n, nl, L, K, blockIdx.x, blockIdx.y);
 }
 
-// out[c][i] = (ip[c][i] - conv[c][i]) * P^-1 mod q_i  (+ add_c[i] when add_c != null).
-// grid.y = c * nl + i.  add_c may alias out (same element is read then written).
 __global__ __launch_bounds__(kEw) void moddown_tail_kernel(const uint64_t *__restrict__ ip,
                                                            const uint64_t *__restrict__ conv, const uint64_t *add0,
                                                            const uint64_t *add1, uint64_t *out,
                                                            const PrimeConst *__restrict__ pcs,
                                                            const uint64_t *__restrict__ pinv, uint32_t log_n,
                                                            uint32_t nl, uint32_t K) {
-    const uint32_t c = blockIdx.y / nl, i = blockIdx.y - c * nl;
-    const size_t n = (size_t)blockIdx.x * kEw + threadIdx.x;
-    const PrimeConst pc = pcs[i];
-    const uint64_t x = ip[(((size_t)c * (nl + K) + i) << log_n) + n];
-    const size_t off = (((size_t)c * nl + i) << log_n) + n;
-    uint64_t r = shoup(submod(x, conv[off], pc.q), pinv[2 * i], pinv[2 * i + 1], pc.q);
-    const uint64_t *add = c == 0 ? add0 : add1;
-    if (add) r = addmod(r, add[((size_t)i << log_n) + n], pc.q);
-    out[off] = r;
+    moddown_tail_unit(ip, conv, add0, add1, out, pcs, pinv, log_n, nl, K, blockIdx.x, blockIdx.y);
 }
 
-// Rescale / modulus switch, step 1: the last limb (coefficient domain, [2][N])
-// lifted from its centred representative into every remaining prime:
-// lift = [2][nl-1][N].  KEEP_T (BGV): the lifted value is t [x t^-1]_{q_l}, so
-// that the difference is 0 mod t as well as mod q_l.
 template <bool KEEP_T>
 __global__ __launch_bounds__(kEw) void rescale_lift_kernel(const uint64_t *__restrict__ last, uint64_t *__restrict__ lift,
                                                            const PrimeConst *__restrict__ pcs,
                                                            const uint64_t *__restrict__ tab, uint32_t log_n,
                                                            uint32_t nl, uint32_t L) {
-    const uint32_t l = nl - 1;
-    const uint32_t c = blockIdx.y / l, i = blockIdx.y - c * l;
-    const size_t n = (size_t)blockIdx.x * kEw + threadIdx.x;
-    const PrimeConst pl = pcs[l];
-    const PrimeConst pc = pcs[i];
-    uint64_t x = last[((size_t)c << log_n) + n];
-    if (KEEP_T) x = shoup(x, pl.tinv, pl.tinv_p, pl.q);
-    uint64_t r = barrett64(x, pc.mu1, pc.mu0, pc.q);
-    if (x > (pl.q >> 1)) r = addmod(r, tab[((size_t)l * L + i) * 3 + 2], pc.q);
-    if (KEEP_T) r = shoup(r, pc.tmod, pc.tmod_p, pc.q);
-    lift[(((size_t)c * l + i) << log_n) + n] = r;
+    rescale_lift_unit<KEEP_T>(last, lift, pcs, tab, log_n, nl, L, blockIdx.x, blockIdx.y);
 }
 
-// Rescale, step 2: out[c][i] = (in[c][i] - lift[c][i]) * q_l^-1 mod q_i.  grid.y = c * (nl-1) + i.
-// out may equal lift.
 __global__ __launch_bounds__(kEw) void rescale_tail_kernel(const uint64_t *__restrict__ in, const uint64_t *lift,
                                                            uint64_t *out, const PrimeConst *__restrict__ pcs,
                                                            const uint64_t *__restrict__ tab, uint32_t log_n,
                                                            uint32_t nl, uint32_t L) {
-    const uint32_t l = nl - 1;
-    const uint32_t c = blockIdx.y / l, i = blockIdx.y - c * l;
-    const size_t n = (size_t)blockIdx.x * kEw + threadIdx.x;
-    const PrimeConst pc = pcs[i];
-    const uint64_t *t = tab + ((size_t)l * L + i) * 3;
-    const size_t off = (((size_t)c * l + i) << log_n) + n;
-    const uint64_t x = in[(((size_t)c * nl + i) << log_n) + n];
-    out[off] = shoup(submod(x, lift[off], pc.q), t[0], t[1], pc.q);
+    rescale_tail_unit(in, lift, out, pcs, tab, log_n, nl, L, blockIdx.x, blockIdx.y);
 }
 
-// sigma_g in the NTT domain: out[k] = in[k'] with 2 brv(k') + 1 = (2 brv(k) + 1) g mod 2N.
-// grid.y = polynomial * nl + limb (the permutation is the same on every limb).
 __global__ __launch_bounds__(kEw) void automorphism_kernel(const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
                                                            uint32_t galois, uint32_t log_n) {
-    const uint32_t k = blockIdx.x * kEw + threadIdx.x;
-    const uint32_t mask2n = (2u << log_n) - 1;
-    const uint32_t rk = __brev(k) >> (32 - log_n);
-    const uint32_t e = ((2u * rk + 1u) * galois) & mask2n;
-    const uint32_t src = __brev((e - 1u) >> 1) >> (32 - log_n);
-    const size_t base = (size_t)blockIdx.y << log_n;
-    out[base + k] = in[base + src];
+    automorphism_unit(in, out, galois, log_n, blockIdx.x, blockIdx.y);
 }
 
 static int check_launch(const char *what) {

@@ -1,132 +1,10 @@
-// Negacyclic NTT / INTT for gfx950 (the paper's butterfly-method NTT, III-A).
-//
-// Convention: forward output index k holds a(psi^(2 brv(k) + 1)).  The forward
-// transform is the radix-2 Cooley-Tukey recursion with psi merged into the
-// twiddles: stage st (0-based) pairs j and j + N/2^(st+1) with twiddle
-// psi^brv(2^st + j / (N/2^st)).  The inverse runs Gentleman-Sande butterflies
-// with psi^-brv(.) from the smallest distance up and folds N^-1 into its last
-// stage.
-//
-// Decomposition: a limb of N = 2^(A+B) residues is seen as a 2^A x 2^B matrix
-// (row p, column c at index p 2^B + c).  The first A forward stages only mix
-// elements of one column; the last B only mix elements of one row.  So the
-// forward transform is a column pass then a row pass, the inverse a row pass
-// then a column pass, each a size-2^A or 2^B sub-transform that lives in LDS:
-//   * a workgroup of 256 threads owns a 4096-residue tile (32 KiB + padding):
-//     16 columns x 256 rows, or 16 rows x 256, so every global access of a
-//     wavefront is a run of whole 128-byte lines;
-//   * inside the tile every thread holds 16 residues in registers and performs
-//     up to 4 butterfly stages on them (a radix-16 round), then the tile is
-//     exchanged through LDS for the next round;
-//   * values stay in Harvey's lazy ranges ([0, 4q) forward, [0, 2q) inverse)
-//     between stages and passes and are reduced to [0, q) at the last store.
-// N <= 4096 is done in one pass by one workgroup per limb.
+// Negacyclic NTT / INTT kernels of single operations; the device code is in
+// ntt_dev.hpp (shared with the batched kernels).
 #include <hip/hip_runtime.h>
 
-#include "modarith.hpp"
-#include "rf_internal.hpp"
+#include "ntt_dev.hpp"
 
 namespace rf {
-
-constexpr int kTile = 4096;
-constexpr int kThreads = 256;
-
-__device__ __forceinline__ void ct_bfly(uint64_t &x, uint64_t &y, uint64_t w, uint64_t wp, uint64_t q,
-                                        uint64_t q2) {
-    uint64_t xr = x >= q2 ? x - q2 : x;       // [0, 2q)
-    uint64_t t = shoup_lazy(y, w, wp, q);     // [0, 2q)
-    x = xr + t;                               // [0, 4q)
-    y = xr - t + q2;                          // (0, 4q)
-}
-
-__device__ __forceinline__ void gs_bfly(uint64_t &x, uint64_t &y, uint64_t w, uint64_t wp, uint64_t q,
-                                        uint64_t q2) {
-    uint64_t s = x + y;                       // x, y in [0, 2q)
-    s = s >= q2 ? s - q2 : s;
-    uint64_t d = x - y + q2;                  // (0, 4q)
-    x = s;
-    y = shoup_lazy(d, w, wp, q);              // [0, 2q)
-}
-
-__device__ __forceinline__ void gs_bfly_last(uint64_t &x, uint64_t &y, const PrimeConst &pc, uint64_t q2) {
-    uint64_t s = x + y;
-    uint64_t d = x - y + q2;
-    x = shoup_lazy(s, pc.ninv, pc.ninv_p, pc.q);
-    y = shoup_lazy(d, pc.wlast, pc.wlast_p, pc.q);
-}
-
-// One round of C butterfly stages of a size-2^S_LOG sub-transform held in LDS
-// (element p of sub-transform u at lds[p * ldu + u]).  Thread t of the
-// sub-transform owns 16 residues: 16 / 2^C groups of 2^C residues spaced by
-// the round's smallest distance 2^DL.
-template <int S_LOG, int ST0, int C, bool FWD, bool SCALE_LAST>
-__device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, uint32_t tw_base,
-                                          const TwPair *__restrict__ tw, const PrimeConst &pc) {
-    constexpr int G = 1 << C;
-    constexpr int NG = 16 / G;
-    constexpr int DL = FWD ? (S_LOG - ST0 - C) : ST0;
-    const uint64_t q = pc.q, q2 = 2 * q;
-#pragma unroll
-    for (int gi = 0; gi < NG; ++gi) {
-        const int grp = t * NG + gi;
-        const int lo = grp & ((1 << DL) - 1);
-        const int hi = grp >> DL;
-        const int base = (hi << (DL + C)) + lo;
-        uint64_t v[G];
-#pragma unroll
-        for (int e = 0; e < G; ++e) v[e] = lds[(base + (e << DL)) * ldu + u];
-        if constexpr (FWD) {
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int st = ST0 + c;
-                const int h = G >> (c + 1);
-#pragma unroll
-                for (int e = 0; e < G; ++e) {
-                    if (e & h) continue;
-                    const int p = base + (e << DL);
-                    const TwPair w = tw[(tw_base << st) + (uint32_t)(p >> (S_LOG - st))];
-                    ct_bfly(v[e], v[e + h], w.w, w.wp, q, q2);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int us = ST0 + c;
-                const int h = 1 << c;
-#pragma unroll
-                for (int e = 0; e < G; ++e) {
-                    if (e & h) continue;
-                    if (SCALE_LAST && us == S_LOG - 1) {
-                        gs_bfly_last(v[e], v[e + h], pc, q2);
-                    } else {
-                        const int p = base + (e << DL);
-                        const TwPair w = tw[(tw_base << (S_LOG - us - 1)) + (uint32_t)(p >> (us + 1))];
-                        gs_bfly(v[e], v[e + h], w.w, w.wp, q, q2);
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < G; ++e) lds[(base + (e << DL)) * ldu + u] = v[e];
-    }
-}
-
-// All rounds of a size-2^S_LOG sub-transform: radix-16 rounds then one shorter round.
-template <int S_LOG, bool FWD, bool SCALE_LAST>
-__device__ __forceinline__ void ntt_rounds(uint64_t *lds, int ldu, int u, int t, uint32_t tw_base,
-                                           const TwPair *__restrict__ tw, const PrimeConst &pc) {
-    static_assert(S_LOG >= 5 && S_LOG <= 12, "sub-transform size");
-    ntt_round<S_LOG, 0, 4, FWD, false>(lds, ldu, u, t, tw_base, tw, pc);
-    __syncthreads();
-    if constexpr (S_LOG <= 8) {
-        ntt_round<S_LOG, 4, S_LOG - 4, FWD, SCALE_LAST>(lds, ldu, u, t, tw_base, tw, pc);
-    } else {
-        ntt_round<S_LOG, 4, 4, FWD, false>(lds, ldu, u, t, tw_base, tw, pc);
-        __syncthreads();
-        ntt_round<S_LOG, 8, S_LOG - 8, FWD, SCALE_LAST>(lds, ldu, u, t, tw_base, tw, pc);
-    }
-    __syncthreads();
-}
 
 struct LimbView {
     const uint64_t *in;
@@ -144,70 +22,22 @@ __device__ __forceinline__ LimbView limb_view(const NttBatch &b, int log_n) {
     return v;
 }
 
-// Column pass: sub-transforms are columns (2^A rows, stride 2^B).  Forward: the
-// first A stages (output lazy in [0, 4q)); inverse: the last A stages with the
-// N^-1 scaling (output in [0, q)).
 template <int A, int B, bool FWD>
 __global__ __launch_bounds__(kThreads) void ntt_cols_kernel(NttBatch b, const TwPair *__restrict__ tw_all,
                                                             const PrimeConst *__restrict__ pcs) {
-    constexpr int S = 1 << A;
-    constexpr int U = kTile / S;
-    constexpr int LDU = U + 1;
-    __shared__ uint64_t lds[S * LDU];
+    __shared__ uint64_t lds[(1 << A) * (kTile / (1 << A) + 1)];
     const LimbView v = limb_view(b, A + B);
     const PrimeConst pc = pcs[v.g];
-    const TwPair *tw = tw_all + ((size_t)v.g << (A + B));
-    const int col0 = blockIdx.x * U;
-#pragma unroll
-    for (int r = 0; r < kTile / kThreads; ++r) {
-        const int idx = threadIdx.x + r * kThreads;
-        const int row = idx / U, col = idx % U;
-        lds[row * LDU + col] = v.in[((size_t)row << B) + col0 + col];
-    }
-    __syncthreads();
-    const int u = threadIdx.x % U, t = threadIdx.x / U;
-    ntt_rounds<A, FWD, !FWD>(lds, LDU, u, t, 1u, tw, pc);
-#pragma unroll
-    for (int r = 0; r < kTile / kThreads; ++r) {
-        const int idx = threadIdx.x + r * kThreads;
-        const int row = idx / U, col = idx % U;
-        uint64_t x = lds[row * LDU + col];
-        if (!FWD) x = csub(x, pc.q);
-        v.out[((size_t)row << B) + col0 + col] = x;
-    }
+    ntt_cols_unit<A, B, FWD>(lds, v.in, v.out, tw_all + ((size_t)v.g << (A + B)), pc, blockIdx.x);
 }
 
-// Row pass: sub-transforms are rows (2^B contiguous residues).  Forward: the last
-// B stages (output in [0, q)); inverse: the first B stages (output lazy in [0, 2q)).
 template <int A, int B, bool FWD>
 __global__ __launch_bounds__(kThreads) void ntt_rows_kernel(NttBatch b, const TwPair *__restrict__ tw_all,
                                                             const PrimeConst *__restrict__ pcs) {
-    constexpr int S = 1 << B;
-    constexpr int U = kTile / S;
-    constexpr int LDU = U + 1;
-    __shared__ uint64_t lds[S * LDU];
+    __shared__ uint64_t lds[(1 << B) * (kTile / (1 << B) + 1)];
     const LimbView v = limb_view(b, A + B);
     const PrimeConst pc = pcs[v.g];
-    const TwPair *tw = tw_all + ((size_t)v.g << (A + B));
-    const int row0 = blockIdx.x * U;
-#pragma unroll
-    for (int r = 0; r < kTile / kThreads; ++r) {
-        const int idx = threadIdx.x + r * kThreads;
-        const int row = idx >> B, p = idx & (S - 1);
-        lds[p * LDU + row] = v.in[((size_t)(row0 + row) << B) + p];
-    }
-    __syncthreads();
-    const int u = threadIdx.x % U, t = threadIdx.x / U;
-    ntt_rounds<B, FWD, false>(lds, LDU, u, t, (1u << A) + row0 + u, tw, pc);
-    const uint64_t q2 = 2 * pc.q;
-#pragma unroll
-    for (int r = 0; r < kTile / kThreads; ++r) {
-        const int idx = threadIdx.x + r * kThreads;
-        const int row = idx >> B, p = idx & (S - 1);
-        uint64_t x = lds[p * LDU + row];
-        if (FWD) x = csub(csub(x, q2), pc.q);
-        v.out[((size_t)(row0 + row) << B) + p] = x;
-    }
+    ntt_rows_unit<A, B, FWD>(lds, v.in, v.out, tw_all + ((size_t)v.g << (A + B)), pc, blockIdx.x);
 }
 
 // Whole limb in one workgroup (N = 2^LOGN <= 4096).
