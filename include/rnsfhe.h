@@ -154,6 +154,49 @@ int rf_tensor(const rf_ctx *ctx, const uint64_t *a, const uint64_t *b, uint64_t 
 int rf_automorphism(const rf_ctx *ctx, const uint64_t *in, uint64_t *out, uint32_t galois_elt,
                     uint32_t n_limbs, uint32_t n_polys, void *stream);
 
+/* ---- Batched HMult+Relin (many ciphertexts, mixed ring degree and level) ----
+ *
+ * A plan fixes a list of independent HMult+Relin items; each item names the
+ * context of its own ring degree (contexts of one prime chain at N = 2^13..2^16
+ * with the same alpha and special primes), its operands, relinearisation key,
+ * output and limb count.  rf_batch_hmult_relin enqueues the whole batch as 13
+ * launches, one per step of the chain (tensor, INTT, ModUp conversion, NTT,
+ * inner product, INTT of the P-limbs, ModDown conversion, NTT, tail), each a
+ * persistent kernel over the work units of every item; rf_batch_graph_launch
+ * replays the same launches captured once in a hipGraph.  Every item's output
+ * is bit-identical to rf_hmult_relin on the same operands.  The plan owns a
+ * small device job table (allocated by rf_batch_create, never during
+ * execution) and refers to the caller's workspace, which must stay valid and
+ * untouched by other work while the plan is in use; two launches of one plan
+ * must not overlap.  Operands, keys and outputs are caller-owned device
+ * memory, outputs must not alias inputs. */
+typedef struct rf_batch rf_batch;
+
+typedef struct rf_batch_item {
+    const rf_ctx *ctx;      /* context of this item's ring degree */
+    const uint64_t *a;      /* [2][n_limbs][N], NTT domain */
+    const uint64_t *b;      /* [2][n_limbs][N], NTT domain */
+    const uint64_t *rlk;    /* [dnum][2][L + k][N] relinearisation key of ctx */
+    uint64_t *out;          /* [2][n_limbs][N] */
+    uint32_t n_limbs;       /* Q-limbs of this item, 1 <= n_limbs <= L */
+} rf_batch_item;
+
+/* Workspace bytes for a batch (0 if the items are invalid). */
+size_t rf_batch_workspace_bytes(const rf_batch_item *items, uint32_t n_items);
+/* Build a plan (copies the item list; uploads the job tables). */
+int rf_batch_create(const rf_batch_item *items, uint32_t n_items, void *workspace,
+                    size_t workspace_bytes, rf_batch **out);
+void rf_batch_destroy(rf_batch *plan);
+/* Tuning knob: number of persistent workgroups of launch `stage` (0..12);
+ * 0 = one workgroup per work unit.  Invalidates a captured graph. */
+int rf_batch_set_grid(rf_batch *plan, uint32_t stage, uint32_t workgroups);
+/* Work units of launch `stage` (or a negative RF_E* code). */
+int rf_batch_stage_units(const rf_batch *plan, uint32_t stage);
+/* Enqueue the batch on `stream`. */
+int rf_batch_hmult_relin(rf_batch *plan, void *stream);
+/* Same, through a hipGraph captured on the first call (and after a grid change). */
+int rf_batch_graph_launch(rf_batch *plan, void *stream);
+
 /* Measurement support.  While enabled, every kernel launch of the library is
  * bracketed by two HIP events recorded on the launch's own stream (a few
  * microseconds of overhead per launch).  rf_profile_read waits for the recorded

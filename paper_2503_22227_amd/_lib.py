@@ -35,6 +35,17 @@ class rf_params(ctypes.Structure):
     ]
 
 
+class rf_batch_item(ctypes.Structure):
+    _fields_ = [
+        ("ctx", ctypes.c_void_p),
+        ("a", ctypes.c_void_p),
+        ("b", ctypes.c_void_p),
+        ("rlk", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("n_limbs", _u32),
+    ]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError("librnsfhe.so is not built (run __graft_entry__.build() or "
                       "python paper_2503_22227_amd/build.py): %s" % LIB_PATH)
@@ -54,6 +65,13 @@ _SIGS = {
     "rf_modswitch": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _sz, _vp]),
     "rf_tensor": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32, _vp]),
     "rf_automorphism": (ctypes.c_int, [_vp, _vp, _vp, _u32, _u32, _u32, _vp]),
+    "rf_batch_workspace_bytes": (_sz, [ctypes.POINTER(rf_batch_item), _u32]),
+    "rf_batch_create": (ctypes.c_int, [ctypes.POINTER(rf_batch_item), _u32, _vp, _sz, ctypes.POINTER(_vp)]),
+    "rf_batch_destroy": (None, [_vp]),
+    "rf_batch_set_grid": (ctypes.c_int, [_vp, _u32, _u32]),
+    "rf_batch_stage_units": (ctypes.c_int, [_vp, _u32]),
+    "rf_batch_hmult_relin": (ctypes.c_int, [_vp, _vp]),
+    "rf_batch_graph_launch": (ctypes.c_int, [_vp, _vp]),
     "rf_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "rf_profile_read": (ctypes.c_int, [ctypes.c_char_p, _sz]),
     "rf_last_error": (ctypes.c_char_p, []),

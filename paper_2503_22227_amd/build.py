@@ -8,7 +8,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librnsfhe.so")
-SOURCES = ["context.hip", "ntt.hip", "keyswitch.hip", "capi.hip", "profile.hip"]
+SOURCES = ["context.hip", "ntt.hip", "keyswitch.hip", "capi.hip", "profile.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1,0 +1,416 @@
+// Batched HMult+Relin over many ciphertexts of different ring degrees and
+// levels: every step of the chain (tensor, INTT, ModUp conversion, NTT, inner
+// product, INTT of the P-limbs, ModDown conversion, NTT, tail) is ONE launch
+// of a persistent kernel that walks the work units of all items.
+//
+// Work units: an NTT pass unit is one 4096-residue tile of one limb
+// (N / 4096 tiles per limb); an element-wise unit is 256 coefficients of one
+// limb, digit or polynomial.  The units of a step are numbered item after
+// item (prefix sums in the job tables); workgroup w of a launch with G
+// workgroups takes the contiguous range [w * per, (w + 1) * per) of units,
+// finds its first item by binary search and then walks forward, so the
+// per-unit overhead is a compare.  Mixed ring degrees are dispatched per unit
+// to the matching template instantiation of the shared device code
+// (ntt_dev.hpp, ks_dev.hpp), so an item's results are bit-identical to the
+// single-operation path.  The launch sequence can be captured once in a
+// hipGraph and replayed; the job tables are device data, so the graph does not
+// depend on anything but the plan.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "ks_dev.hpp"
+#include "ntt_dev.hpp"
+
+namespace rf {
+
+enum BatchStage {
+    kTensor = 0,
+    kInttD0, kInttD1,       // INTT of d2: row pass, column pass
+    kModupConv,
+    kNttExt0, kNttExt1,     // NTT of the ModUp output: column pass, row pass
+    kInnerProduct,
+    kInttP0, kInttP1,       // INTT of the P-limbs
+    kModdownConv,
+    kNttConv0, kNttConv1,   // NTT of the ModDown conversion
+    kTail,
+    kStages
+};
+
+struct KsJob {
+    const uint64_t *a, *b, *evk;
+    uint64_t *out;
+    uint64_t *d2, *d_coeff, *ext, *ip, *conv;
+    const PrimeConst *pcs;
+    const uint64_t *modup_tab;
+    uint64_t modup_stride;
+    const uint64_t *moddown_tab;
+    const uint64_t *pinv;
+    uint32_t log_n, nl, L, K, alpha;
+    uint32_t unit_begin[kStages];
+};
+
+struct NttJob {
+    NttBatch b;
+    const TwPair *tw_all;
+    const PrimeConst *pcs;
+    uint32_t log_n;
+    uint32_t unit_begin;
+};
+
+template <typename J>
+__device__ __forceinline__ uint32_t unit_begin_of(const J &j, int stage);
+template <>
+__device__ __forceinline__ uint32_t unit_begin_of<KsJob>(const KsJob &j, int stage) {
+    return j.unit_begin[stage];
+}
+template <>
+__device__ __forceinline__ uint32_t unit_begin_of<NttJob>(const NttJob &j, int) {
+    return j.unit_begin;
+}
+
+// Last job whose first unit is <= u (jobs sorted by unit_begin).
+template <typename J>
+__device__ __forceinline__ uint32_t find_job(const J *jobs, uint32_t njobs, uint32_t u, int stage) {
+    uint32_t lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (unit_begin_of(jobs[mid], stage) <= u) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(kEw) void ks_batched_kernel(const KsJob *__restrict__ jobs, uint32_t njobs,
+                                                         uint32_t total, uint32_t per_wg) {
+    const uint32_t u0 = blockIdx.x * per_wg;
+    const uint32_t u1 = min(total, u0 + per_wg);
+    if (u0 >= u1) return;
+    uint32_t j = find_job(jobs, njobs, u0, STAGE);
+    for (uint32_t u = u0; u < u1; ++u) {
+        while (j + 1 < njobs && jobs[j + 1].unit_begin[STAGE] <= u) ++j;
+        const KsJob &J = jobs[j];
+        const uint32_t local = u - J.unit_begin[STAGE];
+        const uint32_t cshift = J.log_n - 8;  // N / 256 blocks per row
+        const uint32_t gy = local >> cshift, gx = local & ((1u << cshift) - 1);
+        if constexpr (STAGE == kTensor) {
+            tensor_unit(J.a, J.b, J.out, J.d2, J.pcs, J.log_n, J.nl, gx, gy);
+        } else if constexpr (STAGE == kModupConv) {
+            modup_bconv_unit(J.d_coeff, J.ext, J.pcs, J.modup_tab, J.modup_stride, J.log_n, J.nl, J.L, J.K, J.alpha,
+                             gx, gy);
+        } else if constexpr (STAGE == kInnerProduct) {
+            inner_product_unit(J.d2, J.ext, J.evk, J.ip, J.pcs, J.log_n, J.nl, J.L, J.K, J.alpha, gx, gy);
+        } else if constexpr (STAGE == kModdownConv) {
+            moddown_bconv_unit(J.ip, J.conv, J.pcs, J.moddown_tab, J.log_n, J.nl, J.L, J.K, gx, gy);
+        } else if constexpr (STAGE == kTail) {
+            const size_t poly = (size_t)J.nl << J.log_n;
+            moddown_tail_unit(J.ip, J.conv, J.out, J.out + poly, J.out, J.pcs, J.pinv, J.log_n, J.nl, J.K, gx, gy);
+        }
+    }
+}
+
+// One pass of a batched (I)NTT: FIRST = the pass that reads b.in (forward:
+// columns; inverse: rows); the second pass works in place on b.out.
+template <bool FWD, bool FIRST>
+__global__ __launch_bounds__(kThreads) void ntt_batched_kernel(const NttJob *__restrict__ jobs, uint32_t njobs,
+                                                               uint32_t total, uint32_t per_wg) {
+    __shared__ uint64_t lds[kNttLdsWords];
+    constexpr bool COLS = FWD == FIRST;
+    const uint32_t u0 = blockIdx.x * per_wg;
+    const uint32_t u1 = min(total, u0 + per_wg);
+    if (u0 >= u1) return;
+    uint32_t j = find_job(jobs, njobs, u0, 0);
+    for (uint32_t u = u0; u < u1; ++u) {
+        while (j + 1 < njobs && jobs[j + 1].unit_begin <= u) ++j;
+        const NttJob &J = jobs[j];
+        const uint32_t local = u - J.unit_begin;
+        const uint32_t tshift = J.log_n - 12;  // N / 4096 tiles per limb
+        const uint32_t limb = local >> tshift, tile = local & ((1u << tshift) - 1);
+        const uint32_t poly = limb / J.b.per_poly, li = limb - poly * J.b.per_poly;
+        const uint32_t g = J.b.pmap ? (uint32_t)J.b.pmap[li] : J.b.prime_base + li;
+        const uint64_t *base_in = FIRST ? J.b.in : J.b.out;
+        const uint64_t in_stride = FIRST ? J.b.in_poly_stride : J.b.out_poly_stride;
+        const uint64_t *in = base_in + (size_t)poly * in_stride + ((size_t)li << J.log_n);
+        uint64_t *out = J.b.out + (size_t)poly * J.b.out_poly_stride + ((size_t)li << J.log_n);
+        const PrimeConst pc = J.pcs[g];
+        const TwPair *tw = J.tw_all + ((size_t)g << J.log_n);
+        switch (J.log_n) {
+            case 16:
+                if constexpr (COLS) ntt_cols_unit<8, 8, FWD>(lds, in, out, tw, pc, tile);
+                else ntt_rows_unit<8, 8, FWD>(lds, in, out, tw, pc, tile);
+                break;
+            case 15:
+                if constexpr (COLS) ntt_cols_unit<8, 7, FWD>(lds, in, out, tw, pc, tile);
+                else ntt_rows_unit<8, 7, FWD>(lds, in, out, tw, pc, tile);
+                break;
+            case 14:
+                if constexpr (COLS) ntt_cols_unit<7, 7, FWD>(lds, in, out, tw, pc, tile);
+                else ntt_rows_unit<7, 7, FWD>(lds, in, out, tw, pc, tile);
+                break;
+            default:
+                if constexpr (COLS) ntt_cols_unit<7, 6, FWD>(lds, in, out, tw, pc, tile);
+                else ntt_rows_unit<7, 6, FWD>(lds, in, out, tw, pc, tile);
+                break;
+        }
+    }
+}
+
+}  // namespace rf
+
+using namespace rf;
+
+struct rf_batch {
+    int device = 0;
+    uint32_t n_items = 0;
+    KsJob *d_jobs = nullptr;
+    NttJob *d_ntt[4] = {nullptr, nullptr, nullptr, nullptr};  // INTT d2, NTT ext, INTT P, NTT conv
+    uint32_t total[kStages] = {0};
+    uint32_t grid[kStages] = {0};  // workgroups per launch; 0 = one per unit
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t capture_stream = nullptr;
+};
+
+namespace {
+
+size_t item_ws_limbs(const rf_ctx *c, uint32_t nl) {
+    const ModupLevel &lv = c->modup_levels[nl];
+    return (size_t)nl + (size_t)nl + lv.ext_limbs + 2 * (size_t)(nl + c->K) + 2 * (size_t)nl;
+}
+
+int validate(const rf_batch_item *items, uint32_t n) {
+    if (!items || n == 0) return fail(RF_EINVAL, "rf_batch: no items");
+    const rf_ctx *c0 = items[0].ctx;
+    for (uint32_t i = 0; i < n; ++i) {
+        const rf_batch_item &it = items[i];
+        const rf_ctx *c = it.ctx;
+        if (!c || !it.a || !it.b || !it.rlk || !it.out) return fail(RF_EINVAL, "rf_batch: null pointer in an item");
+        if (c->scheme != RF_CKKS && c->scheme != RF_BGV) return fail(RF_EUNSUPPORTED, "rf_batch: CKKS or BGV");
+        if (c->log_n < 13 || c->log_n > 16) return fail(RF_EUNSUPPORTED, "rf_batch: ring degree 2^13..2^16");
+        if (it.n_limbs < 1 || it.n_limbs > c->L) return fail(RF_ELEVEL, "rf_batch: limb count out of range");
+        if (c->device != c0->device) return fail(RF_EINVAL, "rf_batch: items on different devices");
+        if (it.out == it.a || it.out == it.b) return fail(RF_EINVAL, "rf_batch: out aliases an input");
+    }
+    return RF_OK;
+}
+
+uint32_t stage_units(const rf_ctx *c, uint32_t nl, int stage) {
+    const uint32_t chunks = c->n / kEw, tiles = c->n / kTile;
+    const uint32_t dn = (nl + c->alpha - 1) / c->alpha;
+    switch (stage) {
+        case kTensor: return nl * chunks;
+        case kInttD0: case kInttD1: return nl * tiles;
+        case kModupConv: return dn * chunks;
+        case kNttExt0: case kNttExt1: return c->modup_levels[nl].ext_limbs * tiles;
+        case kInnerProduct: return (nl + c->K) * chunks;
+        case kInttP0: case kInttP1: return 2 * c->K * tiles;
+        case kModdownConv: return 2 * chunks;
+        case kNttConv0: case kNttConv1: return 2 * nl * tiles;
+        case kTail: return 2 * nl * chunks;
+    }
+    return 0;
+}
+
+int enqueue(rf_batch *p, hipStream_t s, bool profile) {
+    static const char *names[kStages] = {"batch_tensor", "batch_ntt_inv_rows", "batch_ntt_inv_cols",
+                                         "batch_modup_bconv", "batch_ntt_fwd_cols", "batch_ntt_fwd_rows",
+                                         "batch_inner_product", "batch_ntt_inv_rows", "batch_ntt_inv_cols",
+                                         "batch_moddown_bconv", "batch_ntt_fwd_cols", "batch_ntt_fwd_rows",
+                                         "batch_moddown_tail"};
+    for (int st = 0; st < kStages; ++st) {
+        const uint32_t total = p->total[st];
+        if (total == 0) continue;
+        const uint32_t g = p->grid[st] == 0 ? total : std::min(total, p->grid[st]);
+        const uint32_t per = (total + g - 1) / g;
+        const uint32_t blocks = (total + per - 1) / per;
+        const uint32_t nj = p->n_items;
+        ProfScope prof(profile ? names[st] : nullptr, s);
+        switch (st) {
+            case kTensor: hipLaunchKernelGGL(ks_batched_kernel<kTensor>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
+            case kModupConv: hipLaunchKernelGGL(ks_batched_kernel<kModupConv>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
+            case kInnerProduct: hipLaunchKernelGGL(ks_batched_kernel<kInnerProduct>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
+            case kModdownConv: hipLaunchKernelGGL(ks_batched_kernel<kModdownConv>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
+            case kTail: hipLaunchKernelGGL(ks_batched_kernel<kTail>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
+            case kInttD0: hipLaunchKernelGGL((ntt_batched_kernel<false, true>), blocks, kThreads, 0, s, p->d_ntt[0], nj, total, per); break;
+            case kInttD1: hipLaunchKernelGGL((ntt_batched_kernel<false, false>), blocks, kThreads, 0, s, p->d_ntt[0], nj, total, per); break;
+            case kNttExt0: hipLaunchKernelGGL((ntt_batched_kernel<true, true>), blocks, kThreads, 0, s, p->d_ntt[1], nj, total, per); break;
+            case kNttExt1: hipLaunchKernelGGL((ntt_batched_kernel<true, false>), blocks, kThreads, 0, s, p->d_ntt[1], nj, total, per); break;
+            case kInttP0: hipLaunchKernelGGL((ntt_batched_kernel<false, true>), blocks, kThreads, 0, s, p->d_ntt[2], nj, total, per); break;
+            case kInttP1: hipLaunchKernelGGL((ntt_batched_kernel<false, false>), blocks, kThreads, 0, s, p->d_ntt[2], nj, total, per); break;
+            case kNttConv0: hipLaunchKernelGGL((ntt_batched_kernel<true, true>), blocks, kThreads, 0, s, p->d_ntt[3], nj, total, per); break;
+            case kNttConv1: hipLaunchKernelGGL((ntt_batched_kernel<true, false>), blocks, kThreads, 0, s, p->d_ntt[3], nj, total, per); break;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(RF_EHIP, std::string("batched launch: ") + hipGetErrorString(e));
+    }
+    return RF_OK;
+}
+
+void drop_graph(rf_batch *p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" size_t rf_batch_workspace_bytes(const rf_batch_item *items, uint32_t n) {
+    if (validate(items, n)) return 0;
+    size_t limbs = 0;
+    for (uint32_t i = 0; i < n; ++i) limbs += item_ws_limbs(items[i].ctx, items[i].n_limbs) * items[i].ctx->n;
+    return limbs * 8;
+}
+
+extern "C" int rf_batch_create(const rf_batch_item *items, uint32_t n, void *ws, size_t ws_bytes, rf_batch **out) {
+    int rc;
+    if (!out) return fail(RF_EINVAL, "rf_batch_create: null out");
+    *out = nullptr;
+    if ((rc = validate(items, n))) return rc;
+    const size_t need = rf_batch_workspace_bytes(items, n);
+    if (!ws || ws_bytes < need)
+        return fail(RF_EWORKSPACE, "rf_batch_create: workspace of " + std::to_string(ws_bytes) + " bytes, need " +
+                                       std::to_string(need));
+    std::vector<KsJob> jobs(n);
+    std::vector<NttJob> ntt[4];
+    for (auto &v : ntt) v.resize(n);
+    uint32_t acc[kStages] = {0};
+    uint64_t *w = (uint64_t *)ws;
+    for (uint32_t i = 0; i < n; ++i) {
+        const rf_batch_item &it = items[i];
+        const rf_ctx *c = it.ctx;
+        const uint32_t nl = it.n_limbs;
+        const size_t N = c->n;
+        const ModupLevel &lv = c->modup_levels[nl];
+        KsJob &J = jobs[i];
+        J.a = it.a;
+        J.b = it.b;
+        J.evk = it.rlk;
+        J.out = it.out;
+        J.d2 = w;
+        J.d_coeff = J.d2 + (size_t)nl * N;
+        J.ext = J.d_coeff + (size_t)nl * N;
+        J.ip = J.ext + (size_t)lv.ext_limbs * N;
+        J.conv = J.ip + 2 * (size_t)(nl + c->K) * N;
+        w = J.conv + 2 * (size_t)nl * N;
+        J.pcs = c->d_pc;
+        J.modup_tab = c->d_modup;
+        J.modup_stride = c->modup_stride;
+        J.moddown_tab = c->scheme == RF_BGV ? c->d_moddown_t : c->d_moddown;
+        J.pinv = c->d_moddown + moddown_pinv_off(c);
+        J.log_n = c->log_n;
+        J.nl = nl;
+        J.L = c->L;
+        J.K = c->K;
+        J.alpha = c->alpha;
+        for (int st = 0; st < kStages; ++st) {
+            J.unit_begin[st] = acc[st];
+            acc[st] += stage_units(c, nl, st);
+        }
+        const uint64_t ipstride = (uint64_t)(nl + c->K) * N;
+        NttBatch bd{J.d2, J.d_coeff, 0, 0, nl, 1, 0, nullptr};
+        NttBatch be{J.ext, J.ext, 0, 0, lv.ext_limbs, 1, 0, c->d_pmaps + lv.pmap_off};
+        NttBatch bp{J.ip + (size_t)nl * N, J.ip + (size_t)nl * N, ipstride, ipstride, c->K, 2, c->L, nullptr};
+        NttBatch bc{J.conv, J.conv, (uint64_t)nl * N, (uint64_t)nl * N, nl, 2, 0, nullptr};
+        const NttBatch bs[4] = {bd, be, bp, bc};
+        const int first_stage[4] = {kInttD0, kNttExt0, kInttP0, kNttConv0};
+        for (int k = 0; k < 4; ++k) {
+            ntt[k][i].b = bs[k];
+            ntt[k][i].tw_all = (k == 1 || k == 3) ? c->d_tw_fwd : c->d_tw_inv;
+            ntt[k][i].pcs = c->d_pc;
+            ntt[k][i].log_n = c->log_n;
+            ntt[k][i].unit_begin = J.unit_begin[first_stage[k]];
+        }
+    }
+    rf_batch *p = new rf_batch();
+    p->device = items[0].ctx->device;
+    p->n_items = n;
+    for (int st = 0; st < kStages; ++st) p->total[st] = acc[st];
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(p->device);
+    bool ok = hipMalloc((void **)&p->d_jobs, sizeof(KsJob) * n) == hipSuccess &&
+              hipMemcpy(p->d_jobs, jobs.data(), sizeof(KsJob) * n, hipMemcpyHostToDevice) == hipSuccess;
+    for (int k = 0; k < 4 && ok; ++k)
+        ok = hipMalloc((void **)&p->d_ntt[k], sizeof(NttJob) * n) == hipSuccess &&
+             hipMemcpy(p->d_ntt[k], ntt[k].data(), sizeof(NttJob) * n, hipMemcpyHostToDevice) == hipSuccess;
+    (void)hipSetDevice(prev);
+    if (!ok) {
+        rf_batch_destroy(p);
+        return fail(RF_EHIP, "rf_batch_create: upload of the job tables");
+    }
+    *out = p;
+    return RF_OK;
+}
+
+extern "C" void rf_batch_destroy(rf_batch *p) {
+    if (!p) return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(p->device);
+    drop_graph(p);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    (void)hipFree(p->d_jobs);
+    for (auto *d : p->d_ntt) (void)hipFree(d);
+    (void)hipSetDevice(prev);
+    delete p;
+}
+
+extern "C" int rf_batch_set_grid(rf_batch *p, uint32_t stage, uint32_t workgroups) {
+    if (!p || stage >= (uint32_t)kStages) return fail(RF_EINVAL, "rf_batch_set_grid: bad stage");
+    if (p->grid[stage] != workgroups) {
+        p->grid[stage] = workgroups;
+        drop_graph(p);
+    }
+    return RF_OK;
+}
+
+extern "C" int rf_batch_stage_units(const rf_batch *p, uint32_t stage) {
+    if (!p || stage >= (uint32_t)kStages) return fail(RF_EINVAL, "rf_batch_stage_units: bad stage");
+    return (int)p->total[stage];
+}
+
+extern "C" int rf_batch_hmult_relin(rf_batch *p, void *stream) {
+    if (!p) return fail(RF_EINVAL, "rf_batch_hmult_relin: null plan");
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    if (prev != p->device) (void)hipSetDevice(p->device);
+    int rc = enqueue(p, (hipStream_t)stream, true);
+    if (prev != p->device) (void)hipSetDevice(prev);
+    return rc;
+}
+
+extern "C" int rf_batch_graph_launch(rf_batch *p, void *stream) {
+    if (!p) return fail(RF_EINVAL, "rf_batch_graph_launch: null plan");
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    if (prev != p->device) (void)hipSetDevice(p->device);
+    int rc = RF_OK;
+    if (!p->exec) {
+        if (!p->capture_stream && hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess)
+            rc = fail(RF_EHIP, "rf_batch_graph_launch: stream");
+        if (!rc && hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            rc = fail(RF_EHIP, "rf_batch_graph_launch: begin capture");
+        if (!rc) {
+            int erc = enqueue(p, p->capture_stream, false);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(p->capture_stream, &g);
+            if (erc) rc = erc;
+            else if (e != hipSuccess || !g) rc = fail(RF_EHIP, "rf_batch_graph_launch: end capture");
+            else {
+                p->graph = g;
+                if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) {
+                    drop_graph(p);
+                    rc = fail(RF_EHIP, "rf_batch_graph_launch: instantiate");
+                }
+            }
+            if (rc && g && !p->graph) (void)hipGraphDestroy(g);
+        }
+    }
+    if (!rc && hipGraphLaunch(p->exec, (hipStream_t)stream) != hipSuccess)
+        rc = fail(RF_EHIP, "rf_batch_graph_launch: launch");
+    if (prev != p->device) (void)hipSetDevice(prev);
+    return rc;
+}

@@ -36,6 +36,7 @@ hipEvent_t take_event() {
 }  // namespace
 
 ProfScope::ProfScope(const char *name, hipStream_t s) : idx_(-1), s_(s) {
+    if (!name) return;
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on) return;
     Rec r{name, take_event(), take_event()};

@@ -164,3 +164,57 @@ class Context:
 def galois_element(r: int, n: int) -> int:
     """5^r mod 2N: the automorphism that rotates CKKS slots left by r."""
     return pow(5, r, 2 * n)
+
+
+BATCH_STAGES = ("tensor", "intt_d2_rows", "intt_d2_cols", "modup_bconv", "ntt_ext_cols", "ntt_ext_rows",
+                "inner_product", "intt_p_rows", "intt_p_cols", "moddown_bconv", "ntt_conv_cols",
+                "ntt_conv_rows", "moddown_tail")
+
+
+class BatchPlan:
+    """A fixed list of independent HMult+Relin items (mixed ring degree and level)
+    executed as one launch per step of the chain, optionally through a hipGraph.
+
+    items: sequence of (ctx, a, b, rlk, out) with a, b, out of shape [2, limbs, N]."""
+
+    def __init__(self, items):
+        self._keep = list(items)
+        arr = (_lib.rf_batch_item * len(items))()
+        for i, (ctx, a, b, rlk, out) in enumerate(items):
+            arr[i] = _lib.rf_batch_item(ctx._h, _ptr(a), _ptr(b), _ptr(rlk), _ptr(out), a.shape[1])
+        nbytes = int(lib.rf_batch_workspace_bytes(arr, len(items)))
+        if nbytes == 0:
+            raise ValueError("invalid batch: %s" % lib.rf_last_error().decode())
+        dev = items[0][1].device
+        self.workspace = torch.empty((nbytes + 7) // 8, dtype=torch.int64, device=dev)
+        h = ctypes.c_void_p()
+        check(lib.rf_batch_create(arr, len(items), _ptr(self.workspace), nbytes, ctypes.byref(h)),
+              "rf_batch_create")
+        self._h = h
+        self.n_items = len(items)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.rf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, graph: bool = False) -> None:
+        if graph:
+            check(lib.rf_batch_graph_launch(self._h, _stream()), "rf_batch_graph_launch")
+        else:
+            check(lib.rf_batch_hmult_relin(self._h, _stream()), "rf_batch_hmult_relin")
+
+    def set_grid(self, stage: int, workgroups: int) -> None:
+        check(lib.rf_batch_set_grid(self._h, stage, workgroups), "rf_batch_set_grid")
+
+    def stage_units(self, stage: int) -> int:
+        n = lib.rf_batch_stage_units(self._h, stage)
+        if n < 0:
+            check(n, "rf_batch_stage_units")
+        return n

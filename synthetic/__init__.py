@@ -103,3 +103,21 @@ WORKLOADS = {
     "pdq": dict(scheme="ckks", log_n=16, log_nmax=16, q_bits=[60] + [45] * 23,
                 p_bits=[60] * 4, alpha=4, log_scale=45, seed=2503222274),
 }
+
+
+def batch_shapes(rng: np.random.Generator, items: int, log_n_choices, limbs_range):
+    """(log_n, limbs) of each batch item: ring degree uniform over the choices,
+    limb count uniform in [lo, hi]."""
+    lns = rng.choice(np.asarray(log_n_choices), size=items)
+    nls = rng.integers(limbs_range[0], limbs_range[1] + 1, size=items)
+    return [(int(a), int(b)) for a, b in zip(lns, nls)]
+
+
+def device_uniform_residues(moduli, n: int, generator, device):
+    """Like ``uniform_residues`` but drawn on a torch device with a seeded torch
+    Generator (for inputs too large to draw on the host); int64 tensor [len(moduli), n]."""
+    import torch
+    out = torch.empty((len(moduli), n), dtype=torch.int64, device=device)
+    for i, m in enumerate(moduli):
+        out[i] = torch.randint(0, int(m), (n,), generator=generator, device=device, dtype=torch.int64)
+    return out

@@ -1,0 +1,103 @@
+"""Batched HMult+Relin over mixed ring degrees and levels: every item of a batch
+(plain launches, graph replays, other grid settings) is bit-identical to the
+single-operation path, and sampled items are bit-identical to the oracle."""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import ckks as C
+from oracle import params as P
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint64)
+
+
+@pytest.fixture(scope="module")
+def batch():
+    from paper_2503_22227_amd import Context
+    w = synthetic.WORKLOADS["ckks_batch"]
+    pbase = P.make_params(w)
+    st = synthetic.streams(w["seed"])
+    rng = st["batch_shape"]
+    shapes = synthetic.batch_shapes(rng, 20, w["log_n_choices"], w["limbs_range"])
+    shapes += [(16, 24), (14, 4), (15, 9), (16, 1), (14, 17)]  # extremes and a 1-limb digit
+    ctxs, keys, params = {}, {}, {}
+    for ln in sorted({s[0] for s in shapes}):
+        p = pbase.at_degree(ln)
+        params[ln] = p
+        ctxs[ln] = Context(p.q, p.p, p.log_n, p.alpha, log_nmax=p.log_nmax)
+        qp = p.q + p.p
+        keys[ln] = np.stack([np.stack([synthetic.uniform_residues(st["rlk"], qp, p.n) for _ in range(2)])
+                             for _ in range(p.dnum())])
+    dkeys = {ln: dev(k) for ln, k in keys.items()}
+    items, host_in = [], []
+    for ln, nl in shapes:
+        p = params[ln]
+        a = np.stack([synthetic.uniform_residues(st["ct_a"], p.q[:nl], p.n) for _ in range(2)])
+        b = np.stack([synthetic.uniform_residues(st["ct_a"], p.q[:nl], p.n) for _ in range(2)])
+        host_in.append((a, b))
+        out = torch.zeros((2, nl, p.n), dtype=torch.int64, device="cuda")
+        items.append((ctxs[ln], dev(a), dev(b), dkeys[ln], out))
+    return dict(shapes=shapes, params=params, ctxs=ctxs, keys=keys, dkeys=dkeys, items=items, host_in=host_in)
+
+
+def single(batch):
+    res = []
+    for (ctx, a, b, rlk, out) in batch["items"]:
+        res.append(host(ctx.hmult_relin(a, b, rlk)))
+    return res
+
+
+def test_batched_equals_single_and_oracle(batch):
+    from paper_2503_22227_amd import BatchPlan
+    print("batch of %d items" % len(batch["items"]), flush=True)
+    ref = single(batch)
+    plan = BatchPlan(batch["items"])
+    plan.run(graph=False)
+    for i, (_, _, _, _, out) in enumerate(batch["items"]):
+        assert np.array_equal(host(out), ref[i]), i
+    # oracle on sampled items: the smallest and one full-size item
+    for i in (len(batch["items"]) - 4, len(batch["items"]) - 5):
+        ln, nl = batch["shapes"][i]
+        p = batch["params"][ln]
+        a, b = batch["host_in"][i]
+        want = C.hmult_relin(C.Ciphertext(a, 1.0), C.Ciphertext(b, 1.0), batch["keys"][ln], p)
+        assert np.array_equal(ref[i], want.data), i
+    plan.close()
+
+
+def test_graph_replays_and_grids(batch):
+    from paper_2503_22227_amd import BatchPlan
+    ref = single(batch)
+    plan = BatchPlan(batch["items"])
+    for rep in range(3):
+        for (_, _, _, _, out) in batch["items"]:
+            out.zero_()
+        plan.run(graph=True)
+        torch.cuda.synchronize()
+        for i, (_, _, _, _, out) in enumerate(batch["items"]):
+            assert np.array_equal(host(out), ref[i]), (rep, i)
+    for stage in range(13):
+        plan.set_grid(stage, 300)
+    for (_, _, _, _, out) in batch["items"]:
+        out.zero_()
+    plan.run(graph=True)
+    for i, (_, _, _, _, out) in enumerate(batch["items"]):
+        assert np.array_equal(host(out), ref[i]), i
+    plan.close()
+
+
+def test_batch_rejects_bad_items(batch):
+    from paper_2503_22227_amd import BatchPlan
+    ctx, a, b, rlk, out = batch["items"][0]
+    with pytest.raises(Exception):
+        BatchPlan([(ctx, a, b, rlk, a)])  # out aliases a
