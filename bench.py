@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the mixed-N batch section")
     ap.add_argument("--workload", default="ckks_n16_l24")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (HBM counter calibration)")
@@ -182,6 +183,11 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dominant,
                 "avg_us": round(kd["avg_us"], 3)}
 
+    batch = None
+    if not args.no_batch:
+        del m_out, r_out, ro_out
+        batch = batch_section(max(3, min(args.steps, 10)))
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
@@ -208,6 +214,7 @@ def main():
                 "rescale_us": round(t_rs / reps * 1e6, 2)},
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in sorted(kernels.items())},
         "roofline": roof,
+        "batch": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -252,6 +259,69 @@ def _ntt_limbs_per_launch(name: str, L: int, K: int, alpha: int) -> float:
     inv = [L, 2 * K] * 2 + [2]                       # INTT of d, of the P-limbs (x2 ops), rescale
     launches = fwd if "fwd" in name else inv
     return sum(launches) / len(launches)
+
+
+def batch_section(reps: int):
+    """256 HMult+Relin items of mixed N in {2^14, 2^15, 2^16} and 4..24 limbs: one graph
+    replay of the batched launches vs one HMult+Relin call per item on the same stream."""
+    import torch
+
+    import synthetic
+    from paper_2503_22227_amd import BatchPlan, Context, autotune
+    from paper_2503_22227_amd.params import chain_for
+
+    w = synthetic.WORKLOADS["ckks_batch"]
+    ch = chain_for(w)
+    st = synthetic.streams(w["seed"])
+    shapes = synthetic.batch_shapes(st["batch_shape"], w["items"], w["log_n_choices"], w["limbs_range"])
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(w["seed"])
+    qp = ch["q"] + ch["p"]
+    ctxs, keys = {}, {}
+    for ln in sorted({x[0] for x in shapes}):
+        ctxs[ln] = Context(ch["q"], ch["p"], ln, w["alpha"], log_nmax=w["log_nmax"])
+        n = 1 << ln
+        dnum = ctxs[ln].dnum
+        keys[ln] = torch.stack([torch.stack([synthetic.device_uniform_residues(qp, n, gen, "cuda")
+                                             for _ in range(2)]) for _ in range(dnum)])
+    items = []
+    for ln, nl in shapes:
+        n = 1 << ln
+        a = torch.stack([synthetic.device_uniform_residues(ch["q"][:nl], n, gen, "cuda") for _ in range(2)])
+        b = torch.stack([synthetic.device_uniform_residues(ch["q"][:nl], n, gen, "cuda") for _ in range(2)])
+        items.append((ctxs[ln], a, b, keys[ln], torch.empty_like(a)))
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps / 1e3
+
+    def plain():
+        for ctx, a, b, k, out in items:
+            ctx.hmult_relin(a, b, k, out=out)
+
+    t_plain = timed(plain)
+    plan = BatchPlan(items)
+    t_default = timed(lambda: plan.run(graph=True))
+    setting = autotune.tune(plan, shapes, reps=2, use_cache=False)
+    t_batch = timed(lambda: plan.run(graph=True))
+    n_items = len(items)
+    limb_bytes = sum(7 * nl * (8 << ln) for ln, nl in shapes)
+    out = {"workload": "256 CKKS HMult+Relin items, N in {2^14,2^15,2^16}, 4..24 limbs, k=4, alpha=8",
+           "items": n_items, "batched_items_per_s": round(n_items / t_batch, 1),
+           "plain_items_per_s": round(n_items / t_plain, 1), "speedup": round(t_plain / t_batch, 3),
+           "batched_ms": round(t_batch * 1e3, 3), "plain_ms": round(t_plain * 1e3, 3),
+           "batched_default_grid_ms": round(t_default * 1e3, 3), "autotuned_grid": setting,
+           "ciphertext_bytes_in_out": limb_bytes}
+    plan.close()
+    return out
 
 
 def cpu_baseline(w):
