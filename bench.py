@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed-N batch section")
+    ap.add_argument("--no-pdq", action="store_true", help="skip the private-query serving section")
+    ap.add_argument("--pdq-queries", type=int, default=60, help="queries per arrival-rate point")
     ap.add_argument("--workload", default="ckks_n16_l24")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (HBM counter calibration)")
@@ -188,6 +190,10 @@ def main():
         del m_out, r_out, ro_out
         batch = batch_section(max(3, min(args.steps, 10)))
 
+    serving = None
+    if not args.no_pdq:
+        serving = pdq_section(args.pdq_queries)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
@@ -215,6 +221,7 @@ def main():
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in sorted(kernels.items())},
         "roofline": roof,
         "batch": batch,
+        "pdq": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -322,6 +329,76 @@ def batch_section(reps: int):
            "ciphertext_bytes_in_out": limb_bytes}
     plan.close()
     return out
+
+
+def pdq_section(n_queries: int):
+    """Private-table range-sum queries at CKKS N=2^16, 24 limbs, alpha=4, scale 2^45 served
+    by the continuous-batching server: saturation rate from a burst, then Poisson
+    arrivals at 0.25 / 0.5 / 0.75 / 0.9 of it; p50/p99 latency (arrival to result on host)."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_2503_22227_amd import Context, pdq
+    from paper_2503_22227_amd.params import chain_for
+    from paper_2503_22227_amd.serve import GpuQueryExecutor, Request, Server
+
+    w = synthetic.WORKLOADS["pdq"]
+    ch = chain_for(w)
+    n = 1 << w["log_n"]
+    L = len(ch["q"])
+    ctx = Context(ch["q"], ch["p"], w["log_n"], w["alpha"], log_nmax=w["log_nmax"])
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(w["seed"])
+    qp = ch["q"] + ch["p"]
+
+    def key():
+        return torch.stack([torch.stack([synthetic.device_uniform_residues(qp, n, gen, "cuda") for _ in range(2)])
+                            for _ in range(ctx.dnum)])
+
+    keys = {"rlk": key()}
+    for i in range(12):
+        keys[1 << i] = key()
+    opx = pdq.GpuExecutor(ctx, keys)
+    st = synthetic.streams(w["seed"])
+    rng = st["arrivals"]
+    ct_bytes = 2 * L * n * 8
+    slots = 4
+
+    def make(count, rate, t0=0.0):
+        reqs, t = [], t0
+        for i in range(count):
+            rows = int(round(np.exp(rng.uniform(np.log(10), np.log(1000)))))
+            a, b = (int(x) for x in rng.choice(4, 2, replace=False))
+            ops, outs, regs = pdq.plan_query(ch["q"], L, 2.0 ** w["log_scale"], rows, a, b)
+            inputs = {k: torch.stack([synthetic.device_uniform_residues(ch["q"], n, gen, "cuda") for _ in range(2)])
+                      for k in ("T", "LO", "HI")}
+            fp = (pdq.peak_live(ops, outputs=outs) + 3) * ct_bytes
+            if rate:
+                t += rng.exponential(1.0 / rate)
+            reqs.append(Request(rid=i, arrival=t, ops=ops, inputs=inputs, outputs=outs, footprint=fp))
+        return reqs
+
+    budget = 6 << 30
+    warm = make(slots, 0)
+    Server(GpuQueryExecutor(opx, slots), budget, slots=slots).run(warm)
+    burst = make(n_queries, 0)
+    stb = Server(GpuQueryExecutor(opx, slots), budget, slots=slots).run(burst)
+    sat = stb.completed / stb.makespan
+    points = []
+    for f in (0.25, 0.5, 0.75, 0.9):
+        reqs = make(n_queries, f * sat)
+        s2 = Server(GpuQueryExecutor(opx, slots), budget, slots=slots).run(reqs)
+        points.append({"load": f, "arrival_rate_qps": round(f * sat, 2),
+                       "queries_per_s": round(s2.completed / s2.makespan, 2),
+                       "p50_ms": round(s2.percentile(50) * 1e3, 2), "p99_ms": round(s2.percentile(99) * 1e3, 2),
+                       "completed": s2.completed, "failed": s2.failed, "peak_inflight": s2.peak_inflight})
+    return {"workload": "range-sum queries, CKKS N=2^16 24 limbs alpha=4 scale 2^45, tables of 10..1000 rows x 4 "
+                        "columns (log-uniform), %d queries per point, %d stream slots, 6 GiB admission budget"
+                        % (n_queries, slots),
+            "ops_per_query_mean": round(float(np.mean([len(r.ops) for r in burst])), 1),
+            "saturation_qps": round(sat, 2), "burst_p50_ms": round(stb.percentile(50) * 1e3, 2),
+            "burst_p99_ms": round(stb.percentile(99) * 1e3, 2), "points": points}
 
 
 def cpu_baseline(w):

@@ -154,6 +154,25 @@ int rf_tensor(const rf_ctx *ctx, const uint64_t *a, const uint64_t *b, uint64_t 
 int rf_automorphism(const rf_ctx *ctx, const uint64_t *in, uint64_t *out, uint32_t galois_elt,
                     uint32_t n_limbs, uint32_t n_polys, void *stream);
 
+/* ---- Element-wise helpers (an extension: the private-query circuit needs them) ----
+ * n_polys polynomials of n_limbs limbs, [n_polys][n_limbs][N], limb i mod q_i;
+ * out may alias an input.  Every residue operation is exact mod q_i. */
+/* out = a + b, a - b */
+int rf_add(const rf_ctx *ctx, const uint64_t *a, const uint64_t *b, uint64_t *out, uint32_t n_limbs,
+           uint32_t n_polys, void *stream);
+int rf_sub(const rf_ctx *ctx, const uint64_t *a, const uint64_t *b, uint64_t *out, uint32_t n_limbs,
+           uint32_t n_polys, void *stream);
+/* out = k * a for a signed integer k (k taken mod q_i) */
+int rf_mul_scalar(const rf_ctx *ctx, const uint64_t *a, int64_t k, uint64_t *out, uint32_t n_limbs,
+                  uint32_t n_polys, void *stream);
+/* ciphertext a = (c0, c1): out = (c0 + k, c1), k added to every residue of c0 (in the
+ * NTT domain: adding the constant polynomial k) */
+int rf_add_scalar(const rf_ctx *ctx, const uint64_t *a, int64_t k, uint64_t *out, uint32_t n_limbs,
+                  void *stream);
+/* out_p = a_p * pt for each polynomial p, pt a single [n_limbs][N] polynomial (same domain) */
+int rf_mul_plain(const rf_ctx *ctx, const uint64_t *a, const uint64_t *pt, uint64_t *out, uint32_t n_limbs,
+                 uint32_t n_polys, void *stream);
+
 /* ---- Batched HMult+Relin (many ciphertexts, mixed ring degree and level) ----
  *
  * A plan fixes a list of independent HMult+Relin items; each item names the

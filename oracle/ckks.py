@@ -357,3 +357,35 @@ def rotate(ct: Ciphertext, g: int, gk: np.ndarray, params: Params) -> Ciphertext
     c1 = automorphism_ntt(ct.data[1], g, moduli, params)
     k0, k1 = keyswitch(c1, gk, params)
     return Ciphertext(np.stack([poly_add(c0, k0, moduli), k1]), ct.scale)
+
+
+# ---------------------------------------------------------------- element-wise helpers
+
+def ct_add(a: Ciphertext, b: Ciphertext, params: Params) -> Ciphertext:
+    moduli = params.q[:a.nlimbs]
+    return Ciphertext(np.stack([poly_add(a.data[c], b.data[c], moduli) for c in range(2)]), a.scale)
+
+
+def ct_sub(a: Ciphertext, b: Ciphertext, params: Params) -> Ciphertext:
+    moduli = params.q[:a.nlimbs]
+    return Ciphertext(np.stack([poly_sub(a.data[c], b.data[c], moduli) for c in range(2)]), a.scale)
+
+
+def ct_mul_int(a: Ciphertext, k: int, params: Params) -> Ciphertext:
+    """k * (c0, c1) for a signed integer k."""
+    moduli = params.q[:a.nlimbs]
+    return Ciphertext(np.stack([np.stack([_core.mul_scalar(a.data[c, i], k % q, q)
+                                          for i, q in enumerate(moduli)]) for c in range(2)]), a.scale)
+
+
+def ct_add_int(a: Ciphertext, k: int, params: Params) -> Ciphertext:
+    """(c0 + k, c1): adds the constant polynomial k (every NTT-domain residue of c0)."""
+    moduli = params.q[:a.nlimbs]
+    c0 = np.stack([_core.add(a.data[0, i], np.full(params.n, k % q, dtype=np.uint64), q)
+                   for i, q in enumerate(moduli)])
+    return Ciphertext(np.stack([c0, a.data[1].copy()]), a.scale)
+
+
+def ct_mul_plain(a: Ciphertext, pt: np.ndarray, params: Params) -> Ciphertext:
+    moduli = params.q[:a.nlimbs]
+    return Ciphertext(np.stack([poly_mul(a.data[c], pt[:a.nlimbs], moduli) for c in range(2)]), a.scale)

@@ -65,6 +65,11 @@ _SIGS = {
     "rf_modswitch": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _sz, _vp]),
     "rf_tensor": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32, _vp]),
     "rf_automorphism": (ctypes.c_int, [_vp, _vp, _vp, _u32, _u32, _u32, _vp]),
+    "rf_add": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32, _u32, _vp]),
+    "rf_sub": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32, _u32, _vp]),
+    "rf_mul_scalar": (ctypes.c_int, [_vp, _vp, ctypes.c_int64, _vp, _u32, _u32, _vp]),
+    "rf_add_scalar": (ctypes.c_int, [_vp, _vp, ctypes.c_int64, _vp, _u32, _vp]),
+    "rf_mul_plain": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32, _u32, _vp]),
     "rf_batch_workspace_bytes": (_sz, [ctypes.POINTER(rf_batch_item), _u32]),
     "rf_batch_create": (ctypes.c_int, [ctypes.POINTER(rf_batch_item), _u32, _vp, _sz, ctypes.POINTER(_vp)]),
     "rf_batch_destroy": (None, [_vp]),

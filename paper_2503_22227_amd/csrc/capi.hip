@@ -251,3 +251,38 @@ extern "C" int rf_modswitch(const rf_ctx *c, const uint64_t *in, uint64_t *out, 
         }
     return RF_OK;
 }
+
+static int ewise_entry(const rf_ctx *c, int op, const uint64_t *a, const uint64_t *b, int64_t k, uint64_t *out,
+                       uint32_t nl, uint32_t np, void *stream, const char *name) {
+    int rc;
+    if ((rc = check_level(c, nl))) return rc;
+    if (!a || !out || np == 0 || ((op == 0 || op == 1 || op == 4) && !b))
+        return fail(RF_EINVAL, std::string(name) + ": bad argument");
+    DeviceGuard g(c->device);
+    return launch_ewise(c, op, a, b, k, out, nl, np, (hipStream_t)stream);
+}
+
+extern "C" int rf_add(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *out, uint32_t nl, uint32_t np,
+                      void *stream) {
+    return ewise_entry(c, 0, a, b, 0, out, nl, np, stream, "rf_add");
+}
+
+extern "C" int rf_sub(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *out, uint32_t nl, uint32_t np,
+                      void *stream) {
+    return ewise_entry(c, 1, a, b, 0, out, nl, np, stream, "rf_sub");
+}
+
+extern "C" int rf_mul_scalar(const rf_ctx *c, const uint64_t *a, int64_t k, uint64_t *out, uint32_t nl, uint32_t np,
+                             void *stream) {
+    return ewise_entry(c, 2, a, nullptr, k, out, nl, np, stream, "rf_mul_scalar");
+}
+
+extern "C" int rf_add_scalar(const rf_ctx *c, const uint64_t *a, int64_t k, uint64_t *out, uint32_t nl,
+                             void *stream) {
+    return ewise_entry(c, 3, a, nullptr, k, out, nl, 2, stream, "rf_add_scalar");
+}
+
+extern "C" int rf_mul_plain(const rf_ctx *c, const uint64_t *a, const uint64_t *p, uint64_t *out, uint32_t nl,
+                            uint32_t np, void *stream) {
+    return ewise_entry(c, 4, a, p, 0, out, nl, np, stream, "rf_mul_plain");
+}

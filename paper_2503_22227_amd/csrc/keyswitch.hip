@@ -79,6 +79,12 @@ __global__ __launch_bounds__(kEw) void automorphism_kernel(const uint64_t *__res
     automorphism_unit(in, out, galois, log_n, blockIdx.x, blockIdx.y);
 }
 
+template <int OP>
+__global__ __launch_bounds__(kEw) void ewise_kernel(const uint64_t *a, const uint64_t *b, int64_t k, uint64_t *out,
+                                                    const PrimeConst *__restrict__ pcs, uint32_t log_n, uint32_t nl) {
+    ewise_unit<OP>(a, b, k, out, pcs, log_n, nl, blockIdx.x, blockIdx.y);
+}
+
 static int check_launch(const char *what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(RF_EHIP, std::string(what) + ": " + hipGetErrorString(e));
@@ -151,6 +157,21 @@ int launch_automorphism(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint
     ProfScope prof("automorphism", s);
     hipLaunchKernelGGL(automorphism_kernel, ew_grid(c, nl * n_polys), dim3(kEw), 0, s, in, out, galois, c->log_n);
     return check_launch("automorphism");
+}
+
+int launch_ewise(const rf_ctx *c, int op, const uint64_t *a, const uint64_t *b, int64_t k, uint64_t *out,
+                 uint32_t nl, uint32_t n_polys, hipStream_t s) {
+    ProfScope prof("elementwise", s);
+    const dim3 g = ew_grid(c, nl * n_polys);
+    switch (op) {
+        case 0: hipLaunchKernelGGL(ewise_kernel<0>, g, dim3(kEw), 0, s, a, b, k, out, c->d_pc, c->log_n, nl); break;
+        case 1: hipLaunchKernelGGL(ewise_kernel<1>, g, dim3(kEw), 0, s, a, b, k, out, c->d_pc, c->log_n, nl); break;
+        case 2: hipLaunchKernelGGL(ewise_kernel<2>, g, dim3(kEw), 0, s, a, b, k, out, c->d_pc, c->log_n, nl); break;
+        case 3: hipLaunchKernelGGL(ewise_kernel<3>, g, dim3(kEw), 0, s, a, b, k, out, c->d_pc, c->log_n, nl); break;
+        case 4: hipLaunchKernelGGL(ewise_kernel<4>, g, dim3(kEw), 0, s, a, b, k, out, c->d_pc, c->log_n, nl); break;
+        default: return fail(RF_EINVAL, "unknown element-wise op");
+    }
+    return check_launch("elementwise");
 }
 
 }  // namespace rf

@@ -207,3 +207,38 @@ __device__ __forceinline__ void automorphism_unit(const uint64_t *__restrict__ i
 }
 
 }  // namespace rf
+
+namespace rf {
+
+// Element-wise residue operations (the paper's lower-tier add / sub / multiply,
+// II and III-A, one thread per residue).  OP: 0 add, 1 sub, 2 multiply by a
+// signed integer constant, 3 add a signed integer constant (polynomial 0 only,
+// polynomial 1 copied), 4 multiply by a plaintext polynomial [nl][N].
+// gy = polynomial * nl + limb.
+template <int OP>
+__device__ __forceinline__ void ewise_unit(const uint64_t *a, const uint64_t *b, int64_t k, uint64_t *out,
+                                           const PrimeConst *__restrict__ pcs, uint32_t log_n, uint32_t nl,
+                                           uint32_t gx, uint32_t gy) {
+    const uint32_t poly = gy / nl, i = gy - poly * nl;
+    const size_t n = (size_t)gx * kEw + threadIdx.x;
+    const size_t off = ((size_t)gy << log_n) + n;
+    const PrimeConst pc = pcs[i];
+    const uint64_t x = a[off];
+    uint64_t r;
+    if constexpr (OP == 0) {
+        r = addmod(x, b[off], pc.q);
+    } else if constexpr (OP == 1) {
+        r = submod(x, b[off], pc.q);
+    } else if constexpr (OP == 4) {
+        r = mulmod(x, b[((size_t)i << log_n) + n], pc.mu1, pc.mu0, pc.q);
+    } else {
+        const uint64_t mag = k < 0 ? (uint64_t)0 - (uint64_t)k : (uint64_t)k;
+        uint64_t km = barrett64(mag, pc.mu1, pc.mu0, pc.q);
+        if (k < 0 && km) km = pc.q - km;
+        if constexpr (OP == 2) r = mulmod(x, km, pc.mu1, pc.mu0, pc.q);
+        else r = poly == 0 ? addmod(x, km, pc.q) : x;
+    }
+    out[off] = r;
+}
+
+}  // namespace rf

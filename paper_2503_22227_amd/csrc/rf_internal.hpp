@@ -122,6 +122,8 @@ int launch_rescale_lift(const rf_ctx *c, const uint64_t *last, uint64_t *lift, u
                         bool keep_t, hipStream_t s);
 int launch_rescale_tail(const rf_ctx *c, const uint64_t *in, const uint64_t *lift, uint64_t *out,
                         uint32_t nl, hipStream_t s);
+int launch_ewise(const rf_ctx *c, int op, const uint64_t *a, const uint64_t *b, int64_t k, uint64_t *out,
+                 uint32_t nl, uint32_t n_polys, hipStream_t s);
 int launch_automorphism(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint32_t galois,
                         uint32_t nl, uint32_t n_polys, hipStream_t s);
 

@@ -78,16 +78,18 @@ class Context:
     def workspace_bytes(self, op: int, nlimbs: int) -> int:
         return int(lib.rf_workspace_bytes(self._h, op, nlimbs))
 
-    def workspace(self, op: int, nlimbs: int) -> torch.Tensor:
-        """A cached device workspace for (op, nlimbs); allocated once, reused by every call."""
-        key = (op, nlimbs)
-        ws = self._ws.get(key)
-        if ws is None:
-            nbytes = self.workspace_bytes(op, nlimbs)
-            if nbytes == 0:
-                raise ValueError("no workspace size for op %d at %d limbs" % (op, nlimbs))
+    def workspace(self, op: int, nlimbs: int, slot: int = 0) -> torch.Tensor:
+        """The device workspace of ``slot``, grown to what (op, nlimbs) needs; every call
+        on one slot reuses it.  Work enqueued on different streams at the same time must
+        use different slots.  A buffer replaced by a larger one is released through torch's
+        stream-ordered caching allocator, so queued kernels still see valid memory."""
+        nbytes = self.workspace_bytes(op, nlimbs)
+        if nbytes == 0:
+            raise ValueError("no workspace size for op %d at %d limbs" % (op, nlimbs))
+        ws = self._ws.get(slot)
+        if ws is None or ws.numel() * 8 < nbytes:
             ws = torch.empty((nbytes + 7) // 8, dtype=torch.int64, device=self.device)
-            self._ws[key] = ws
+            self._ws[slot] = ws
         return ws
 
     # ---------------------------------------------------------------- operations
@@ -106,50 +108,77 @@ class Context:
         return out
 
     def hmult_relin(self, a: torch.Tensor, b: torch.Tensor, rlk: torch.Tensor,
-                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+                    out: Optional[torch.Tensor] = None, slot: int = 0) -> torch.Tensor:
         nl = a.shape[1]
         out = self.empty(2, nl, self.n) if out is None else out
-        ws = self.workspace(_lib.RF_OP_HMULT_RELIN, nl)
+        ws = self.workspace(_lib.RF_OP_HMULT_RELIN, nl, slot)
         check(lib.rf_hmult_relin(self._h, _ptr(a), _ptr(b), _ptr(rlk), _ptr(out), nl, _ptr(ws),
                                  ws.numel() * 8, _stream()), "rf_hmult_relin")
         return out
 
     def rotate(self, ct: torch.Tensor, galois: int, gk: torch.Tensor,
-               out: Optional[torch.Tensor] = None) -> torch.Tensor:
+               out: Optional[torch.Tensor] = None, slot: int = 0) -> torch.Tensor:
         nl = ct.shape[1]
         out = self.empty(2, nl, self.n) if out is None else out
-        ws = self.workspace(_lib.RF_OP_ROTATE, nl)
+        ws = self.workspace(_lib.RF_OP_ROTATE, nl, slot)
         check(lib.rf_rotate(self._h, _ptr(ct), galois, _ptr(gk), _ptr(out), nl, _ptr(ws),
                             ws.numel() * 8, _stream()), "rf_rotate")
         return out
 
     def keyswitch(self, d: torch.Tensor, evk: torch.Tensor, out: torch.Tensor,
-                  accumulate: bool = False) -> torch.Tensor:
+                  accumulate: bool = False, slot: int = 0) -> torch.Tensor:
         nl = d.shape[-2]
-        ws = self.workspace(_lib.RF_OP_KEYSWITCH, nl)
+        ws = self.workspace(_lib.RF_OP_KEYSWITCH, nl, slot)
         check(lib.rf_keyswitch(self._h, _ptr(d), _ptr(evk), _ptr(out), nl, 1 if accumulate else 0,
                                _ptr(ws), ws.numel() * 8, _stream()), "rf_keyswitch")
         return out
 
-    def rescale(self, ct: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    def rescale(self, ct: torch.Tensor, out: Optional[torch.Tensor] = None, slot: int = 0) -> torch.Tensor:
         nl = ct.shape[1]
         out = self.empty(2, nl - 1, self.n) if out is None else out
-        ws = self.workspace(_lib.RF_OP_RESCALE, nl)
+        ws = self.workspace(_lib.RF_OP_RESCALE, nl, slot)
         check(lib.rf_rescale(self._h, _ptr(ct), _ptr(out), nl, _ptr(ws), ws.numel() * 8, _stream()),
               "rf_rescale")
         return out
 
-    def modswitch(self, ct: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    def modswitch(self, ct: torch.Tensor, out: Optional[torch.Tensor] = None, slot: int = 0) -> torch.Tensor:
         """CKKS: drop the last limb.  BGV: (c - delta)/q_l keeping the message mod t; the
         caller multiplies the ciphertext's correction factor by q_l^-1 mod t."""
         nl = ct.shape[1]
         out = self.empty(2, nl - 1, self.n) if out is None else out
         if self.scheme == "bgv":
-            ws = self.workspace(_lib.RF_OP_MODSWITCH, nl)
+            ws = self.workspace(_lib.RF_OP_MODSWITCH, nl, slot)
             wp, wb = _ptr(ws), ws.numel() * 8
         else:
             wp, wb = None, 0
         check(lib.rf_modswitch(self._h, _ptr(ct), _ptr(out), nl, wp, wb, _stream()), "rf_modswitch")
+        return out
+
+    def add(self, a: torch.Tensor, b: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = torch.empty_like(a) if out is None else out
+        check(lib.rf_add(self._h, _ptr(a), _ptr(b), _ptr(out), a.shape[1], a.shape[0], _stream()), "rf_add")
+        return out
+
+    def sub(self, a: torch.Tensor, b: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = torch.empty_like(a) if out is None else out
+        check(lib.rf_sub(self._h, _ptr(a), _ptr(b), _ptr(out), a.shape[1], a.shape[0], _stream()), "rf_sub")
+        return out
+
+    def mul_scalar(self, a: torch.Tensor, k: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = torch.empty_like(a) if out is None else out
+        check(lib.rf_mul_scalar(self._h, _ptr(a), int(k), _ptr(out), a.shape[1], a.shape[0], _stream()),
+              "rf_mul_scalar")
+        return out
+
+    def add_scalar(self, a: torch.Tensor, k: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = torch.empty_like(a) if out is None else out
+        check(lib.rf_add_scalar(self._h, _ptr(a), int(k), _ptr(out), a.shape[1], _stream()), "rf_add_scalar")
+        return out
+
+    def mul_plain(self, a: torch.Tensor, pt: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = torch.empty_like(a) if out is None else out
+        check(lib.rf_mul_plain(self._h, _ptr(a), _ptr(pt), _ptr(out), a.shape[1], a.shape[0], _stream()),
+              "rf_mul_plain")
         return out
 
     def automorphism(self, x: torch.Tensor, galois: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
