@@ -72,7 +72,10 @@ typedef struct rf_params {
     uint32_t n_p;            /* k: special primes, 1 <= k */
     const uint64_t *p;       /* host array of k primes, each < 2^61 */
     uint32_t alpha;          /* Q-primes per key-switching digit, 1 <= alpha <= 8 */
-    uint64_t t;              /* plaintext modulus (BFV/BGV), 0 for CKKS */
+    uint64_t t;              /* plaintext modulus (BFV/BGV, 2 <= t < 2^32), 0 for CKKS */
+    uint32_t n_b;            /* BFV: auxiliary base B of the BEHZ multiplication (0 otherwise) */
+    const uint64_t *b;       /* host array of n_b primes, each < 2^61 */
+    uint64_t m_sk;           /* BFV: the extra prime of B_sk = B u {m_sk}; m~ = 2^32 is fixed */
 } rf_params;
 
 typedef struct rf_ctx rf_ctx;
@@ -105,10 +108,15 @@ int rf_ntt(const rf_ctx *ctx, uint64_t *data, uint32_t first_limb, uint32_t n_li
 int rf_intt(const rf_ctx *ctx, uint64_t *data, uint32_t first_limb, uint32_t n_limbs,
             uint32_t n_polys, void *stream);
 
-/* HMult+Relin (CKKS; the paper's multiply followed by relinearize):
+/* HMult+Relin (the paper's multiply followed by relinearize):
  * out = (d0 + KS_0(d2), d1 + KS_1(d2)) with (d0, d1, d2) the tensor product of
- * a and b, all three ciphertexts with `n_limbs` Q-limbs in the NTT domain,
- * rlk the relinearisation key.  out must not alias a or b. */
+ * a and b, rlk the relinearisation key, out must not alias a or b.
+ *   CKKS / BGV: ciphertexts with `n_limbs` Q-limbs in the NTT domain.
+ *   BFV: ciphertexts with all L limbs (n_limbs == L) in the COEFFICIENT domain;
+ *   (d0, d1, d2) is the BEHZ tensor: extension to B_sk with the small
+ *   Montgomery reduction by m~ = 2^32, products on q u B_sk, fast floor of
+ *   t d / Q and the Shenoy-Kumaresan conversion back to q (the multiply of the
+ *   paper's BFV table, section III middle tier). */
 int rf_hmult_relin(const rf_ctx *ctx, const uint64_t *a, const uint64_t *b, const uint64_t *rlk,
                    uint64_t *out, uint32_t n_limbs, void *workspace, size_t workspace_bytes,
                    void *stream);

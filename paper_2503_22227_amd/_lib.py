@@ -32,6 +32,9 @@ class rf_params(ctypes.Structure):
         ("p", _u64p),
         ("alpha", _u32),
         ("t", ctypes.c_uint64),
+        ("n_b", _u32),
+        ("b", _u64p),
+        ("m_sk", ctypes.c_uint64),
     ]
 
 

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kEw) void ks_batched_kernel(const KsJob *__restrict
         const uint32_t cshift = J.log_n - 8;  // N / 256 blocks per row
         const uint32_t gy = local >> cshift, gx = local & ((1u << cshift) - 1);
         if constexpr (STAGE == kTensor) {
-            tensor_unit(J.a, J.b, J.out, J.d2, J.pcs, J.log_n, J.nl, gx, gy);
+            tensor_unit(J.a, J.b, J.out, J.d2, J.pcs, J.log_n, J.nl, nullptr, gx, gy);
         } else if constexpr (STAGE == kModupConv) {
             modup_bconv_unit(J.d_coeff, J.ext, J.pcs, J.modup_tab, J.modup_stride, J.log_n, J.nl, J.L, J.K, J.alpha,
                              gx, gy);

@@ -93,9 +93,17 @@ int keyswitch_core(const rf_ctx *c, const uint64_t *d, const uint64_t *evk, uint
 
 }  // namespace
 
+// BFV HMult+Relin workspace, in limbs of N residues (W = L + nb + 1):
+//   ext [4][W] | tens [3][W] | d2 [L] | ks_out [2][L] | key-switch workspace
+static size_t bfv_ws_limbs(const rf_ctx *c) {
+    const size_t W = c->L + c->nb + 1;
+    return 7 * W + 3 * (size_t)c->L + ks_layout(c, c->L).total / c->n;
+}
+
 extern "C" size_t rf_workspace_bytes(const rf_ctx *c, int op, uint32_t nl) {
     if (!c || nl < 1 || nl > c->L) return 0;
     const size_t N = c->n;
+    if (c->scheme == RF_BFV && op == RF_OP_HMULT_RELIN) return nl == c->L ? bfv_ws_limbs(c) * N * 8 : 0;
     switch (op) {
         case RF_OP_KEYSWITCH: return ks_layout(c, nl).total * 8;
         case RF_OP_HMULT_RELIN:
@@ -143,6 +151,29 @@ extern "C" int rf_keyswitch(const rf_ctx *c, const uint64_t *d, const uint64_t *
                           (uint64_t *)ws, (hipStream_t)stream);
 }
 
+// BFV: BEHZ tensor on q u B_sk, then relinearisation of d2 (coefficient domain in and out).
+static int bfv_hmult_relin(const rf_ctx *c, const uint64_t *a, const uint64_t *b, const uint64_t *rlk, uint64_t *out,
+                           uint64_t *ws, hipStream_t s) {
+    int rc;
+    const size_t N = c->n, L = c->L;
+    const uint32_t W = c->L + c->nb + 1;
+    uint64_t *ext = ws;                       // [4][W][N]: a0, a1, b0, b1 on q u B_sk
+    uint64_t *tens = ext + 4 * (size_t)W * N; // [3][W][N]
+    uint64_t *d2 = tens + 3 * (size_t)W * N;  // [L][N]
+    uint64_t *ks = d2 + L * N;                // [2][L][N]
+    uint64_t *ks_ws = ks + 2 * L * N;
+    const uint64_t wstride = (uint64_t)W * N;
+    if ((rc = launch_behz_extend(c, a, b, ext, s))) return rc;
+    if ((rc = launch_ntt(c, batch(ext, ext, wstride, wstride, W, 4, 0, c->d_pmap_qb), true, s))) return rc;
+    if ((rc = launch_tensor_map(c, ext, ext + 2 * wstride, tens, tens + 2 * wstride, W, c->d_pmap_qb, s))) return rc;
+    if ((rc = launch_ntt(c, batch(tens, tens, wstride, wstride, W, 3, 0, c->d_pmap_qb), false, s))) return rc;
+    if ((rc = launch_behz_floor_sk(c, tens, out, d2, s))) return rc;
+    if ((rc = launch_ntt(c, batch(d2, d2, 0, 0, c->L, 1, 0, nullptr), true, s))) return rc;
+    if ((rc = keyswitch_core(c, d2, rlk, ks, c->L, nullptr, nullptr, ks_ws, s))) return rc;
+    if ((rc = launch_ntt(c, batch(ks, ks, L * N, L * N, c->L, 2, 0, nullptr), false, s))) return rc;
+    return launch_ewise(c, 0, out, ks, 0, out, c->L, 2, s);
+}
+
 extern "C" int rf_hmult_relin(const rf_ctx *c, const uint64_t *a, const uint64_t *b, const uint64_t *rlk,
                               uint64_t *out, uint32_t nl, void *ws, size_t ws_bytes, void *stream) {
     int rc;
@@ -152,6 +183,10 @@ extern "C" int rf_hmult_relin(const rf_ctx *c, const uint64_t *a, const uint64_t
     if ((rc = check_ws(c, RF_OP_HMULT_RELIN, nl, ws, ws_bytes))) return rc;
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
+    if (c->scheme == RF_BFV) {
+        if (nl != c->L) return fail(RF_ELEVEL, "rf_hmult_relin: BFV ciphertexts carry all L limbs");
+        return bfv_hmult_relin(c, a, b, rlk, out, (uint64_t *)ws, s);
+    }
     const size_t poly = (size_t)nl * c->n;
     uint64_t *d2 = (uint64_t *)ws;
     uint64_t *ks_ws = d2 + poly;
@@ -166,6 +201,7 @@ extern "C" int rf_rotate(const rf_ctx *c, const uint64_t *in, uint32_t galois, c
     if (!in || !gk || !out) return fail(RF_EINVAL, "rf_rotate: null argument");
     if (out == in) return fail(RF_EINVAL, "rf_rotate: out aliases in");
     if ((galois & 1u) == 0 || galois >= 2u * c->n) return fail(RF_EINVAL, "rf_rotate: Galois element must be odd and < 2N");
+    if (c->scheme == RF_BFV) return fail(RF_EUNSUPPORTED, "rf_rotate: CKKS or BGV (NTT-domain ciphertexts)");
     if ((rc = check_ws(c, RF_OP_ROTATE, nl, ws, ws_bytes))) return rc;
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;

@@ -108,6 +108,8 @@ static void free_tables(rf_ctx *c) {
     (void)hipFree(c->d_moddown_t);
     (void)hipFree(c->d_rescale);
     (void)hipFree(c->d_pmaps);
+    (void)hipFree(c->d_behz);
+    (void)hipFree(c->d_pmap_qb);
 }
 
 extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
@@ -123,6 +125,13 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
     if (p->n_p > 8) return fail(RF_EUNSUPPORTED, "at most 8 special primes");
     if (p->scheme != RF_CKKS && (p->t < 2 || p->t >= (1ull << 32)))
         return fail(RF_EINVAL, "BFV/BGV need a plaintext modulus 2 <= t < 2^32");
+    if (p->scheme == RF_BFV) {
+        if (p->n_b < 1 || !p->b || p->m_sk == 0) return fail(RF_EINVAL, "BFV needs an auxiliary base B and m_sk");
+        if (p->n_b > (uint32_t)kMaxBfvLimbs || p->n_q > (uint32_t)kMaxBfvLimbs)
+            return fail(RF_EUNSUPPORTED, "BFV: at most 24 Q-primes and 24 auxiliary primes");
+    }
+    if (p->n_q + p->n_p + (p->scheme == RF_BFV ? p->n_b + 1 : 0) > (uint32_t)kMaxPrimes)
+        return fail(RF_EUNSUPPORTED, "too many primes");
 
     rf_ctx *c = new rf_ctx();
     c->device = device;
@@ -137,9 +146,14 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
     c->t = p->t;
     for (uint32_t i = 0; i < c->L; ++i) c->primes.push_back(p->q[i]);
     for (uint32_t i = 0; i < c->K; ++i) c->primes.push_back(p->p[i]);
+    if (c->scheme == RF_BFV) {
+        c->nb = p->n_b;
+        for (uint32_t i = 0; i < c->nb; ++i) c->primes.push_back(p->b[i]);
+        c->primes.push_back(p->m_sk);
+    }
     const uint64_t nmax = 1ull << c->log_nmax;
     const uint32_t N = c->n;
-    const uint32_t NP = c->L + c->K;
+    const uint32_t NP = (uint32_t)c->primes.size();
     for (uint32_t g = 0; g < NP; ++g) {
         uint64_t q = c->primes[g];
         if (q >= (1ull << 61) || q < 3 || (q - 1) % (2 * nmax) != 0 || !is_prime_h(q)) {
@@ -202,7 +216,8 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
 
     // ModUp: for every digit j and every digit size s (a truncated last digit at a lower level)
     const uint32_t A = c->alpha;
-    c->modup_stride = 2 * (size_t)A + (size_t)A * NP;
+    const uint32_t NQP = c->L + c->K;  // the key-switching basis Q u P
+    c->modup_stride = 2 * (size_t)A + (size_t)A * NQP;
     std::vector<uint64_t> mu((size_t)c->dnum * A * c->modup_stride, 0);
     for (uint32_t j = 0; j < c->dnum; ++j) {
         for (uint32_t s = 1; s <= A; ++s) {
@@ -217,12 +232,12 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
                 uint64_t f = inv_h(prod, qi);
                 blk[2 * i] = f;
                 blk[2 * i + 1] = shoup_companion(f, qi);
-                for (uint32_t g = 0; g < NP; ++g) {
+                for (uint32_t g = 0; g < NQP; ++g) {
                     uint64_t m = c->primes[g];
                     uint64_t v = 1;
                     for (uint32_t h = 0; h < s; ++h)
                         if (h != i) v = mulmod_h(v, c->primes[start + h] % m, m);
-                    blk[2 * A + (size_t)i * NP + g] = v;
+                    blk[2 * A + (size_t)i * NQP + g] = v;
                 }
             }
         }
@@ -310,8 +325,112 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
         c->modup_levels[nl] = lv;
     }
 
+    // BFV: BEHZ tables and the prime map of q u B_sk
+    std::vector<uint64_t> bz;
+    std::vector<uint8_t> pmqb;
+    if (c->scheme == RF_BFV) {
+        const uint32_t L = c->L, nb = c->nb, KB = c->L + c->K;  // index of b_0 in `primes`
+        BehzLayout &o = c->behz;
+        o.L = L;
+        o.nb = nb;
+        uint32_t at = 0;
+        auto take = [&at](uint32_t n) { uint32_t r = at; at += n; return r; };
+        o.ext_factor = take(2 * L);
+        o.cross_q_bsk = take(L * (nb + 1));
+        o.cross_q_mt = take(L);
+        o.neg_qinv_mt = take(1);
+        o.q_bsk = take(nb + 1);
+        o.mtinv_bsk = take(2 * (nb + 1));
+        o.floor_factor = take(2 * L);
+        o.t_bsk = take(2 * (nb + 1));
+        o.qinv_bsk = take(2 * (nb + 1));
+        o.sk_factor = take(2 * nb);
+        o.cross_b_q = take(nb * L);
+        o.cross_b_msk = take(nb);
+        o.minv_msk = take(2);
+        o.m_q = take(L);
+        o.total = at;
+        bz.assign(at, 0);
+        const uint64_t mt_mask = 0xffffffffull;
+        auto bsk = [&](uint32_t m) { return c->primes[KB + m]; };  // m in [0, nb]: b_0..b_{nb-1}, m_sk
+        // products of the Q-primes other than q_i, modulo a target (64-bit arithmetic)
+        auto qhat_mod = [&](uint32_t i, uint64_t m) {
+            uint64_t v = 1 % m;
+            for (uint32_t h = 0; h < L; ++h)
+                if (h != i) v = mulmod_h(v, c->primes[h] % m, m);
+            return v;
+        };
+        auto qhat_mt = [&](uint32_t i) {  // mod 2^32
+            uint64_t v = 1;
+            for (uint32_t h = 0; h < L; ++h)
+                if (h != i) v = (v * (c->primes[h] & mt_mask)) & mt_mask;
+            return v;
+        };
+        uint64_t qmt = 1;
+        for (uint32_t h = 0; h < L; ++h) qmt = (qmt * (c->primes[h] & mt_mask)) & mt_mask;
+        // inverse of an odd number mod 2^32 by Newton iteration
+        uint64_t inv = qmt;
+        for (int k = 0; k < 5; ++k) inv = (inv * (2 - qmt * inv)) & mt_mask;
+        bz[o.neg_qinv_mt] = (0x100000000ull - inv) & mt_mask;
+        for (uint32_t i = 0; i < L; ++i) {
+            uint64_t qi = c->primes[i];
+            uint64_t qh_inv = inv_h(qhat_mod(i, qi), qi);
+            uint64_t f = mulmod_h((1ull << 32) % qi, qh_inv, qi);
+            bz[o.ext_factor + 2 * i] = f;
+            bz[o.ext_factor + 2 * i + 1] = shoup_companion(f, qi);
+            uint64_t ff = mulmod_h(c->t % qi, qh_inv, qi);
+            bz[o.floor_factor + 2 * i] = ff;
+            bz[o.floor_factor + 2 * i + 1] = shoup_companion(ff, qi);
+            for (uint32_t m = 0; m <= nb; ++m) bz[o.cross_q_bsk + i * (nb + 1) + m] = qhat_mod(i, bsk(m));
+            bz[o.cross_q_mt + i] = qhat_mt(i);
+        }
+        for (uint32_t m = 0; m <= nb; ++m) {
+            uint64_t bm = bsk(m);
+            uint64_t qm = 1;
+            for (uint32_t h = 0; h < L; ++h) qm = mulmod_h(qm, c->primes[h] % bm, bm);
+            bz[o.q_bsk + m] = qm;
+            uint64_t mti = inv_h((1ull << 32) % bm, bm);
+            bz[o.mtinv_bsk + 2 * m] = mti;
+            bz[o.mtinv_bsk + 2 * m + 1] = shoup_companion(mti, bm);
+            uint64_t tm = c->t % bm;
+            bz[o.t_bsk + 2 * m] = tm;
+            bz[o.t_bsk + 2 * m + 1] = shoup_companion(tm, bm);
+            uint64_t qi = inv_h(qm, bm);
+            bz[o.qinv_bsk + 2 * m] = qi;
+            bz[o.qinv_bsk + 2 * m + 1] = shoup_companion(qi, bm);
+        }
+        auto mhat_mod = [&](uint32_t j, uint64_t m) {  // (M / b_j) mod m
+            uint64_t v = 1 % m;
+            for (uint32_t h = 0; h < nb; ++h)
+                if (h != j) v = mulmod_h(v, bsk(h) % m, m);
+            return v;
+        };
+        const uint64_t msk = bsk(nb);
+        for (uint32_t j = 0; j < nb; ++j) {
+            uint64_t bj = bsk(j);
+            uint64_t f = inv_h(mhat_mod(j, bj), bj);
+            bz[o.sk_factor + 2 * j] = f;
+            bz[o.sk_factor + 2 * j + 1] = shoup_companion(f, bj);
+            for (uint32_t i = 0; i < L; ++i) bz[o.cross_b_q + j * L + i] = mhat_mod(j, c->primes[i]);
+            bz[o.cross_b_msk + j] = mhat_mod(j, msk);
+        }
+        uint64_t mm = 1;
+        for (uint32_t h = 0; h < nb; ++h) mm = mulmod_h(mm, bsk(h) % msk, msk);
+        uint64_t minv = inv_h(mm, msk);
+        bz[o.minv_msk] = minv;
+        bz[o.minv_msk + 1] = shoup_companion(minv, msk);
+        for (uint32_t i = 0; i < L; ++i) {
+            uint64_t qi = c->primes[i], v = 1;
+            for (uint32_t h = 0; h < nb; ++h) v = mulmod_h(v, bsk(h) % qi, qi);
+            bz[o.m_q + i] = v;
+        }
+        for (uint32_t i = 0; i < L; ++i) pmqb.push_back((uint8_t)i);
+        for (uint32_t m = 0; m <= nb; ++m) pmqb.push_back((uint8_t)(KB + m));
+    }
+
     int rc = RF_OK;
-    if ((rc = upload(&c->d_pc, pc)) || (rc = upload(&c->d_tw_fwd, twf)) || (rc = upload(&c->d_tw_inv, twi)) ||
+    if ((!bz.empty() && ((rc = upload(&c->d_behz, bz)) || (rc = upload(&c->d_pmap_qb, pmqb)))) ||
+        (rc = upload(&c->d_pc, pc)) || (rc = upload(&c->d_tw_fwd, twf)) || (rc = upload(&c->d_tw_inv, twi)) ||
         (rc = upload(&c->d_modup, mu)) || (rc = upload(&c->d_moddown, md)) ||
         (!mdt.empty() && (rc = upload(&c->d_moddown_t, mdt))) || (rc = upload(&c->d_rescale, rs)) ||
         (rc = upload(&c->d_pmaps, pm))) {

@@ -22,8 +22,23 @@ namespace rf {
 
 __global__ __launch_bounds__(kEw) void tensor_kernel(const uint64_t *__restrict__ a, const uint64_t *__restrict__ b,
                                                      uint64_t *__restrict__ d01, uint64_t *__restrict__ d2,
-                                                     const PrimeConst *__restrict__ pcs, uint32_t log_n, uint32_t nl) {
-    tensor_unit(a, b, d01, d2, pcs, log_n, nl, blockIdx.x, blockIdx.y);
+                                                     const PrimeConst *__restrict__ pcs, uint32_t log_n, uint32_t nl,
+                                                     const uint8_t *pmap) {
+    tensor_unit(a, b, d01, d2, pcs, log_n, nl, pmap, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(kEw) void behz_extend_kernel(const uint64_t *a, const uint64_t *b, uint64_t *ext,
+                                                          const PrimeConst *__restrict__ pcs,
+                                                          const uint64_t *__restrict__ tab, BehzLayout o, uint32_t kb,
+                                                          uint32_t log_n) {
+    behz_extend_unit(a, b, ext, pcs, tab, o, kb, log_n, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(kEw) void behz_floor_sk_kernel(const uint64_t *tens, uint64_t *out01, uint64_t *out2,
+                                                            const PrimeConst *__restrict__ pcs,
+                                                            const uint64_t *__restrict__ tab, BehzLayout o,
+                                                            uint32_t kb, uint32_t log_n) {
+    behz_floor_sk_unit(tens, out01, out2, pcs, tab, o, kb, log_n, blockIdx.x, blockIdx.y);
 }
 
 __global__ __launch_bounds__(kEw) void modup_bconv_kernel(const uint64_t *__restrict__ x, uint64_t *__restrict__ ext,
@@ -96,8 +111,30 @@ static dim3 ew_grid(const rf_ctx *c, uint32_t y) { return dim3(c->n / kEw, y); }
 int launch_tensor(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *d01, uint64_t *d2, uint32_t nl,
                   hipStream_t s) {
     ProfScope prof("tensor", s);
-    hipLaunchKernelGGL(tensor_kernel, ew_grid(c, nl), dim3(kEw), 0, s, a, b, d01, d2, c->d_pc, c->log_n, nl);
+    hipLaunchKernelGGL(tensor_kernel, ew_grid(c, nl), dim3(kEw), 0, s, a, b, d01, d2, c->d_pc, c->log_n, nl,
+                       (const uint8_t *)nullptr);
     return check_launch("tensor");
+}
+
+int launch_tensor_map(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *d01, uint64_t *d2,
+                      uint32_t nl, const uint8_t *pmap, hipStream_t s) {
+    ProfScope prof("tensor", s);
+    hipLaunchKernelGGL(tensor_kernel, ew_grid(c, nl), dim3(kEw), 0, s, a, b, d01, d2, c->d_pc, c->log_n, nl, pmap);
+    return check_launch("tensor");
+}
+
+int launch_behz_extend(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *ext, hipStream_t s) {
+    ProfScope prof("behz_extend", s);
+    hipLaunchKernelGGL(behz_extend_kernel, ew_grid(c, 4), dim3(kEw), 0, s, a, b, ext, c->d_pc, c->d_behz, c->behz,
+                       c->L + c->K, c->log_n);
+    return check_launch("behz_extend");
+}
+
+int launch_behz_floor_sk(const rf_ctx *c, const uint64_t *tens, uint64_t *out01, uint64_t *out2, hipStream_t s) {
+    ProfScope prof("behz_floor_sk", s);
+    hipLaunchKernelGGL(behz_floor_sk_kernel, ew_grid(c, 3), dim3(kEw), 0, s, tens, out01, out2, c->d_pc, c->d_behz,
+                       c->behz, c->L + c->K, c->log_n);
+    return check_launch("behz_floor_sk");
 }
 
 int launch_modup_bconv(const rf_ctx *c, const uint64_t *x, uint64_t *ext, uint32_t nl, hipStream_t s) {

@@ -16,12 +16,12 @@ constexpr int kEw = 256;  // threads per block of the element-wise kernels
 // d0 = a0 b0, d1 = a0 b1 + a1 b0 (into d01 = [2][nl][N]), d2 = a1 b1 (into d2 = [nl][N]).
 __device__ __forceinline__ void tensor_unit(const uint64_t *__restrict__ a, const uint64_t *__restrict__ b,
                                                      uint64_t *__restrict__ d01, uint64_t *__restrict__ d2,
-                                                     const PrimeConst *__restrict__ pcs, uint32_t log_n, uint32_t nl, uint32_t gx, uint32_t gy) {
+                                                     const PrimeConst *__restrict__ pcs, uint32_t log_n, uint32_t nl, const uint8_t *pmap, uint32_t gx, uint32_t gy) {
     const uint32_t i = gy;
     const size_t n = (size_t)gx * kEw + threadIdx.x;
     const size_t poly = (size_t)nl << log_n;
     const size_t off = ((size_t)i << log_n) + n;
-    const PrimeConst pc = pcs[i];
+    const PrimeConst pc = pcs[pmap ? (uint32_t)pmap[i] : i];
     const uint64_t a0 = a[off], a1 = a[poly + off], b0 = b[off], b1 = b[poly + off];
     u128 acc = mul_wide(a0, b1);
     mac(acc, a1, b0);
@@ -239,6 +239,121 @@ __device__ __forceinline__ void ewise_unit(const uint64_t *a, const uint64_t *b,
         else r = poly == 0 ? addmod(x, km, pc.q) : x;
     }
     out[off] = r;
+}
+
+}  // namespace rf
+
+namespace rf {
+
+// BEHZ step 1 for one coefficient-domain polynomial (gy selects it among
+// a0, a1, b0, b1): fast conversion of [m~ x]_q to B_sk u {m~}, then the small
+// Montgomery reduction by m~ = 2^32.  ext = [poly][L + nb + 1][N]: the q part
+// is a copy of x, then b_0..b_{nb-1}, m_sk.  Prime indices: q_i = i,
+// bsk_m = kb + m.
+__device__ __forceinline__ void behz_extend_unit(const uint64_t *a, const uint64_t *b, uint64_t *ext,
+                                                 const PrimeConst *__restrict__ pcs, const uint64_t *__restrict__ tab,
+                                                 BehzLayout o, uint32_t kb, uint32_t log_n, uint32_t gx, uint32_t gy) {
+    const uint32_t L = o.L, nb = o.nb, W = L + nb + 1;
+    const size_t n = (size_t)gx * kEw + threadIdx.x;
+    const size_t poly = (size_t)L << log_n;
+    const uint64_t *x = (gy < 2 ? a : b) + (gy & 1) * poly + n;
+    uint64_t *dst = ext + (((size_t)gy * W) << log_n) + n;
+    uint64_t y[kMaxBfvLimbs];
+    uint32_t acc_mt = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxBfvLimbs; ++i) {
+        y[i] = 0;
+        if (i < (int)L) {
+            const uint64_t xi = x[(size_t)i << log_n];
+            dst[(size_t)i << log_n] = xi;
+            y[i] = shoup(xi, tab[o.ext_factor + 2 * i], tab[o.ext_factor + 2 * i + 1], pcs[i].q);
+            acc_mt += (uint32_t)y[i] * (uint32_t)tab[o.cross_q_mt + i];
+        }
+    }
+    // r = -x~_{m~} Q^-1 mod 2^32, centred
+    const uint32_t r32 = acc_mt * (uint32_t)tab[o.neg_qinv_mt];
+    const bool neg = r32 >= 0x80000000u;
+    const uint64_t rmag = neg ? (uint64_t)(0x100000000ull - r32) : (uint64_t)r32;
+    for (uint32_t m = 0; m <= nb; ++m) {
+        const PrimeConst pc = pcs[kb + m];
+        u128 acc = {0, 0};
+#pragma unroll
+        for (int i = 0; i < kMaxBfvLimbs; ++i)
+            if (i < (int)L) mac(acc, y[i], tab[o.cross_q_bsk + i * (nb + 1) + m]);
+        uint64_t v = barrett128(acc, pc.mu1, pc.mu0, pc.q);
+        const uint64_t qr = mulmod(tab[o.q_bsk + m], barrett64(rmag, pc.mu1, pc.mu0, pc.q), pc.mu1, pc.mu0, pc.q);
+        v = neg ? submod(v, qr, pc.q) : addmod(v, qr, pc.q);
+        dst[(size_t)(L + m) << log_n] = shoup(v, tab[o.mtinv_bsk + 2 * m], tab[o.mtinv_bsk + 2 * m + 1], pc.q);
+    }
+}
+
+// BEHZ steps 3-4 for one polynomial d on q u B_sk (coefficient domain, gy selects
+// d0, d1, d2 of tens = [3][L + nb + 1][N]): fast floor of t d / Q into B_sk, then
+// the Shenoy-Kumaresan conversion B_sk -> q.  d0, d1 go to out01 = [2][L][N],
+// d2 to out2 = [L][N].
+__device__ __forceinline__ void behz_floor_sk_unit(const uint64_t *tens, uint64_t *out01, uint64_t *out2,
+                                                   const PrimeConst *__restrict__ pcs,
+                                                   const uint64_t *__restrict__ tab, BehzLayout o, uint32_t kb,
+                                                   uint32_t log_n, uint32_t gx, uint32_t gy) {
+    const uint32_t L = o.L, nb = o.nb, W = L + nb + 1;
+    const size_t n = (size_t)gx * kEw + threadIdx.x;
+    const uint64_t *d = tens + (((size_t)gy * W) << log_n) + n;
+    uint64_t *out = (gy < 2 ? out01 + (((size_t)gy * L) << log_n) : out2) + n;
+    uint64_t z[kMaxBfvLimbs];
+#pragma unroll
+    for (int i = 0; i < kMaxBfvLimbs; ++i) {
+        z[i] = 0;
+        if (i < (int)L)
+            z[i] = shoup(d[(size_t)i << log_n], tab[o.floor_factor + 2 * i], tab[o.floor_factor + 2 * i + 1],
+                         pcs[i].q);
+    }
+    // fast floor into B_sk: f_m = (t d_m - conv_m) Q^-1 mod bsk_m
+    uint64_t f[kMaxBfvLimbs + 1];
+#pragma unroll
+    for (int m = 0; m <= kMaxBfvLimbs; ++m) {
+        f[m] = 0;
+        if (m <= (int)nb) {
+            const PrimeConst pc = pcs[kb + m];
+            u128 acc = {0, 0};
+#pragma unroll
+            for (int i = 0; i < kMaxBfvLimbs; ++i)
+                if (i < (int)L) mac(acc, z[i], tab[o.cross_q_bsk + i * (nb + 1) + m]);
+            const uint64_t conv = barrett128(acc, pc.mu1, pc.mu0, pc.q);
+            const uint64_t td = shoup(d[(size_t)(L + m) << log_n], tab[o.t_bsk + 2 * m], tab[o.t_bsk + 2 * m + 1],
+                                      pc.q);
+            f[m] = shoup(submod(td, conv, pc.q), tab[o.qinv_bsk + 2 * m], tab[o.qinv_bsk + 2 * m + 1], pc.q);
+        }
+    }
+    // Shenoy-Kumaresan: w_j = f_j (M/b_j)^-1 mod b_j, alpha from the m_sk residue
+    uint64_t w[kMaxBfvLimbs];
+    u128 acc_msk = {0, 0};
+#pragma unroll
+    for (int j = 0; j < kMaxBfvLimbs; ++j) {
+        w[j] = 0;
+        if (j < (int)nb) {
+            w[j] = shoup(f[j], tab[o.sk_factor + 2 * j], tab[o.sk_factor + 2 * j + 1], pcs[kb + j].q);
+            mac(acc_msk, w[j], tab[o.cross_b_msk + j]);
+        }
+    }
+    const PrimeConst pm = pcs[kb + nb];
+    uint64_t fmsk = 0;
+#pragma unroll
+    for (int m = 0; m <= kMaxBfvLimbs; ++m)
+        if (m == (int)nb) fmsk = f[m];
+    const uint64_t cmsk = barrett128(acc_msk, pm.mu1, pm.mu0, pm.q);
+    const uint64_t alpha = shoup(submod(cmsk, fmsk, pm.q), tab[o.minv_msk], tab[o.minv_msk + 1], pm.q);
+    const bool neg = alpha > (pm.q >> 1);
+    const uint64_t amag = neg ? pm.q - alpha : alpha;
+    for (uint32_t i = 0; i < L; ++i) {
+        const PrimeConst pc = pcs[i];
+        u128 acc = {0, 0};
+#pragma unroll
+        for (int j = 0; j < kMaxBfvLimbs; ++j)
+            if (j < (int)nb) mac(acc, w[j], tab[o.cross_b_q + j * L + i]);
+        const uint64_t r = barrett128(acc, pc.mu1, pc.mu0, pc.q);
+        const uint64_t am = mulmod(barrett64(amag, pc.mu1, pc.mu0, pc.q), tab[o.m_q + i], pc.mu1, pc.mu0, pc.q);
+        out[(size_t)i << log_n] = neg ? addmod(r, am, pc.q) : submod(r, am, pc.q);
+    }
 }
 
 }  // namespace rf

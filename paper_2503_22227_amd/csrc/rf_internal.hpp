@@ -11,6 +11,7 @@
 namespace rf {
 
 constexpr int kMaxAlpha = 8;
+constexpr int kMaxBfvLimbs = 24;  // BFV: Q-primes and auxiliary primes the BEHZ kernels hold in registers
 constexpr int kMaxPrimes = 250;  // L + k, prime indices fit in a byte
 
 // Per-prime constants, device resident.  Prime index g < L is q_g, g >= L is p_{g-L}.
@@ -38,6 +39,27 @@ struct NttBatch {
     uint32_t n_polys;
     uint32_t prime_base;
     const uint8_t *pmap;       // device array [per_poly] or nullptr
+};
+
+// Offsets (uint64 entries) of the BEHZ tables of a BFV context (L Q-primes,
+// nb auxiliary primes B, B_sk = B u {m_sk}, m~ = 2^32).
+struct BehzLayout {
+    uint32_t L, nb;
+    uint32_t ext_factor;   // [L] pairs: m~ (Q/q_i)^-1 mod q_i
+    uint32_t cross_q_bsk;  // [L][nb+1]: Q/q_i mod bsk_m
+    uint32_t cross_q_mt;   // [L]: Q/q_i mod 2^32
+    uint32_t neg_qinv_mt;  // [1]: -Q^-1 mod 2^32
+    uint32_t q_bsk;        // [nb+1]: Q mod bsk_m
+    uint32_t mtinv_bsk;    // [nb+1] pairs: m~^-1 mod bsk_m
+    uint32_t floor_factor; // [L] pairs: t (Q/q_i)^-1 mod q_i
+    uint32_t t_bsk;        // [nb+1] pairs: t mod bsk_m
+    uint32_t qinv_bsk;     // [nb+1] pairs: Q^-1 mod bsk_m
+    uint32_t sk_factor;    // [nb] pairs: (M/b_j)^-1 mod b_j
+    uint32_t cross_b_q;    // [nb][L]: M/b_j mod q_i
+    uint32_t cross_b_msk;  // [nb]: M/b_j mod m_sk
+    uint32_t minv_msk;     // [1] pair: M^-1 mod m_sk
+    uint32_t m_q;          // [L]: M mod q_i
+    uint32_t total;
 };
 
 // Host-side layout of the ModUp extension basis at one level.
@@ -68,6 +90,11 @@ struct rf_ctx {
     uint64_t *d_moddown_t = nullptr;       // ModDown constants keeping the message mod t (BGV)
     uint64_t *d_rescale = nullptr;         // rescale constants
     uint8_t *d_pmaps = nullptr;            // ModUp extension prime maps for every level
+    // BFV: auxiliary base B and m_sk follow the special primes in `primes`
+    uint32_t nb = 0;
+    uint64_t *d_behz = nullptr;            // BEHZ tables (rf::BehzLayout)
+    uint8_t *d_pmap_qb = nullptr;          // prime indices of q u B_sk
+    rf::BehzLayout behz{};
     size_t modup_stride = 0;               // uint64 entries per (digit, size) block
 };
 
@@ -124,6 +151,10 @@ int launch_rescale_tail(const rf_ctx *c, const uint64_t *in, const uint64_t *lif
                         uint32_t nl, hipStream_t s);
 int launch_ewise(const rf_ctx *c, int op, const uint64_t *a, const uint64_t *b, int64_t k, uint64_t *out,
                  uint32_t nl, uint32_t n_polys, hipStream_t s);
+int launch_behz_extend(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *ext, hipStream_t s);
+int launch_behz_floor_sk(const rf_ctx *c, const uint64_t *tens, uint64_t *out01, uint64_t *out2, hipStream_t s);
+int launch_tensor_map(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *d01, uint64_t *d2,
+                      uint32_t nl, const uint8_t *pmap, hipStream_t s);
 int launch_automorphism(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint32_t galois,
                         uint32_t nl, uint32_t n_polys, hipStream_t s);
 

@@ -37,7 +37,7 @@ class Context:
 
     def __init__(self, q: Sequence[int], p: Sequence[int], log_n: int, alpha: int,
                  log_nmax: Optional[int] = None, scheme: str = "ckks", t: int = 0,
-                 device: int = 0):
+                 device: int = 0, b: Sequence[int] = (), m_sk: int = 0):
         self.scheme = scheme
         self.t = int(t)
         self.q = [int(x) for x in q]
@@ -52,9 +52,12 @@ class Context:
         self.device = torch.device("cuda", device)
         qa = (ctypes.c_uint64 * self.L)(*self.q)
         pa = (ctypes.c_uint64 * self.k)(*self.p)
+        self.b = [int(x) for x in b]
+        ba = (ctypes.c_uint64 * max(1, len(self.b)))(*self.b)
         prm = _lib.rf_params(SCHEMES[scheme], self.log_n, self.log_nmax, self.L,
                              ctypes.cast(qa, ctypes.POINTER(ctypes.c_uint64)), self.k,
-                             ctypes.cast(pa, ctypes.POINTER(ctypes.c_uint64)), self.alpha, int(t))
+                             ctypes.cast(pa, ctypes.POINTER(ctypes.c_uint64)), self.alpha, int(t),
+                             len(self.b), ctypes.cast(ba, ctypes.POINTER(ctypes.c_uint64)), int(m_sk))
         h = ctypes.c_void_p()
         check(lib.rf_ctx_create(ctypes.byref(prm), device, ctypes.byref(h)), "rf_ctx_create")
         self._h = h
