@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed-N batch section")
     ap.add_argument("--no-pdq", action="store_true", help="skip the private-query serving section")
     ap.add_argument("--pdq-queries", type=int, default=60, help="queries per arrival-rate point")
+    ap.add_argument("--no-bfv-bgv", action="store_true", help="skip the BFV/BGV section")
     ap.add_argument("--workload", default="ckks_n16_l24")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (HBM counter calibration)")
@@ -190,6 +191,10 @@ def main():
         del m_out, r_out, ro_out
         batch = batch_section(max(3, min(args.steps, 10)))
 
+    exact = None
+    if not args.no_bfv_bgv:
+        exact = bfv_bgv_section(max(args.steps, 10))
+
     serving = None
     if not args.no_pdq:
         serving = pdq_section(args.pdq_queries)
@@ -221,6 +226,7 @@ def main():
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in sorted(kernels.items())},
         "roofline": roof,
         "batch": batch,
+        "bfv_bgv": exact,
         "pdq": serving,
         "cpu_baseline": cpu,
     }
@@ -328,6 +334,46 @@ def batch_section(reps: int):
            "batched_default_grid_ms": round(t_default * 1e3, 3), "autotuned_grid": setting,
            "ciphertext_bytes_in_out": limb_bytes}
     plan.close()
+    return out
+
+
+def bfv_bgv_section(reps: int):
+    """BFV (BEHZ) and BGV HMult+Relin at N=2^15 with 14 55-bit primes, t=65537, one 60-bit
+    special prime (alpha=1), seeded uniform residues."""
+    import torch
+
+    import synthetic
+    from paper_2503_22227_amd import Context
+    from paper_2503_22227_amd.params import chain_for
+
+    out = {}
+    for name in ("bfv_n15", "bgv_n15"):
+        w = synthetic.WORKLOADS[name]
+        ch = chain_for(w)
+        n = 1 << w["log_n"]
+        ctx = Context(ch["q"], ch["p"], w["log_n"], w["alpha"], log_nmax=w["log_nmax"], scheme=w["scheme"],
+                      t=w["t"], b=ch["b"], m_sk=ch["msk"])
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(w["seed"])
+        qp = ch["q"] + ch["p"]
+        rlk = torch.stack([torch.stack([synthetic.device_uniform_residues(qp, n, gen, "cuda") for _ in range(2)])
+                           for _ in range(ctx.dnum)])
+        a = torch.stack([synthetic.device_uniform_residues(ch["q"], n, gen, "cuda") for _ in range(2)])
+        b = torch.stack([synthetic.device_uniform_residues(ch["q"], n, gen, "cuda") for _ in range(2)])
+        o = torch.empty_like(a)
+        ctx.hmult_relin(a, b, rlk, out=o)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            ctx.hmult_relin(a, b, rlk, out=o)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        out[w["scheme"]] = {"hmult_relin_us": round(us, 2), "hmult_relin_per_s": round(1e6 / us, 1)}
+        ctx.close()
+    out["workload"] = "N=2^15, 14 x 55-bit Q, t=65537, 1 special 60-bit prime (alpha=1); BFV B = 14 x 60-bit + m_sk"
     return out
 
 

@@ -9,7 +9,7 @@ import ctypes
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "librnsfhe.so")
+LIB_PATH = os.environ.get("RF_LIBRARY") or os.path.join(_PKG, "librnsfhe.so")
 
 RF_OK, RF_EINVAL, RF_ELEVEL, RF_EDOMAIN, RF_EWORKSPACE, RF_EHIP, RF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 RF_CKKS, RF_BFV, RF_BGV = 0, 1, 2

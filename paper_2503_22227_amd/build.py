@@ -19,15 +19,23 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source into one shared library next to this file; returns its path."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile every source into one shared library (next to this file by default);
+    returns its path.  ``defines`` are extra -D flags (kernel variants for tuning)."""
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + FLAGS + ["-D" + d for d in defines] + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    # the host pass does not know the device feature flag; that note is harmless
+    noise = "is not a recognized feature for this target"
+    text = "\n".join(l for l in res.stdout.splitlines() if noise not in l and "--hip-link" not in l)
+    if text.strip():
+        print(text, flush=True)
+    if res.returncode != 0:
+        raise subprocess.CalledProcessError(res.returncode, cmd)
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

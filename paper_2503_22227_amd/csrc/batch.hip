@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kEw) void ks_batched_kernel(const KsJob *__restrict
 // One pass of a batched (I)NTT: FIRST = the pass that reads b.in (forward:
 // columns; inverse: rows); the second pass works in place on b.out.
 template <bool FWD, bool FIRST>
-__global__ __launch_bounds__(kThreads) void ntt_batched_kernel(const NttJob *__restrict__ jobs, uint32_t njobs,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesCols))) void ntt_batched_kernel(const NttJob *__restrict__ jobs, uint32_t njobs,
                                                                uint32_t total, uint32_t per_wg) {
     __shared__ uint64_t lds[kNttLdsWords];
     constexpr bool COLS = FWD == FIRST;
@@ -202,11 +202,11 @@ uint32_t stage_units(const rf_ctx *c, uint32_t nl, int stage) {
     switch (stage) {
         case kTensor: return nl * chunks;
         case kInttD0: case kInttD1: return nl * tiles;
-        case kModupConv: return dn * chunks;
+        case kModupConv: return dn * modup_chunks(nl, c->K) * chunks;
         case kNttExt0: case kNttExt1: return c->modup_levels[nl].ext_limbs * tiles;
         case kInnerProduct: return (nl + c->K) * chunks;
         case kInttP0: case kInttP1: return 2 * c->K * tiles;
-        case kModdownConv: return 2 * chunks;
+        case kModdownConv: return 2 * moddown_chunks(nl) * chunks;
         case kNttConv0: case kNttConv1: return 2 * nl * tiles;
         case kTail: return 2 * nl * chunks;
     }

@@ -140,7 +140,7 @@ int launch_behz_floor_sk(const rf_ctx *c, const uint64_t *tens, uint64_t *out01,
 int launch_modup_bconv(const rf_ctx *c, const uint64_t *x, uint64_t *ext, uint32_t nl, hipStream_t s) {
     const uint32_t dn = (nl + c->alpha - 1) / c->alpha;
     ProfScope prof("modup_bconv", s);
-    hipLaunchKernelGGL(modup_bconv_kernel, ew_grid(c, dn), dim3(kEw), 0, s, x, ext, c->d_pc, c->d_modup,
+    hipLaunchKernelGGL(modup_bconv_kernel, ew_grid(c, dn * modup_chunks(nl, c->K)), dim3(kEw), 0, s, x, ext, c->d_pc, c->d_modup,
                        c->modup_stride, c->log_n, nl, c->L, c->K, c->alpha);
     return check_launch("modup_bconv");
 }
@@ -156,7 +156,7 @@ int launch_inner_product(const rf_ctx *c, const uint64_t *d, const uint64_t *ext
 int launch_moddown_bconv(const rf_ctx *c, const uint64_t *ip, uint64_t *conv, uint32_t nl, hipStream_t s) {
     ProfScope prof("moddown_bconv", s);
     const uint64_t *tab = c->scheme == RF_BGV ? c->d_moddown_t : c->d_moddown;
-    hipLaunchKernelGGL(moddown_bconv_kernel, ew_grid(c, 2), dim3(kEw), 0, s, ip, conv, c->d_pc, tab,
+    hipLaunchKernelGGL(moddown_bconv_kernel, ew_grid(c, 2 * moddown_chunks(nl)), dim3(kEw), 0, s, ip, conv, c->d_pc, tab,
                        c->log_n, nl, c->L, c->K);
     return check_launch("moddown_bconv");
 }

@@ -30,17 +30,33 @@ __device__ __forceinline__ void tensor_unit(const uint64_t *__restrict__ a, cons
     d2[off] = barrett128(mul_wide(a1, b1), pc.mu1, pc.mu0, pc.q);
 }
 
-// ModUp base conversion of every digit at level nl: x = [nl][N] coefficient
-// domain; ext = digits back to back, digit j holding nl - s_j + K limbs ordered
-// as the basis Q_l u P without the digit's own primes.  grid.y = digit.
+// Targets of a base conversion handled by one work unit: splitting the
+// targets over several units multiplies the parallelism of the conversion
+// (its inputs are re-read and re-scaled per chunk, which is cheap next to the
+// chunk's multiply-accumulates) and lets the unrolled target loop prefetch its
+// uniform constants.
+constexpr int kConvChunk = 8;
+
+__host__ __device__ inline uint32_t modup_chunks(uint32_t nl, uint32_t K) {
+    return (nl + K - 1 + kConvChunk - 1) / kConvChunk;
+}
+__host__ __device__ inline uint32_t moddown_chunks(uint32_t nl) { return (nl + kConvChunk - 1) / kConvChunk; }
+
+// ModUp base conversion at level nl: x = [nl][N] coefficient domain; ext =
+// digits back to back, digit j holding nl - s_j + K limbs ordered as the basis
+// Q_l u P without the digit's own primes.  gy = digit * modup_chunks + chunk.
 __device__ __forceinline__ void modup_bconv_unit(const uint64_t *__restrict__ x, uint64_t *__restrict__ ext,
-                                                          const PrimeConst *__restrict__ pcs,
-                                                          const uint64_t *__restrict__ tab, size_t tab_stride,
-                                                          uint32_t log_n, uint32_t nl, uint32_t L, uint32_t K,
-                                                          uint32_t alpha, uint32_t gx, uint32_t gy) {
-    const uint32_t j = gy;
+                                                 const PrimeConst *__restrict__ pcs,
+                                                 const uint64_t *__restrict__ tab, size_t tab_stride,
+                                                 uint32_t log_n, uint32_t nl, uint32_t L, uint32_t K,
+                                                 uint32_t alpha, uint32_t gx, uint32_t gy) {
+    const uint32_t nch = modup_chunks(nl, K);
+    const uint32_t j = gy / nch, ch = gy - j * nch;
     const uint32_t start = j * alpha;
     const uint32_t s = min(alpha, nl - start);
+    const uint32_t ntarget = nl - s + K;
+    const uint32_t t0 = ch * kConvChunk;
+    if (t0 >= ntarget) return;
     const size_t n = (size_t)gx * kEw + threadIdx.x;
     const uint64_t *blk = tab + ((size_t)j * alpha + (s - 1)) * tab_stride;
     const uint64_t *cross = blk + 2 * alpha;
@@ -54,16 +70,19 @@ __device__ __forceinline__ void modup_bconv_unit(const uint64_t *__restrict__ x,
             y[i] = shoup(x[((size_t)(start + i) << log_n) + n], blk[2 * i], blk[2 * i + 1], q);
         }
     }
-    const uint32_t ntarget = nl - s + K;
     uint64_t *dst = ext + (((size_t)j * (nl + K - alpha)) << log_n) + n;
-    for (uint32_t tt = 0; tt < ntarget; ++tt) {
-        const uint32_t g = tt < start ? tt : (tt < nl - s ? tt + s : L + (tt - (nl - s)));
-        const PrimeConst pc = pcs[g];
-        u128 acc = {0, 0};
 #pragma unroll
-        for (int i = 0; i < kMaxAlpha; ++i)
-            if (i < (int)s) mac(acc, y[i], cross[(size_t)i * NP + g]);
-        dst[(size_t)tt << log_n] = barrett128(acc, pc.mu1, pc.mu0, pc.q);
+    for (int k = 0; k < kConvChunk; ++k) {
+        const uint32_t tt = t0 + k;
+        if (tt < ntarget) {
+            const uint32_t g = tt < start ? tt : (tt < nl - s ? tt + s : L + (tt - (nl - s)));
+            const PrimeConst pc = pcs[g];
+            u128 acc = {0, 0};
+#pragma unroll
+            for (int i = 0; i < kMaxAlpha; ++i)
+                if (i < (int)s) mac(acc, y[i], cross[(size_t)i * NP + g]);
+            dst[(size_t)tt << log_n] = barrett128(acc, pc.mu1, pc.mu0, pc.q);
+        }
     }
 }
 
@@ -102,14 +121,16 @@ __device__ __forceinline__ void inner_product_unit(const uint64_t *__restrict__ 
     ip[out_poly + ((size_t)m << log_n) + n] = barrett128(acc1, pc.mu1, pc.mu0, pc.q);
 }
 
-// ModDown base conversion P -> Q_l with centred digits, grid.y = polynomial (2).
-// ip = [2][nl + K][N] with the K P-limbs already in the coefficient domain;
-// conv = [2][nl][N] coefficient domain.
+// ModDown base conversion P -> Q_l with centred digits, gy = polynomial *
+// moddown_chunks + chunk.  ip = [2][nl + K][N] with the K P-limbs already in
+// the coefficient domain; conv = [2][nl][N] coefficient domain.
 __device__ __forceinline__ void moddown_bconv_unit(const uint64_t *__restrict__ ip, uint64_t *__restrict__ conv,
-                                                            const PrimeConst *__restrict__ pcs,
-                                                            const uint64_t *__restrict__ tab, uint32_t log_n,
-                                                            uint32_t nl, uint32_t L, uint32_t K, uint32_t gx, uint32_t gy) {
-    const uint32_t c = gy;
+                                                   const PrimeConst *__restrict__ pcs,
+                                                   const uint64_t *__restrict__ tab, uint32_t log_n,
+                                                   uint32_t nl, uint32_t L, uint32_t K, uint32_t gx, uint32_t gy) {
+    const uint32_t nch = moddown_chunks(nl);
+    const uint32_t c = gy / nch, ch = gy - c * nch;
+    const uint32_t i0 = ch * kConvChunk;
     const size_t n = (size_t)gx * kEw + threadIdx.x;
     const uint64_t *src = ip + (((size_t)c * (nl + K) + nl) << log_n) + n;
     const uint64_t *cross = tab + 2 * (size_t)K;
@@ -126,13 +147,17 @@ __device__ __forceinline__ void moddown_bconv_unit(const uint64_t *__restrict__ 
         }
     }
     uint64_t *dst = conv + (((size_t)c * nl) << log_n) + n;
-    for (uint32_t i = 0; i < nl; ++i) {
-        const PrimeConst pc = pcs[i];
-        u128 acc = mul_wide(cnt, negp[i]);
 #pragma unroll
-        for (int a = 0; a < 8; ++a)
-            if (a < (int)K) mac(acc, y[a], cross[(size_t)a * L + i]);
-        dst[(size_t)i << log_n] = barrett128(acc, pc.mu1, pc.mu0, pc.q);
+    for (int k = 0; k < kConvChunk; ++k) {
+        const uint32_t i = i0 + k;
+        if (i < nl) {
+            const PrimeConst pc = pcs[i];
+            u128 acc = mul_wide(cnt, negp[i]);
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+                if (a < (int)K) mac(acc, y[a], cross[(size_t)a * L + i]);
+            dst[(size_t)i << log_n] = barrett128(acc, pc.mu1, pc.mu0, pc.q);
+        }
     }
 }
 

@@ -23,7 +23,7 @@ __device__ __forceinline__ LimbView limb_view(const NttBatch &b, int log_n) {
 }
 
 template <int A, int B, bool FWD>
-__global__ __launch_bounds__(kThreads) void ntt_cols_kernel(NttBatch b, const TwPair *__restrict__ tw_all,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesCols))) void ntt_cols_kernel(NttBatch b, const TwPair *__restrict__ tw_all,
                                                             const PrimeConst *__restrict__ pcs) {
     __shared__ uint64_t lds[(1 << A) * (kTile / (1 << A) + 1)];
     const LimbView v = limb_view(b, A + B);
@@ -32,7 +32,7 @@ __global__ __launch_bounds__(kThreads) void ntt_cols_kernel(NttBatch b, const Tw
 }
 
 template <int A, int B, bool FWD>
-__global__ __launch_bounds__(kThreads) void ntt_rows_kernel(NttBatch b, const TwPair *__restrict__ tw_all,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesRows))) void ntt_rows_kernel(NttBatch b, const TwPair *__restrict__ tw_all,
                                                             const PrimeConst *__restrict__ pcs) {
     __shared__ uint64_t lds[(1 << B) * (kTile / (1 << B) + 1)];
     const LimbView v = limb_view(b, A + B);

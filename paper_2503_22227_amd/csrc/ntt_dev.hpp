@@ -86,8 +86,11 @@ __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, 
 #pragma unroll
                 for (int e = 0; e < G; ++e) {
                     if (e & h) continue;
-                    const int p = base + (e << DL);
-                    const TwPair w = tw[(tw_base << st) + (uint32_t)(p >> (S_LOG - st))];
+                    // in the first round every group starts below 2^DL, so the twiddle
+                    // index depends on e only (uniform across the sub-transform)
+                    const uint32_t idx = ST0 == 0 ? (tw_base << st) + (uint32_t)(e >> (C - c))
+                                                  : (tw_base << st) + (uint32_t)((base + (e << DL)) >> (S_LOG - st));
+                    const TwPair w = tw[idx];
                     ct_bfly(v[e], v[e + h], w.w, w.wp, q, q2);
                 }
             }
@@ -102,8 +105,10 @@ __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, 
                     if (SCALE_LAST && us == S_LOG - 1) {
                         gs_bfly_last(v[e], v[e + h], pc, q2);
                     } else {
-                        const int p = base + (e << DL);
-                        const TwPair w = tw[(tw_base << (S_LOG - us - 1)) + (uint32_t)(p >> (us + 1))];
+                        // in the last round every group starts below 2^DL: index from e only
+                        const uint32_t lo_part = ST0 + C == S_LOG ? (uint32_t)(e >> (c + 1))
+                                                                  : (uint32_t)((base + (e << DL)) >> (us + 1));
+                        const TwPair w = tw[(tw_base << (S_LOG - us - 1)) + lo_part];
                         gs_bfly(v[e], v[e + h], w.w, w.wp, q, q2);
                     }
                 }
@@ -192,6 +197,18 @@ __device__ __forceinline__ void ntt_rows_unit(uint64_t *lds, const uint64_t *in,
     }
     __syncthreads();
 }
+
+// Waves per SIMD the NTT kernels are compiled for.  Measured on MI355X at
+// N = 2^16: 4 (a 128-VGPR cap, four workgroups per CU) gains nothing on the row
+// pass and makes the column pass spill, so the passes are built for 3.
+#ifndef RF_NTT_WAVES_COLS
+#define RF_NTT_WAVES_COLS 3
+#endif
+#ifndef RF_NTT_WAVES_ROWS
+#define RF_NTT_WAVES_ROWS 3
+#endif
+constexpr int kNttWavesCols = RF_NTT_WAVES_COLS;
+constexpr int kNttWavesRows = RF_NTT_WAVES_ROWS;
 
 // LDS words a column or row unit needs (the largest tile: 2^8 x 17 padded).
 constexpr int kNttLdsWords = 256 * 17;
