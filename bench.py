@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-pdq", action="store_true", help="skip the private-query serving section")
     ap.add_argument("--pdq-queries", type=int, default=60, help="queries per arrival-rate point")
     ap.add_argument("--no-bfv-bgv", action="store_true", help="skip the BFV/BGV section")
+    ap.add_argument("--ntt-microbench", action="store_true",
+                    help="only time forward and inverse NTTs of 60 limbs at N=2^16 (kernel profiling)")
     ap.add_argument("--workload", default="ckks_n16_l24")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (HBM counter calibration)")
@@ -57,6 +59,45 @@ def copy_calibration():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_per_launch": nbytes, "launches": 3}), flush=True)
+
+
+def ntt_microbench(reps: int):
+    """Forward then inverse NTT of 60 limbs (the ModUp output of one dnum=3 key switch) at
+    N=2^16 on the 28-prime chain, ``reps`` times; per-kernel HIP-event averages."""
+    import torch
+
+    import synthetic
+    from paper_2503_22227_amd import Context
+    from paper_2503_22227_amd import _lib
+    from paper_2503_22227_amd.params import chain_for
+
+    w = synthetic.WORKLOADS["ckks_n16_l24"]
+    ch = chain_for(w)
+    n = 1 << w["log_n"]
+    ctx = Context(ch["q"], ch["p"], w["log_n"], w["alpha"], log_nmax=w["log_nmax"])
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1)
+    qp = ch["q"] + ch["p"]
+    x = synthetic.device_uniform_residues((qp * 3)[:60], n, gen, "cuda")
+    limbs = [(0, 28), (0, 28), (0, 4)]  # 60 limbs as three batches over the chain
+    ctx.ntt(x, 0, 28, 2)
+    ctx.intt(x, 0, 28, 2)
+    torch.cuda.synchronize()
+    _lib.profile_read()
+    _lib.profile_enable(True)
+    for _ in range(reps):
+        ctx.ntt(x, 0, 28, 2)
+        ctx.intt(x, 0, 28, 2)
+    torch.cuda.synchronize()
+    prof = _lib.profile_read()
+    _lib.profile_enable(False)
+    del limbs
+    out = {k: {"launches": c, "avg_us": round(ms / c * 1e3, 3)} for k, (c, ms) in prof.items()}
+    bfly = 56 * (n // 2) * (w["log_n"] // 2)
+    for k in out:
+        out[k]["valu_frac_24ops"] = round(bfly * BFLY_OPS / (out[k]["avg_us"] * 1e-6) / VALU_SLOTS_PER_S, 4)
+    print(json.dumps({"ntt_microbench": "56 limbs (2 polys x 28 primes) at N=2^16 per launch", "kernels": out}),
+          flush=True)
 
 
 def algorithmic_bytes(kernel: str, nl: int, K: int, alpha: int, n: int, op: str) -> float:
@@ -84,6 +125,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.ntt_microbench:
+        ntt_microbench(args.steps)
         return
 
     import numpy as np
