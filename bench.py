@@ -6,8 +6,11 @@ primes, uint64 limbs): seeded uniform residues for the ciphertexts and keys
 (throughput does not depend on the values), resident in HBM before timing.
 
 One step = HMult+Relin of two 24-limb ciphertexts, rescale of the product,
-and HRotate of a 24-limb ciphertext by a random amount in [1, N/2).
-``value`` counts the two key-switching operations of each step per second.
+and HRotate of a 24-limb ciphertext by a random amount in [1, N/2); the
+HMult+Relin -> rescale chain and the independent HRotate are issued on two
+streams.  ``value`` counts the two key-switching operations of each step per
+second; the same step on one stream and each operation alone (latency) are
+reported beside it.
 
 Also reported: per-operation rates from their own timed loops, per-kernel
 durations from HIP events recorded on the launch stream (rf_profile_*), the
@@ -62,8 +65,9 @@ def copy_calibration():
 
 
 def ntt_microbench(reps: int):
-    """Forward then inverse NTT of 60 limbs (the ModUp output of one dnum=3 key switch) at
-    N=2^16 on the 28-prime chain, ``reps`` times; per-kernel HIP-event averages."""
+    """Forward then inverse NTT of 28, 56, 112 and 224 limbs (1, 2, 4, 8 polynomials over the
+    28-prime chain) at N=2^16, ``reps`` times each; per-kernel HIP-event averages and the
+    VALU fraction at 24 ops per butterfly."""
     import torch
 
     import synthetic
@@ -78,26 +82,27 @@ def ntt_microbench(reps: int):
     gen = torch.Generator(device="cuda")
     gen.manual_seed(1)
     qp = ch["q"] + ch["p"]
-    x = synthetic.device_uniform_residues((qp * 3)[:60], n, gen, "cuda")
-    limbs = [(0, 28), (0, 28), (0, 4)]  # 60 limbs as three batches over the chain
-    ctx.ntt(x, 0, 28, 2)
-    ctx.intt(x, 0, 28, 2)
-    torch.cuda.synchronize()
-    _lib.profile_read()
-    _lib.profile_enable(True)
-    for _ in range(reps):
-        ctx.ntt(x, 0, 28, 2)
-        ctx.intt(x, 0, 28, 2)
-    torch.cuda.synchronize()
-    prof = _lib.profile_read()
-    _lib.profile_enable(False)
-    del limbs
-    out = {k: {"launches": c, "avg_us": round(ms / c * 1e3, 3)} for k, (c, ms) in prof.items()}
-    bfly = 56 * (n // 2) * (w["log_n"] // 2)
-    for k in out:
-        out[k]["valu_frac_24ops"] = round(bfly * BFLY_OPS / (out[k]["avg_us"] * 1e-6) / VALU_SLOTS_PER_S, 4)
-    print(json.dumps({"ntt_microbench": "56 limbs (2 polys x 28 primes) at N=2^16 per launch", "kernels": out}),
-          flush=True)
+    res = {}
+    for polys in (1, 2, 4, 8):
+        x = torch.stack([synthetic.device_uniform_residues(qp, n, gen, "cuda") for _ in range(polys)])
+        ctx.ntt(x, 0, 28, polys)
+        ctx.intt(x, 0, 28, polys)
+        torch.cuda.synchronize()
+        _lib.profile_read()
+        _lib.profile_enable(True)
+        for _ in range(reps):
+            ctx.ntt(x, 0, 28, polys)
+            ctx.intt(x, 0, 28, polys)
+        torch.cuda.synchronize()
+        prof = _lib.profile_read()
+        _lib.profile_enable(False)
+        bfly = 28 * polys * (n // 2) * (w["log_n"] // 2)
+        res[28 * polys] = {k: {"avg_us": round(ms / c * 1e3, 3),
+                               "us_per_limb": round(ms / c * 1e3 / (28 * polys), 4),
+                               "valu_frac_24ops": round(bfly * BFLY_OPS / (ms / c * 1e-3) / VALU_SLOTS_PER_S, 4)}
+                           for k, (c, ms) in prof.items()}
+        del x
+    print(json.dumps({"ntt_microbench": "limbs per launch -> kernel stats at N=2^16", "limbs": res}), flush=True)
 
 
 def algorithmic_bytes(kernel: str, nl: int, K: int, alpha: int, n: int, op: str) -> float:
@@ -167,6 +172,22 @@ def main():
         ctx.rescale(m_out, out=r_out)
         ctx.rotate(a, g, gk, out=ro_out)
 
+    # the timed step: the HMult+Relin -> rescale chain and the independent HRotate
+    # run on two streams (own workspace slots), so their small launches overlap
+    s_mul, s_rot = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def step_concurrent():
+        cur = torch.cuda.current_stream()
+        s_mul.wait_stream(cur)
+        s_rot.wait_stream(cur)
+        with torch.cuda.stream(s_mul):
+            ctx.hmult_relin(a, b, rlk, out=m_out, slot=0)
+            ctx.rescale(m_out, out=r_out, slot=0)
+        with torch.cuda.stream(s_rot):
+            ctx.rotate(a, g, gk, out=ro_out, slot=1)
+        cur.wait_stream(s_mul)
+        cur.wait_stream(s_rot)
+
     stream = torch.cuda.current_stream()
 
     def timed(fn, reps):
@@ -181,9 +202,10 @@ def main():
         return e0.elapsed_time(e1) / 1e3
 
     for _ in range(args.warmup):
-        step()
+        step_concurrent()
     torch.cuda.synchronize()
-    t_steps = timed(step, args.steps)
+    t_steps = timed(step_concurrent, args.steps)
+    t_serial = timed(step, args.steps)
     ms_per_step = t_steps / args.steps * 1e3
     value = 2 * args.steps / t_steps
 
@@ -263,7 +285,8 @@ def main():
         "config": {"workload": "CKKS N=2^16 L=24 k=4 dnum=3 (alpha=8): HMult+Relin, rescale, HRotate "
                                "on single ciphertexts", "log_n": w["log_n"], "limbs": L,
                    "special_primes": K, "alpha": alpha, "rotation": r},
-        "ops": {"hmult_relin_per_s": round(reps / t_hm, 2), "hrotate_per_s": round(reps / t_ro, 2),
+        "ops": {"step_ms_one_stream": round(t_serial / args.steps * 1e3, 4),
+                "hmult_relin_per_s": round(reps / t_hm, 2), "hrotate_per_s": round(reps / t_ro, 2),
                 "rescale_per_s": round(reps / t_rs, 2),
                 "hmult_relin_us": round(t_hm / reps * 1e6, 2), "hrotate_us": round(t_ro / reps * 1e6, 2),
                 "rescale_us": round(t_rs / reps * 1e6, 2)},

@@ -86,6 +86,7 @@ int keyswitch_core(const rf_ctx *c, const uint64_t *d, const uint64_t *evk, uint
                                   nullptr), false, s)))
         return rc;
     if ((rc = launch_moddown_bconv(c, ip, conv, nl, s))) return rc;
+    if (c->log_n > 12) return launch_ntt_fwd_moddown(c, conv, ip, add0, add1, out, nl, s);
     if ((rc = launch_ntt(c, batch(conv, conv, (uint64_t)nl * N, (uint64_t)nl * N, nl, 2, 0, nullptr), true, s)))
         return rc;
     return launch_moddown_tail(c, ip, conv, add0, add1, out, nl, s);
@@ -236,15 +237,20 @@ static int divide_last(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint3
     if ((rc = launch_ntt(c, batch(in + (size_t)(nl - 1) * N, last, in_stride, N, 1, 2, nl - 1, nullptr), false, s)))
         return rc;
     if ((rc = launch_rescale_lift(c, last, lift, nl, keep_t, s))) return rc;
-    if ((rc = launch_ntt(c, batch(lift, lift, (uint64_t)(nl - 1) * N, (uint64_t)(nl - 1) * N, nl - 1, 2, 0, nullptr),
-                         true, s)))
-        return rc;
     // out has a smaller polynomial stride than in: when they overlap, compute in
     // the workspace and copy the result over.
     const bool overlap = (const void *)out < (const void *)(in + 2 * (size_t)nl * N) &&
                          (const void *)in < (const void *)(out + 2 * (size_t)(nl - 1) * N);
-    if (!overlap) return launch_rescale_tail(c, in, lift, out, nl, s);
-    if ((rc = launch_rescale_tail(c, in, lift, lift, nl, s))) return rc;
+    if (c->log_n > 12) {
+        if (!overlap) return launch_ntt_fwd_rescale(c, lift, in, out, nl, s);
+        if ((rc = launch_ntt_fwd_rescale(c, lift, in, lift, nl, s))) return rc;
+    } else {
+        if ((rc = launch_ntt(c, batch(lift, lift, (uint64_t)(nl - 1) * N, (uint64_t)(nl - 1) * N, nl - 1, 2, 0,
+                                      nullptr), true, s)))
+            return rc;
+        if (!overlap) return launch_rescale_tail(c, in, lift, out, nl, s);
+        if ((rc = launch_rescale_tail(c, in, lift, lift, nl, s))) return rc;
+    }
     if (hipMemcpyAsync(out, lift, 2 * (size_t)(nl - 1) * N * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return fail(RF_EHIP, "copy of the divided ciphertext");
     return RF_OK;

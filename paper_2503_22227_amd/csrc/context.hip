@@ -237,7 +237,7 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
                     uint64_t v = 1;
                     for (uint32_t h = 0; h < s; ++h)
                         if (h != i) v = mulmod_h(v, c->primes[start + h] % m, m);
-                    blk[2 * A + (size_t)i * NQP + g] = v;
+                    blk[2 * A + (size_t)g * A + i] = v;  // target-major: a target's constants are contiguous
                 }
             }
         }
@@ -258,7 +258,7 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
             uint64_t v = 1;
             for (uint32_t h = 0; h < c->K; ++h)
                 if (h != a) v = mulmod_h(v, c->primes[c->L + h] % qi, qi);
-            md[moddown_cross_off(c) + (size_t)a * c->L + i] = v;
+            md[moddown_cross_off(c) + (size_t)i * c->K + a] = v;  // target-major
         }
     }
     for (uint32_t i = 0; i < c->L; ++i) {
@@ -283,7 +283,7 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
             mdt[2 * a + 1] = shoup_companion(f, pa);
             for (uint32_t i = 0; i < c->L; ++i) {
                 uint64_t qi = c->primes[i];
-                size_t o = moddown_cross_off(c) + (size_t)a * c->L + i;
+                size_t o = moddown_cross_off(c) + (size_t)i * c->K + a;
                 mdt[o] = mulmod_h(md[o], c->t % qi, qi);
             }
         }

@@ -42,6 +42,37 @@ __host__ __device__ inline uint32_t modup_chunks(uint32_t nl, uint32_t K) {
 }
 __host__ __device__ inline uint32_t moddown_chunks(uint32_t nl) { return (nl + kConvChunk - 1) / kConvChunk; }
 
+// ModUp conversion of one chunk of targets for a digit of S primes (S a
+// compile-time constant, so the S multiply-accumulates per target are fully
+// unrolled and the target's S constants, stored contiguously, can be fetched
+// with wide scalar loads ahead of use).
+template <int S>
+__device__ __forceinline__ void modup_conv_s(const uint64_t *__restrict__ x, uint64_t *__restrict__ dst,
+                                             const PrimeConst *__restrict__ pcs, const uint64_t *__restrict__ blk,
+                                             uint32_t alpha, uint32_t start, uint32_t ntarget, uint32_t t0,
+                                             uint32_t nl, uint32_t L, uint32_t log_n, size_t n) {
+    uint64_t y[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        const uint64_t q = pcs[start + i].q;
+        y[i] = shoup(x[((size_t)(start + i) << log_n) + n], blk[2 * i], blk[2 * i + 1], q);
+    }
+    const uint64_t *cross = blk + 2 * alpha;
+#pragma unroll
+    for (int k = 0; k < kConvChunk; ++k) {
+        const uint32_t tt = t0 + k;
+        if (tt < ntarget) {
+            const uint32_t g = tt < start ? tt : (tt < nl - S ? tt + S : L + (tt - (nl - S)));
+            const PrimeConst pc = pcs[g];
+            const uint64_t *cg = cross + (size_t)g * alpha;
+            u128 acc = mul_wide(y[0], cg[0]);
+#pragma unroll
+            for (int i = 1; i < S; ++i) mac(acc, y[i], cg[i]);
+            dst[(size_t)tt << log_n] = barrett128(acc, pc.mu1, pc.mu0, pc.q);
+        }
+    }
+}
+
 // ModUp base conversion at level nl: x = [nl][N] coefficient domain; ext =
 // digits back to back, digit j holding nl - s_j + K limbs ordered as the basis
 // Q_l u P without the digit's own primes.  gy = digit * modup_chunks + chunk.
@@ -59,30 +90,16 @@ __device__ __forceinline__ void modup_bconv_unit(const uint64_t *__restrict__ x,
     if (t0 >= ntarget) return;
     const size_t n = (size_t)gx * kEw + threadIdx.x;
     const uint64_t *blk = tab + ((size_t)j * alpha + (s - 1)) * tab_stride;
-    const uint64_t *cross = blk + 2 * alpha;
-    const uint32_t NP = L + K;
-    uint64_t y[kMaxAlpha];
-#pragma unroll
-    for (int i = 0; i < kMaxAlpha; ++i) {
-        y[i] = 0;
-        if (i < (int)s) {
-            const uint64_t q = pcs[start + i].q;
-            y[i] = shoup(x[((size_t)(start + i) << log_n) + n], blk[2 * i], blk[2 * i + 1], q);
-        }
-    }
     uint64_t *dst = ext + (((size_t)j * (nl + K - alpha)) << log_n) + n;
-#pragma unroll
-    for (int k = 0; k < kConvChunk; ++k) {
-        const uint32_t tt = t0 + k;
-        if (tt < ntarget) {
-            const uint32_t g = tt < start ? tt : (tt < nl - s ? tt + s : L + (tt - (nl - s)));
-            const PrimeConst pc = pcs[g];
-            u128 acc = {0, 0};
-#pragma unroll
-            for (int i = 0; i < kMaxAlpha; ++i)
-                if (i < (int)s) mac(acc, y[i], cross[(size_t)i * NP + g]);
-            dst[(size_t)tt << log_n] = barrett128(acc, pc.mu1, pc.mu0, pc.q);
-        }
+    switch (s) {
+        case 1: modup_conv_s<1>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 2: modup_conv_s<2>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 3: modup_conv_s<3>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 4: modup_conv_s<4>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 5: modup_conv_s<5>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 6: modup_conv_s<6>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 7: modup_conv_s<7>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        default: modup_conv_s<8>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
     }
 }
 
@@ -102,6 +119,7 @@ __device__ __forceinline__ void inner_product_unit(const uint64_t *__restrict__ 
     const uint32_t dn = (nl + alpha - 1) / alpha;
     const size_t key_poly = (size_t)(L + K) << log_n;
     u128 acc0 = {0, 0}, acc1 = {0, 0};
+#pragma unroll 4
     for (uint32_t j = 0; j < dn; ++j) {
         const uint32_t start = j * alpha;
         const uint32_t s = min(alpha, nl - start);
@@ -121,6 +139,36 @@ __device__ __forceinline__ void inner_product_unit(const uint64_t *__restrict__ 
     ip[out_poly + ((size_t)m << log_n) + n] = barrett128(acc1, pc.mu1, pc.mu0, pc.q);
 }
 
+// ModDown conversion of one chunk of Q targets from KP special primes
+// (compile-time), centred digits.
+template <int KP>
+__device__ __forceinline__ void moddown_conv_k(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
+                                               const PrimeConst *__restrict__ pcs, const uint64_t *__restrict__ tab,
+                                               uint32_t i0, uint32_t nl, uint32_t L, uint32_t log_n) {
+    const uint64_t *cross = tab + 2 * KP;
+    const uint64_t *negp = tab + 2 * KP + (size_t)KP * L + 2 * (size_t)L;
+    uint64_t y[KP];
+    uint64_t cnt = 0;
+#pragma unroll
+    for (int a = 0; a < KP; ++a) {
+        const uint64_t p = pcs[L + a].q;
+        y[a] = shoup(src[(size_t)a << log_n], tab[2 * a], tab[2 * a + 1], p);
+        cnt += y[a] > (p >> 1) ? 1u : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kConvChunk; ++k) {
+        const uint32_t i = i0 + k;
+        if (i < nl) {
+            const PrimeConst pc = pcs[i];
+            const uint64_t *ci = cross + (size_t)i * KP;
+            u128 acc = mul_wide(cnt, negp[i]);
+#pragma unroll
+            for (int a = 0; a < KP; ++a) mac(acc, y[a], ci[a]);
+            dst[(size_t)i << log_n] = barrett128(acc, pc.mu1, pc.mu0, pc.q);
+        }
+    }
+}
+
 // ModDown base conversion P -> Q_l with centred digits, gy = polynomial *
 // moddown_chunks + chunk.  ip = [2][nl + K][N] with the K P-limbs already in
 // the coefficient domain; conv = [2][nl][N] coefficient domain.
@@ -133,31 +181,16 @@ __device__ __forceinline__ void moddown_bconv_unit(const uint64_t *__restrict__ 
     const uint32_t i0 = ch * kConvChunk;
     const size_t n = (size_t)gx * kEw + threadIdx.x;
     const uint64_t *src = ip + (((size_t)c * (nl + K) + nl) << log_n) + n;
-    const uint64_t *cross = tab + 2 * (size_t)K;
-    const uint64_t *negp = tab + 2 * (size_t)K + (size_t)K * L + 2 * (size_t)L;
-    uint64_t y[8];
-    uint64_t cnt = 0;
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-        y[a] = 0;
-        if (a < (int)K) {
-            const uint64_t p = pcs[L + a].q;
-            y[a] = shoup(src[(size_t)a << log_n], tab[2 * a], tab[2 * a + 1], p);
-            cnt += y[a] > (p >> 1) ? 1u : 0u;
-        }
-    }
     uint64_t *dst = conv + (((size_t)c * nl) << log_n) + n;
-#pragma unroll
-    for (int k = 0; k < kConvChunk; ++k) {
-        const uint32_t i = i0 + k;
-        if (i < nl) {
-            const PrimeConst pc = pcs[i];
-            u128 acc = mul_wide(cnt, negp[i]);
-#pragma unroll
-            for (int a = 0; a < 8; ++a)
-                if (a < (int)K) mac(acc, y[a], cross[(size_t)a * L + i]);
-            dst[(size_t)i << log_n] = barrett128(acc, pc.mu1, pc.mu0, pc.q);
-        }
+    switch (K) {
+        case 1: moddown_conv_k<1>(src, dst, pcs, tab, i0, nl, L, log_n); break;
+        case 2: moddown_conv_k<2>(src, dst, pcs, tab, i0, nl, L, log_n); break;
+        case 3: moddown_conv_k<3>(src, dst, pcs, tab, i0, nl, L, log_n); break;
+        case 4: moddown_conv_k<4>(src, dst, pcs, tab, i0, nl, L, log_n); break;
+        case 5: moddown_conv_k<5>(src, dst, pcs, tab, i0, nl, L, log_n); break;
+        case 6: moddown_conv_k<6>(src, dst, pcs, tab, i0, nl, L, log_n); break;
+        case 7: moddown_conv_k<7>(src, dst, pcs, tab, i0, nl, L, log_n); break;
+        default: moddown_conv_k<8>(src, dst, pcs, tab, i0, nl, L, log_n); break;
     }
 }
 

@@ -14,12 +14,15 @@
 // elements of one column; the last B only mix elements of one row.  So the
 // forward transform is a column pass then a row pass, the inverse a row pass
 // then a column pass, each a size-2^A or 2^B sub-transform that lives in LDS:
-//   * a workgroup of 256 threads owns a 4096-residue tile (32 KiB + padding):
-//     16 columns x 256 rows, or 16 rows x 256, so every global access of a
-//     wavefront is a run of whole 128-byte lines;
-//   * inside the tile every thread holds 16 residues in registers and performs
-//     up to 4 butterfly stages on them (a radix-16 round), then the tile is
-//     exchanged through LDS for the next round;
+//   * a workgroup owns a 4096-residue tile (32 KiB + padding): 16 columns x
+//     256 rows, or 16 rows x 256, so every global access of a wavefront is a
+//     run of whole 128-byte lines;
+//   * inside the tile every thread holds kElems residues in registers and
+//     performs up to log2(kElems) butterfly stages on them (a radix-kElems
+//     round), then the tile is exchanged through LDS for the next round.
+//     kElems = 16 (256-thread workgroups, radix-16 rounds) is the default:
+//     on MI355X, 8 (512 threads, radix-8 rounds) is no faster on small
+//     launches and slower on large ones;
 //   * values stay in Harvey's lazy ranges ([0, 4q) forward, [0, 2q) inverse)
 //     between stages and passes and are reduced to [0, q) at the last store.
 // N <= 4096 is done in one pass by one workgroup per limb.
@@ -32,7 +35,13 @@
 namespace rf {
 
 constexpr int kTile = 4096;
-constexpr int kThreads = 256;
+#ifndef RF_NTT_ELEMS
+#define RF_NTT_ELEMS 16
+#endif
+constexpr int kElems = RF_NTT_ELEMS;               // residues per thread
+constexpr int kElemsLog = kElems == 16 ? 4 : 3;    // stages per round
+constexpr int kThreads = kTile / kElems;           // threads per workgroup
+static_assert(kElems == 8 || kElems == 16, "8 or 16 residues per thread");
 
 __device__ __forceinline__ void ct_bfly(uint64_t &x, uint64_t &y, uint64_t w, uint64_t wp, uint64_t q,
                                         uint64_t q2) {
@@ -60,13 +69,13 @@ __device__ __forceinline__ void gs_bfly_last(uint64_t &x, uint64_t &y, const Pri
 
 // One round of C butterfly stages of a size-2^S_LOG sub-transform held in LDS
 // (element p of sub-transform u at lds[p * ldu + u]).  Thread t of the
-// sub-transform owns 16 residues: 16 / 2^C groups of 2^C residues spaced by
+// sub-transform owns kElems residues: kElems / 2^C groups of 2^C residues spaced by
 // the round's smallest distance 2^DL.
 template <int S_LOG, int ST0, int C, bool FWD, bool SCALE_LAST>
 __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, uint32_t tw_base,
                                           const TwPair *__restrict__ tw, const PrimeConst &pc) {
     constexpr int G = 1 << C;
-    constexpr int NG = 16 / G;
+    constexpr int NG = kElems / G;
     constexpr int DL = FWD ? (S_LOG - ST0 - C) : ST0;
     const uint64_t q = pc.q, q2 = 2 * q;
 #pragma unroll
@@ -119,21 +128,23 @@ __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, 
     }
 }
 
-// All rounds of a size-2^S_LOG sub-transform: radix-16 rounds then one shorter round.
+// Rounds of a size-2^S_LOG sub-transform from stage ST0 on: radix-kElems rounds,
+// the last one shorter when kElemsLog does not divide S_LOG.
+template <int S_LOG, int ST0, bool FWD, bool SCALE_LAST>
+__device__ __forceinline__ void ntt_rounds_from(uint64_t *lds, int ldu, int u, int t, uint32_t tw_base,
+                                                const TwPair *__restrict__ tw, const PrimeConst &pc) {
+    constexpr int C = (S_LOG - ST0) < kElemsLog ? (S_LOG - ST0) : kElemsLog;
+    constexpr bool LAST = ST0 + C == S_LOG;
+    ntt_round<S_LOG, ST0, C, FWD, SCALE_LAST && LAST>(lds, ldu, u, t, tw_base, tw, pc);
+    __syncthreads();
+    if constexpr (!LAST) ntt_rounds_from<S_LOG, ST0 + C, FWD, SCALE_LAST>(lds, ldu, u, t, tw_base, tw, pc);
+}
+
 template <int S_LOG, bool FWD, bool SCALE_LAST>
 __device__ __forceinline__ void ntt_rounds(uint64_t *lds, int ldu, int u, int t, uint32_t tw_base,
                                            const TwPair *__restrict__ tw, const PrimeConst &pc) {
     static_assert(S_LOG >= 5 && S_LOG <= 12, "sub-transform size");
-    ntt_round<S_LOG, 0, 4, FWD, false>(lds, ldu, u, t, tw_base, tw, pc);
-    __syncthreads();
-    if constexpr (S_LOG <= 8) {
-        ntt_round<S_LOG, 4, S_LOG - 4, FWD, SCALE_LAST>(lds, ldu, u, t, tw_base, tw, pc);
-    } else {
-        ntt_round<S_LOG, 4, 4, FWD, false>(lds, ldu, u, t, tw_base, tw, pc);
-        __syncthreads();
-        ntt_round<S_LOG, 8, S_LOG - 8, FWD, SCALE_LAST>(lds, ldu, u, t, tw_base, tw, pc);
-    }
-    __syncthreads();
+    ntt_rounds_from<S_LOG, 0, FWD, SCALE_LAST>(lds, ldu, u, t, tw_base, tw, pc);
 }
 
 // Column pass unit: sub-transforms are columns (2^A rows, stride 2^B), tile
@@ -167,12 +178,21 @@ __device__ __forceinline__ void ntt_cols_unit(uint64_t *lds, const uint64_t *in,
     __syncthreads();
 }
 
+// Final store of a pass: out[idx] = x.  Passes take the store as a functor, so
+// an element-wise step that follows the transform (the ModDown or rescale
+// tail) runs in the pass's epilogue instead of another kernel.
+struct StoreEpi {
+    uint64_t *out;
+    __device__ __forceinline__ void operator()(size_t idx, uint64_t x) const { out[idx] = x; }
+};
+
 // Row pass unit: sub-transforms are rows (2^B contiguous residues), tile `tile`
 // covers 4096 / 2^B consecutive rows.  Forward: the last B stages (output in
-// [0, q)); inverse: the first B stages (output lazy in [0, 2q)).
-template <int A, int B, bool FWD>
-__device__ __forceinline__ void ntt_rows_unit(uint64_t *lds, const uint64_t *in, uint64_t *out,
-                                              const TwPair *__restrict__ tw, const PrimeConst &pc, int tile) {
+// [0, q)); inverse: the first B stages (output lazy in [0, 2q)).  The result
+// for limb index idx goes through epi(idx, value).
+template <int A, int B, bool FWD, typename Epi>
+__device__ __forceinline__ void ntt_rows_unit_epi(uint64_t *lds, const uint64_t *in, const TwPair *__restrict__ tw,
+                                                  const PrimeConst &pc, int tile, const Epi &epi) {
     constexpr int S = 1 << B;
     constexpr int U = kTile / S;
     constexpr int LDU = U + 1;
@@ -193,10 +213,41 @@ __device__ __forceinline__ void ntt_rows_unit(uint64_t *lds, const uint64_t *in,
         const int row = idx >> B, p = idx & (S - 1);
         uint64_t x = lds[p * LDU + row];
         if (FWD) x = csub(csub(x, q2), pc.q);
-        out[((size_t)(row0 + row) << B) + p] = x;
+        epi(((size_t)(row0 + row) << B) + p, x);
     }
     __syncthreads();
 }
+
+template <int A, int B, bool FWD>
+__device__ __forceinline__ void ntt_rows_unit(uint64_t *lds, const uint64_t *in, uint64_t *out,
+                                              const TwPair *__restrict__ tw, const PrimeConst &pc, int tile) {
+    ntt_rows_unit_epi<A, B, FWD>(lds, in, tw, pc, tile, StoreEpi{out});
+}
+
+// ModDown tail as the epilogue of the last forward pass of NTT(conv):
+// out = (ip - NTT(conv)) * P^-1 mod q (+ add).  add may alias out.
+struct ModdownTailEpi {
+    const uint64_t *ip;
+    const uint64_t *add;
+    uint64_t *out;
+    uint64_t pinv, pinv_p, q;
+    __device__ __forceinline__ void operator()(size_t idx, uint64_t conv) const {
+        uint64_t r = shoup(submod(ip[idx], conv, q), pinv, pinv_p, q);
+        if (add) r = addmod(r, add[idx], q);
+        out[idx] = r;
+    }
+};
+
+// Rescale / modulus-switch tail as the epilogue of the NTT of the lifted limb:
+// out = (in - NTT(lift)) * q_l^-1 mod q.
+struct RescaleTailEpi {
+    const uint64_t *in;
+    uint64_t *out;
+    uint64_t qlinv, qlinv_p, q;
+    __device__ __forceinline__ void operator()(size_t idx, uint64_t lift) const {
+        out[idx] = shoup(submod(in[idx], lift, q), qlinv, qlinv_p, q);
+    }
+};
 
 // Waves per SIMD the NTT kernels are compiled for.  Measured on MI355X at
 // N = 2^16: 4 (a 128-VGPR cap, four workgroups per CU) gains nothing on the row

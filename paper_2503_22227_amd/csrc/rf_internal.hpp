@@ -102,11 +102,11 @@ namespace rf {
 
 // Offsets (in uint64 entries) inside the ModUp table block of (digit j, digit size s):
 //   [0, 2*alpha):            factor pairs (w, w') of [(Q_j/q_i)^-1]_{q_i}, i' < s
-//   [2*alpha, ...):          cross[i'][g] = [Q_j/q_i]_{prime g}, g in [0, L+K)
+//   [2*alpha, ...):          cross[g][i'] = [Q_j/q_i]_{prime g}, g in [0, L+K), target-major
 inline size_t modup_block(const rf_ctx *c, uint32_t j, uint32_t s) {
     return ((size_t)j * c->alpha + (s - 1)) * c->modup_stride;
 }
-// ModDown table: [K] factor pairs (w, w') of [(P/p)^-1]_p; [K][L] cross [P/p]_{q_i};
+// ModDown table: [K] factor pairs (w, w') of [(P/p)^-1]_p; [L][K] cross [P/p]_{q_i} (target-major);
 // [L] pairs P^-1 mod q_i; [L] (q_i - [P]_{q_i}).
 inline size_t moddown_cross_off(const rf_ctx *c) { return 2 * (size_t)c->K; }
 inline size_t moddown_pinv_off(const rf_ctx *c) { return 2 * (size_t)c->K + (size_t)c->K * c->L; }
@@ -134,6 +134,13 @@ int fail(int code, const std::string &msg);
 
 // kernel launchers (kernels.hip)
 int launch_ntt(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s);
+// Forward NTT of conv [2][nl][N] whose last pass applies the ModDown tail
+// (two-pass ring degrees only): out[c][i] = (ip[c][i] - NTT(conv)) P^-1 + add_c.
+int launch_ntt_fwd_moddown(const rf_ctx *c, uint64_t *conv, const uint64_t *ip, const uint64_t *add0,
+                           const uint64_t *add1, uint64_t *out, uint32_t nl, hipStream_t s);
+// Forward NTT of lift [2][nl-1][N] whose last pass applies the rescale tail.
+int launch_ntt_fwd_rescale(const rf_ctx *c, uint64_t *lift, const uint64_t *in, uint64_t *out, uint32_t nl,
+                           hipStream_t s);
 int launch_tensor(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *d01,
                   uint64_t *d2, uint32_t nl, hipStream_t s);
 int launch_modup_bconv(const rf_ctx *c, const uint64_t *x, uint64_t *ext, uint32_t nl,
