@@ -117,6 +117,7 @@ def algorithmic_bytes(kernel: str, nl: int, K: int, alpha: int, n: int, op: str)
         "inner_product": dn * (nl + K) + 2 * dn * (nl + K) + 2 * (nl + K),
         "moddown_bconv": 2 * K + 2 * nl,
         "moddown_tail": 8 * nl if op == "hmult" else 7 * nl,
+        "rescale_lift": 2 + 2 * (nl - 1),
         "automorphism": 2 * nl,
     }
     return table[kernel] * limb if kernel in table else float("nan")
@@ -327,17 +328,26 @@ def _counter_traffic(kernel: str):
 def _kernel_symbol(name: str) -> str:
     """Profiler name of a kernel as it appears in rocprofv3 tables."""
     table = {"ntt_fwd_cols": "ntt_cols_kernel<8, 8, true>", "ntt_fwd_rows": "ntt_rows_kernel<8, 8, true>",
-             "ntt_inv_cols": "ntt_cols_kernel<8, 8, false>", "ntt_inv_rows": "ntt_rows_kernel<8, 8, false>"}
+             "ntt_inv_cols": "ntt_cols_kernel<8, 8, false>", "ntt_inv_rows": "ntt_rows_kernel<8, 8, false>",
+             "ntt_fwd_rows_moddown": "ntt_rows_moddown_kernel<8, 8>",
+             "ntt_fwd_rows_rescale": "ntt_rows_rescale_kernel<8, 8>"}
     return table.get(name, name + "_kernel")
 
 
 def _ntt_limbs_per_launch(name: str, L: int, K: int, alpha: int) -> float:
-    """Mean limbs per launch of an NTT pass in one step (HMult+Relin, rescale, HRotate at L limbs)."""
+    """Mean limbs per launch of an NTT pass in one step (HMult+Relin, rescale, HRotate at L limbs).
+    The forward row pass of NTT(conv) carries the ModDown tail and that of the
+    lifted limb the rescale tail; the other passes are plain."""
     dn = (L + alpha - 1) // alpha
     ext = sum(L - min(alpha, L - j * alpha) + K for j in range(dn))
-    fwd = [ext, 2 * L] * 2 + [2 * (L - 1)]          # ModUp NTT, ModDown NTT (x2 ops), rescale
-    inv = [L, 2 * K] * 2 + [2]                       # INTT of d, of the P-limbs (x2 ops), rescale
-    launches = fwd if "fwd" in name else inv
+    launches = {
+        "ntt_fwd_cols": [ext, 2 * L] * 2 + [2 * (L - 1)],   # ModUp NTT, ModDown NTT (x2 ops), rescale
+        "ntt_fwd_rows": [ext, ext],
+        "ntt_fwd_rows_moddown": [2 * L, 2 * L],
+        "ntt_fwd_rows_rescale": [2 * (L - 1)],
+        "ntt_inv_rows": [L, 2 * K] * 2 + [2],              # INTT of d, of the P-limbs (x2 ops), rescale
+        "ntt_inv_cols": [L, 2 * K] * 2 + [2],
+    }[name]
     return sum(launches) / len(launches)
 
 

@@ -57,6 +57,11 @@ struct NttJob {
     const PrimeConst *pcs;
     uint32_t log_n;
     uint32_t unit_begin;
+    // ModDown tail applied by the last pass of NTT(conv): out = (ip - .) P^-1 + out
+    const uint64_t *ip;
+    uint64_t *out;
+    const uint64_t *pinv;
+    uint32_t nl, K;
 };
 
 template <typename J>
@@ -112,12 +117,14 @@ __global__ __launch_bounds__(kEw) void ks_batched_kernel(const KsJob *__restrict
 }
 
 // One pass of a batched (I)NTT: FIRST = the pass that reads b.in (forward:
-// columns; inverse: rows); the second pass works in place on b.out.
-template <bool FWD, bool FIRST>
+// columns; inverse: rows); the second pass works in place on b.out.  TAIL (the
+// forward row pass of NTT(conv)) writes the ModDown result instead.
+template <bool FWD, bool FIRST, bool TAIL = false>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesCols))) void ntt_batched_kernel(const NttJob *__restrict__ jobs, uint32_t njobs,
                                                                uint32_t total, uint32_t per_wg) {
     __shared__ uint64_t lds[kNttLdsWords];
     constexpr bool COLS = FWD == FIRST;
+    static_assert(!TAIL || (FWD && !FIRST), "the tail follows the forward row pass");
     const uint32_t u0 = blockIdx.x * per_wg;
     const uint32_t u1 = min(total, u0 + per_wg);
     if (u0 >= u1) return;
@@ -136,6 +143,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
         uint64_t *out = J.b.out + (size_t)poly * J.b.out_poly_stride + ((size_t)li << J.log_n);
         const PrimeConst pc = J.pcs[g];
         const TwPair *tw = J.tw_all + ((size_t)g << J.log_n);
+        if constexpr (TAIL) {
+            // limb li of polynomial poly of conv [2][nl][N]: ModDown tail into out
+            const size_t lo = ((size_t)poly * (J.nl + J.K) + li) << J.log_n;
+            const size_t oo = ((size_t)poly * J.nl + li) << J.log_n;
+            const ModdownTailEpi epi{J.ip + lo, J.out + oo, J.out + oo, J.pinv[2 * li], J.pinv[2 * li + 1], pc.q};
+            switch (J.log_n) {
+                case 16: ntt_rows_unit_epi<8, 8, true>(lds, in, tw, pc, tile, epi); break;
+                case 15: ntt_rows_unit_epi<8, 7, true>(lds, in, tw, pc, tile, epi); break;
+                case 14: ntt_rows_unit_epi<7, 7, true>(lds, in, tw, pc, tile, epi); break;
+                default: ntt_rows_unit_epi<7, 6, true>(lds, in, tw, pc, tile, epi); break;
+            }
+            continue;
+        }
         switch (J.log_n) {
             case 16:
                 if constexpr (COLS) ntt_cols_unit<8, 8, FWD>(lds, in, out, tw, pc, tile);
@@ -208,7 +228,7 @@ uint32_t stage_units(const rf_ctx *c, uint32_t nl, int stage) {
         case kInttP0: case kInttP1: return 2 * c->K * tiles;
         case kModdownConv: return 2 * moddown_chunks(nl) * chunks;
         case kNttConv0: case kNttConv1: return 2 * nl * tiles;
-        case kTail: return 2 * nl * chunks;
+        case kTail: return 0;  // applied by the last pass of NTT(conv)
     }
     return 0;
 }
@@ -217,7 +237,7 @@ int enqueue(rf_batch *p, hipStream_t s, bool profile) {
     static const char *names[kStages] = {"batch_tensor", "batch_ntt_inv_rows", "batch_ntt_inv_cols",
                                          "batch_modup_bconv", "batch_ntt_fwd_cols", "batch_ntt_fwd_rows",
                                          "batch_inner_product", "batch_ntt_inv_rows", "batch_ntt_inv_cols",
-                                         "batch_moddown_bconv", "batch_ntt_fwd_cols", "batch_ntt_fwd_rows",
+                                         "batch_moddown_bconv", "batch_ntt_fwd_cols", "batch_ntt_fwd_rows_moddown",
                                          "batch_moddown_tail"};
     for (int st = 0; st < kStages; ++st) {
         const uint32_t total = p->total[st];
@@ -240,7 +260,7 @@ int enqueue(rf_batch *p, hipStream_t s, bool profile) {
             case kInttP0: hipLaunchKernelGGL((ntt_batched_kernel<false, true>), blocks, kThreads, 0, s, p->d_ntt[2], nj, total, per); break;
             case kInttP1: hipLaunchKernelGGL((ntt_batched_kernel<false, false>), blocks, kThreads, 0, s, p->d_ntt[2], nj, total, per); break;
             case kNttConv0: hipLaunchKernelGGL((ntt_batched_kernel<true, true>), blocks, kThreads, 0, s, p->d_ntt[3], nj, total, per); break;
-            case kNttConv1: hipLaunchKernelGGL((ntt_batched_kernel<true, false>), blocks, kThreads, 0, s, p->d_ntt[3], nj, total, per); break;
+            case kNttConv1: hipLaunchKernelGGL((ntt_batched_kernel<true, false, true>), blocks, kThreads, 0, s, p->d_ntt[3], nj, total, per); break;
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail(RF_EHIP, std::string("batched launch: ") + hipGetErrorString(e));
@@ -322,6 +342,11 @@ extern "C" int rf_batch_create(const rf_batch_item *items, uint32_t n, void *ws,
             ntt[k][i].pcs = c->d_pc;
             ntt[k][i].log_n = c->log_n;
             ntt[k][i].unit_begin = J.unit_begin[first_stage[k]];
+            ntt[k][i].ip = J.ip;
+            ntt[k][i].out = J.out;
+            ntt[k][i].pinv = J.pinv;
+            ntt[k][i].nl = nl;
+            ntt[k][i].K = c->K;
         }
     }
     rf_batch *p = new rf_batch();
