@@ -68,13 +68,13 @@ typedef struct rf_params {
                                 psi_max = g^((q-1)/2^(log_nmax+1)) for the smallest g >= 2 with
                                 psi_max^(2^log_nmax) = -1; every prime is 1 mod 2^(log_nmax+1) */
     uint32_t n_q;            /* L: ciphertext primes q_0..q_{L-1}, 1 <= L */
-    const uint64_t *q;       /* host array of L primes, each < 2^61 */
+    const uint64_t *q;       /* host array of L primes, each < 2^60 */
     uint32_t n_p;            /* k: special primes, 1 <= k */
-    const uint64_t *p;       /* host array of k primes, each < 2^61 */
+    const uint64_t *p;       /* host array of k primes, each < 2^60 */
     uint32_t alpha;          /* Q-primes per key-switching digit, 1 <= alpha <= 8 */
     uint64_t t;              /* plaintext modulus (BFV/BGV, 2 <= t < 2^32), 0 for CKKS */
     uint32_t n_b;            /* BFV: auxiliary base B of the BEHZ multiplication (0 otherwise) */
-    const uint64_t *b;       /* host array of n_b primes, each < 2^61 */
+    const uint64_t *b;       /* host array of n_b primes, each < 2^60 */
     uint64_t m_sk;           /* BFV: the extra prime of B_sk = B u {m_sk}; m~ = 2^32 is fixed */
 } rf_params;
 

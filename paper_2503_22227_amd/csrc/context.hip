@@ -156,9 +156,9 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
     const uint32_t NP = (uint32_t)c->primes.size();
     for (uint32_t g = 0; g < NP; ++g) {
         uint64_t q = c->primes[g];
-        if (q >= (1ull << 61) || q < 3 || (q - 1) % (2 * nmax) != 0 || !is_prime_h(q)) {
+        if (q >= (1ull << 60) || q < 3 || (q - 1) % (2 * nmax) != 0 || !is_prime_h(q)) {
             delete c;
-            return fail(RF_EINVAL, "prime " + std::to_string(g) + " is not an NTT-friendly prime below 2^61");
+            return fail(RF_EINVAL, "prime " + std::to_string(g) + " is not an NTT-friendly prime below 2^60");
         }
         for (uint32_t h = 0; h < g; ++h)
             if (c->primes[h] == q) {
@@ -187,6 +187,9 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
         uint64_t ninv = inv_h(N, q);
         pc[g].ninv = ninv;
         pc[g].ninv_p = shoup_companion(ninv, q);
+        pc[g].r64 = (uint64_t)(((u128h)1 << 64) % q);
+        pc[g].r64_p = shoup_companion(pc[g].r64, q);
+        pc[g].one_p = shoup_companion(1, q);
         uint64_t psi = c->psi[g], psi_inv = inv_h(psi, q);
         pw[0] = pwi[0] = 1;
         for (uint32_t e = 1; e < N; ++e) {

@@ -51,11 +51,13 @@ __device__ __forceinline__ void modup_conv_s(const uint64_t *__restrict__ x, uin
                                              const PrimeConst *__restrict__ pcs, const uint64_t *__restrict__ blk,
                                              uint32_t alpha, uint32_t start, uint32_t ntarget, uint32_t t0,
                                              uint32_t nl, uint32_t L, uint32_t log_n, size_t n) {
-    uint64_t y[S];
+    uint32_t yl[S], yh[S];
 #pragma unroll
     for (int i = 0; i < S; ++i) {
         const uint64_t q = pcs[start + i].q;
-        y[i] = shoup(x[((size_t)(start + i) << log_n) + n], blk[2 * i], blk[2 * i + 1], q);
+        const uint64_t y = shoup(x[((size_t)(start + i) << log_n) + n], blk[2 * i], blk[2 * i + 1], q);
+        yl[i] = (uint32_t)y & 0x3fffffffu;
+        yh[i] = (uint32_t)(y >> 30);
     }
     const uint64_t *cross = blk + 2 * alpha;
 #pragma unroll
@@ -65,17 +67,18 @@ __device__ __forceinline__ void modup_conv_s(const uint64_t *__restrict__ x, uin
             const uint32_t g = tt < start ? tt : (tt < nl - S ? tt + S : L + (tt - (nl - S)));
             const PrimeConst pc = pcs[g];
             const uint64_t *cg = cross + (size_t)g * alpha;
-            u128 acc = mul_wide(y[0], cg[0]);
+            MacAcc acc;
 #pragma unroll
-            for (int i = 1; i < S; ++i) mac(acc, y[i], cg[i]);
-            dst[(size_t)tt << log_n] = barrett128(acc, pc.mu1, pc.mu0, pc.q);
+            for (int i = 0; i < S; ++i) acc.mac_split(yl[i], yh[i], cg[i]);
+            dst[(size_t)tt << log_n] = reduce128_lazy(acc.value(), pc.q, pc.r64, pc.r64_p, pc.one_p);
         }
     }
 }
 
 // ModUp base conversion at level nl: x = [nl][N] coefficient domain; ext =
 // digits back to back, digit j holding nl - s_j + K limbs ordered as the basis
-// Q_l u P without the digit's own primes.  gy = digit * modup_chunks + chunk.
+// Q_l u P without the digit's own primes, each residue in [0, 4q) (the forward
+// NTT that follows accepts that range).  gy = digit * modup_chunks + chunk.
 __device__ __forceinline__ void modup_bconv_unit(const uint64_t *__restrict__ x, uint64_t *__restrict__ ext,
                                                  const PrimeConst *__restrict__ pcs,
                                                  const uint64_t *__restrict__ tab, size_t tab_stride,
@@ -147,13 +150,15 @@ __device__ __forceinline__ void moddown_conv_k(const uint64_t *__restrict__ src,
                                                uint32_t i0, uint32_t nl, uint32_t L, uint32_t log_n) {
     const uint64_t *cross = tab + 2 * KP;
     const uint64_t *negp = tab + 2 * KP + (size_t)KP * L + 2 * (size_t)L;
-    uint64_t y[KP];
+    uint32_t yl[KP], yh[KP];
     uint64_t cnt = 0;
 #pragma unroll
     for (int a = 0; a < KP; ++a) {
         const uint64_t p = pcs[L + a].q;
-        y[a] = shoup(src[(size_t)a << log_n], tab[2 * a], tab[2 * a + 1], p);
-        cnt += y[a] > (p >> 1) ? 1u : 0u;
+        const uint64_t y = shoup(src[(size_t)a << log_n], tab[2 * a], tab[2 * a + 1], p);
+        cnt += y > (p >> 1) ? 1u : 0u;
+        yl[a] = (uint32_t)y & 0x3fffffffu;
+        yh[a] = (uint32_t)(y >> 30);
     }
 #pragma unroll
     for (int k = 0; k < kConvChunk; ++k) {
@@ -161,17 +166,19 @@ __device__ __forceinline__ void moddown_conv_k(const uint64_t *__restrict__ src,
         if (i < nl) {
             const PrimeConst pc = pcs[i];
             const uint64_t *ci = cross + (size_t)i * KP;
-            u128 acc = mul_wide(cnt, negp[i]);
+            MacAcc acc;
+            acc.add(cnt * negp[i]);
 #pragma unroll
-            for (int a = 0; a < KP; ++a) mac(acc, y[a], ci[a]);
-            dst[(size_t)i << log_n] = barrett128(acc, pc.mu1, pc.mu0, pc.q);
+            for (int a = 0; a < KP; ++a) acc.mac_split(yl[a], yh[a], ci[a]);
+            dst[(size_t)i << log_n] = reduce128_lazy(acc.value(), pc.q, pc.r64, pc.r64_p, pc.one_p);
         }
     }
 }
 
 // ModDown base conversion P -> Q_l with centred digits, gy = polynomial *
 // moddown_chunks + chunk.  ip = [2][nl + K][N] with the K P-limbs already in
-// the coefficient domain; conv = [2][nl][N] coefficient domain.
+// the coefficient domain; conv = [2][nl][N] coefficient domain, residues in
+// [0, 4q) (a forward NTT follows).
 __device__ __forceinline__ void moddown_bconv_unit(const uint64_t *__restrict__ ip, uint64_t *__restrict__ conv,
                                                    const PrimeConst *__restrict__ pcs,
                                                    const uint64_t *__restrict__ tab, uint32_t log_n,
@@ -334,10 +341,7 @@ __device__ __forceinline__ void behz_extend_unit(const uint64_t *a, const uint64
     const uint64_t rmag = neg ? (uint64_t)(0x100000000ull - r32) : (uint64_t)r32;
     for (uint32_t m = 0; m <= nb; ++m) {
         const PrimeConst pc = pcs[kb + m];
-        u128 acc = {0, 0};
-#pragma unroll
-        for (int i = 0; i < kMaxBfvLimbs; ++i)
-            if (i < (int)L) mac(acc, y[i], tab[o.cross_q_bsk + i * (nb + 1) + m]);
+        const u128 acc = dot_wide<kMaxBfvLimbs>(y, [&](int i) { return tab[o.cross_q_bsk + i * (nb + 1) + m]; }, L);
         uint64_t v = barrett128(acc, pc.mu1, pc.mu0, pc.q);
         const uint64_t qr = mulmod(tab[o.q_bsk + m], barrett64(rmag, pc.mu1, pc.mu0, pc.q), pc.mu1, pc.mu0, pc.q);
         v = neg ? submod(v, qr, pc.q) : addmod(v, qr, pc.q);
@@ -372,10 +376,8 @@ __device__ __forceinline__ void behz_floor_sk_unit(const uint64_t *tens, uint64_
         f[m] = 0;
         if (m <= (int)nb) {
             const PrimeConst pc = pcs[kb + m];
-            u128 acc = {0, 0};
-#pragma unroll
-            for (int i = 0; i < kMaxBfvLimbs; ++i)
-                if (i < (int)L) mac(acc, z[i], tab[o.cross_q_bsk + i * (nb + 1) + m]);
+            const u128 acc =
+                dot_wide<kMaxBfvLimbs>(z, [&](int i) { return tab[o.cross_q_bsk + i * (nb + 1) + m]; }, L);
             const uint64_t conv = barrett128(acc, pc.mu1, pc.mu0, pc.q);
             const uint64_t td = shoup(d[(size_t)(L + m) << log_n], tab[o.t_bsk + 2 * m], tab[o.t_bsk + 2 * m + 1],
                                       pc.q);
@@ -384,15 +386,12 @@ __device__ __forceinline__ void behz_floor_sk_unit(const uint64_t *tens, uint64_
     }
     // Shenoy-Kumaresan: w_j = f_j (M/b_j)^-1 mod b_j, alpha from the m_sk residue
     uint64_t w[kMaxBfvLimbs];
-    u128 acc_msk = {0, 0};
 #pragma unroll
     for (int j = 0; j < kMaxBfvLimbs; ++j) {
         w[j] = 0;
-        if (j < (int)nb) {
-            w[j] = shoup(f[j], tab[o.sk_factor + 2 * j], tab[o.sk_factor + 2 * j + 1], pcs[kb + j].q);
-            mac(acc_msk, w[j], tab[o.cross_b_msk + j]);
-        }
+        if (j < (int)nb) w[j] = shoup(f[j], tab[o.sk_factor + 2 * j], tab[o.sk_factor + 2 * j + 1], pcs[kb + j].q);
     }
+    const u128 acc_msk = dot_wide<kMaxBfvLimbs>(w, [&](int j) { return tab[o.cross_b_msk + j]; }, nb);
     const PrimeConst pm = pcs[kb + nb];
     uint64_t fmsk = 0;
 #pragma unroll
@@ -404,10 +403,7 @@ __device__ __forceinline__ void behz_floor_sk_unit(const uint64_t *tens, uint64_
     const uint64_t amag = neg ? pm.q - alpha : alpha;
     for (uint32_t i = 0; i < L; ++i) {
         const PrimeConst pc = pcs[i];
-        u128 acc = {0, 0};
-#pragma unroll
-        for (int j = 0; j < kMaxBfvLimbs; ++j)
-            if (j < (int)nb) mac(acc, w[j], tab[o.cross_b_q + j * L + i]);
+        const u128 acc = dot_wide<kMaxBfvLimbs>(w, [&](int j) { return tab[o.cross_b_q + j * L + i]; }, nb);
         const uint64_t r = barrett128(acc, pc.mu1, pc.mu0, pc.q);
         const uint64_t am = mulmod(barrett64(amag, pc.mu1, pc.mu0, pc.q), tab[o.m_q + i], pc.mu1, pc.mu0, pc.q);
         out[(size_t)i << log_n] = neg ? addmod(r, am, pc.q) : submod(r, am, pc.q);

@@ -22,6 +22,8 @@ struct PrimeConst {
     uint64_t wlast, wlast_p; // psi^-brv(1) * N^-1 (last inverse stage) and companion
     uint64_t tmod, tmod_p;   // plaintext modulus t mod q and companion (BGV/BFV; 0 for CKKS)
     uint64_t tinv, tinv_p;   // t^-1 mod q and companion
+    uint64_t r64, r64_p;     // 2^64 mod q and companion
+    uint64_t one_p;          // floor(2^64 / q): Shoup companion of 1
 };
 
 struct __align__(16) TwPair {
