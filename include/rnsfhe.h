@@ -110,7 +110,7 @@ int rf_intt(const rf_ctx *ctx, uint64_t *data, uint32_t first_limb, uint32_t n_l
 
 /* HMult+Relin (the paper's multiply followed by relinearize):
  * out = (d0 + KS_0(d2), d1 + KS_1(d2)) with (d0, d1, d2) the tensor product of
- * a and b, rlk the relinearisation key, out must not alias a or b.
+ * a and b, rlk the relinearisation key, out must not overlap a or b.
  *   CKKS / BGV: ciphertexts with `n_limbs` Q-limbs in the NTT domain.
  *   BFV: ciphertexts with all L limbs (n_limbs == L) in the COEFFICIENT domain;
  *   (d0, d1, d2) is the BEHZ tensor: extension to B_sk with the small
@@ -124,7 +124,7 @@ int rf_hmult_relin(const rf_ctx *ctx, const uint64_t *a, const uint64_t *b, cons
 /* HRotate: out = (sigma_g(c0) + KS_0(sigma_g(c1)), KS_1(sigma_g(c1))) with
  * sigma_g : a(X) -> a(X^g), g odd in [1, 2N), and gk the key from s(X^g) to s.
  * g = 5^r mod 2N rotates the slots left by r; g = 2N - 1 conjugates.
- * out must not alias in. */
+ * out must not overlap in. */
 int rf_rotate(const rf_ctx *ctx, const uint64_t *in, uint32_t galois_elt, const uint64_t *gk,
               uint64_t *out, uint32_t n_limbs, void *workspace, size_t workspace_bytes,
               void *stream);

@@ -38,6 +38,9 @@ int check_ws(const rf_ctx *c, int op, uint32_t nl, void *ws, size_t ws_bytes) {
     return RF_OK;
 }
 
+// Whether [a, a + na) and [b, b + nb) (in uint64 residues) share memory.
+bool overlaps(const uint64_t *a, size_t na, const uint64_t *b, size_t nb) { return a < b + nb && b < a + na; }
+
 // Set the context's device for the duration of a call.
 struct DeviceGuard {
     int prev = -1;
@@ -67,26 +70,34 @@ NttBatch batch(const uint64_t *in, uint64_t *out, uint64_t in_stride, uint64_t o
 }
 
 // (KS_0(d), KS_1(d)) into out [2][nl][N]; add0/add1 (nullable) are added.
+// dc_ready: the workspace's d_coeff region already holds INTT(d) (written by a
+// fused first pass, launch_intt_first).  galois0 != 0: add0 is added as
+// sigma_g(add0) (two-pass ring degrees only).
 int keyswitch_core(const rf_ctx *c, const uint64_t *d, const uint64_t *evk, uint64_t *out, uint32_t nl,
-                   const uint64_t *add0, const uint64_t *add1, uint64_t *ws, hipStream_t s) {
+                   const uint64_t *add0, const uint64_t *add1, uint64_t *ws, hipStream_t s, bool dc_ready = false,
+                   uint32_t galois0 = 0) {
     const KsLayout l = ks_layout(c, nl);
     const size_t N = c->n;
     const ModupLevel &lv = c->modup_levels[nl];
     uint64_t *d_coeff = ws + l.d_coeff, *ext = ws + l.ext, *ip = ws + l.ip, *conv = ws + l.conv;
     int rc;
     // ModUp: INTT of d, base conversion of each digit, NTT of the new limbs
-    if ((rc = launch_ntt(c, batch(d, d_coeff, 0, 0, nl, 1, 0, nullptr), false, s))) return rc;
+    if (!dc_ready && (rc = launch_ntt(c, batch(d, d_coeff, 0, 0, nl, 1, 0, nullptr), false, s))) return rc;
     if ((rc = launch_modup_bconv(c, d_coeff, ext, nl, s))) return rc;
     if ((rc = launch_ntt(c, batch(ext, ext, 0, 0, lv.ext_limbs, 1, 0, c->d_pmaps + lv.pmap_off), true, s))) return rc;
     // inner product with the key over Q_l u P
     if ((rc = launch_inner_product(c, d, ext, evk, ip, nl, s))) return rc;
     // ModDown: INTT of the P-limbs, base conversion to Q_l, NTT, subtract and scale by P^-1
     const uint64_t ip_stride = (uint64_t)(nl + c->K) * N;
-    if ((rc = launch_ntt(c, batch(ip + (size_t)nl * N, ip + (size_t)nl * N, ip_stride, ip_stride, c->K, 2, c->L,
-                                  nullptr), false, s)))
-        return rc;
+    const NttBatch pl = batch(ip + (size_t)nl * N, ip + (size_t)nl * N, ip_stride, ip_stride, c->K, 2, c->L, nullptr);
+    if (c->log_n > 12) {
+        // the INTT folds in the conversion's input factor; the conversion runs in
+        // the first pass of the NTT and the tail in its last pass
+        if ((rc = launch_ntt(c, pl, false, s, c->d_pc_md))) return rc;
+        return launch_ntt_fwd_moddown(c, conv, ip, add0, add1, out, nl, s, galois0);
+    }
+    if ((rc = launch_ntt(c, pl, false, s))) return rc;
     if ((rc = launch_moddown_bconv(c, ip, conv, nl, s))) return rc;
-    if (c->log_n > 12) return launch_ntt_fwd_moddown(c, conv, ip, add0, add1, out, nl, s);
     if ((rc = launch_ntt(c, batch(conv, conv, (uint64_t)nl * N, (uint64_t)nl * N, nl, 2, 0, nullptr), true, s)))
         return rc;
     return launch_moddown_tail(c, ip, conv, add0, add1, out, nl, s);
@@ -180,7 +191,9 @@ extern "C" int rf_hmult_relin(const rf_ctx *c, const uint64_t *a, const uint64_t
     int rc;
     if ((rc = check_level(c, nl))) return rc;
     if (!a || !b || !rlk || !out) return fail(RF_EINVAL, "rf_hmult_relin: null argument");
-    if (out == a || out == b) return fail(RF_EINVAL, "rf_hmult_relin: out aliases an input");
+    const size_t ct = 2 * (size_t)nl * c->n;
+    if (overlaps(out, ct, a, ct) || overlaps(out, ct, b, ct))
+        return fail(RF_EINVAL, "rf_hmult_relin: out overlaps an input");
     if ((rc = check_ws(c, RF_OP_HMULT_RELIN, nl, ws, ws_bytes))) return rc;
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
@@ -191,6 +204,11 @@ extern "C" int rf_hmult_relin(const rf_ctx *c, const uint64_t *a, const uint64_t
     const size_t poly = (size_t)nl * c->n;
     uint64_t *d2 = (uint64_t *)ws;
     uint64_t *ks_ws = d2 + poly;
+    if (c->log_n > 12) {
+        // the tensor runs in the first pass of INTT(d2)
+        if ((rc = launch_intt_first(c, a, b, out, d2, ks_ws + ks_layout(c, nl).d_coeff, 0, nl, s))) return rc;
+        return keyswitch_core(c, d2, rlk, out, nl, out, out + poly, ks_ws, s, true);
+    }
     if ((rc = launch_tensor(c, a, b, out, d2, nl, s))) return rc;
     return keyswitch_core(c, d2, rlk, out, nl, out, out + poly, ks_ws, s);
 }
@@ -200,7 +218,8 @@ extern "C" int rf_rotate(const rf_ctx *c, const uint64_t *in, uint32_t galois, c
     int rc;
     if ((rc = check_level(c, nl))) return rc;
     if (!in || !gk || !out) return fail(RF_EINVAL, "rf_rotate: null argument");
-    if (out == in) return fail(RF_EINVAL, "rf_rotate: out aliases in");
+    if (overlaps(out, 2 * (size_t)nl * c->n, in, 2 * (size_t)nl * c->n))
+        return fail(RF_EINVAL, "rf_rotate: out overlaps in");
     if ((galois & 1u) == 0 || galois >= 2u * c->n) return fail(RF_EINVAL, "rf_rotate: Galois element must be odd and < 2N");
     if (c->scheme == RF_BFV) return fail(RF_EUNSUPPORTED, "rf_rotate: CKKS or BGV (NTT-domain ciphertexts)");
     if ((rc = check_ws(c, RF_OP_ROTATE, nl, ws, ws_bytes))) return rc;
@@ -209,6 +228,12 @@ extern "C" int rf_rotate(const rf_ctx *c, const uint64_t *in, uint32_t galois, c
     const size_t poly = (size_t)nl * c->n;
     uint64_t *d = (uint64_t *)ws;
     uint64_t *ks_ws = d + poly;
+    if (c->log_n > 12) {
+        // sigma_g(a1) is gathered by the first pass of its INTT, sigma_g(a0) by the ModDown tail
+        if ((rc = launch_intt_first(c, in, nullptr, nullptr, d, ks_ws + ks_layout(c, nl).d_coeff, galois, nl, s)))
+            return rc;
+        return keyswitch_core(c, d, gk, out, nl, in, nullptr, ks_ws, s, true, galois);
+    }
     if ((rc = launch_automorphism(c, in, out, galois, nl, 1, s))) return rc;
     if ((rc = launch_automorphism(c, in + poly, d, galois, nl, 1, s))) return rc;
     return keyswitch_core(c, d, gk, out, nl, out, nullptr, ks_ws, s);
@@ -236,15 +261,16 @@ static int divide_last(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint3
     const uint64_t in_stride = (uint64_t)nl * N;
     if ((rc = launch_ntt(c, batch(in + (size_t)(nl - 1) * N, last, in_stride, N, 1, 2, nl - 1, nullptr), false, s)))
         return rc;
-    if ((rc = launch_rescale_lift(c, last, lift, nl, keep_t, s))) return rc;
     // out has a smaller polynomial stride than in: when they overlap, compute in
     // the workspace and copy the result over.
     const bool overlap = (const void *)out < (const void *)(in + 2 * (size_t)nl * N) &&
                          (const void *)in < (const void *)(out + 2 * (size_t)(nl - 1) * N);
     if (c->log_n > 12) {
-        if (!overlap) return launch_ntt_fwd_rescale(c, lift, in, out, nl, s);
-        if ((rc = launch_ntt_fwd_rescale(c, lift, in, lift, nl, s))) return rc;
+        // the lift runs in the first pass of the NTT and the tail in its last pass
+        if (!overlap) return launch_ntt_fwd_rescale(c, last, lift, in, out, nl, keep_t, s);
+        if ((rc = launch_ntt_fwd_rescale(c, last, lift, in, lift, nl, keep_t, s))) return rc;
     } else {
+        if ((rc = launch_rescale_lift(c, last, lift, nl, keep_t, s))) return rc;
         if ((rc = launch_ntt(c, batch(lift, lift, (uint64_t)(nl - 1) * N, (uint64_t)(nl - 1) * N, nl - 1, 2, 0,
                                       nullptr), true, s)))
             return rc;

@@ -101,6 +101,7 @@ const char *last_error() { return g_last_error.c_str(); }
 
 static void free_tables(rf_ctx *c) {
     (void)hipFree(c->d_pc);
+    (void)hipFree(c->d_pc_md);
     (void)hipFree(c->d_tw_fwd);
     (void)hipFree(c->d_tw_inv);
     (void)hipFree(c->d_modup);
@@ -298,6 +299,19 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
         }
     }
 
+    // INTT constants of the special primes with the ModDown input factor folded
+    // into the last stage, so the INTT of the P-limbs yields [y (P/p_a)^-1]_{p_a}
+    std::vector<PrimeConst> pc_md = pc;
+    for (uint32_t a = 0; a < c->K; ++a) {
+        PrimeConst &e = pc_md[c->L + a];
+        const uint64_t pa = e.q;
+        const uint64_t f = (c->scheme == RF_BGV ? mdt : md)[2 * a];
+        e.ninv = mulmod_h(e.ninv, f, pa);
+        e.ninv_p = shoup_companion(e.ninv, pa);
+        e.wlast = mulmod_h(e.wlast, f, pa);
+        e.wlast_p = shoup_companion(e.wlast, pa);
+    }
+
     // Rescale: drop q_l (l >= 1) into every q_i, i < l
     std::vector<uint64_t> rs((size_t)c->L * c->L * 3, 0);
     for (uint32_t l = 1; l < c->L; ++l) {
@@ -433,7 +447,7 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
 
     int rc = RF_OK;
     if ((!bz.empty() && ((rc = upload(&c->d_behz, bz)) || (rc = upload(&c->d_pmap_qb, pmqb)))) ||
-        (rc = upload(&c->d_pc, pc)) || (rc = upload(&c->d_tw_fwd, twf)) || (rc = upload(&c->d_tw_inv, twi)) ||
+        (rc = upload(&c->d_pc, pc)) || (rc = upload(&c->d_pc_md, pc_md)) || (rc = upload(&c->d_tw_fwd, twf)) || (rc = upload(&c->d_tw_inv, twi)) ||
         (rc = upload(&c->d_modup, mu)) || (rc = upload(&c->d_moddown, md)) ||
         (!mdt.empty() && (rc = upload(&c->d_moddown_t, mdt))) || (rc = upload(&c->d_rescale, rs)) ||
         (rc = upload(&c->d_pmaps, pm))) {

@@ -12,9 +12,14 @@ struct LimbView {
     uint32_t g;  // prime index
 };
 
+// grid.y runs over the limbs with the polynomials interleaved (limb li of every
+// polynomial, then limb li + 1, ...): the tiles that share a prime's twiddles
+// are launched back to back, 16 workgroups apart at N = 2^16, which places them
+// on the same XCD (workgroups are dealt to the 8 XCDs in turn), so the second
+// reads the twiddles from that XCD's L2.
 __device__ __forceinline__ LimbView limb_view(const NttBatch &b, int log_n) {
     const uint32_t limb = blockIdx.y;
-    const uint32_t poly = limb / b.per_poly, li = limb - poly * b.per_poly;
+    const uint32_t li = limb / b.n_polys, poly = limb - li * b.n_polys;
     LimbView v;
     v.g = b.pmap ? (uint32_t)b.pmap[li] : b.prime_base + li;
     v.in = b.in + (size_t)poly * b.in_poly_stride + ((size_t)li << log_n);
@@ -40,22 +45,110 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
     ntt_rows_unit<A, B, FWD>(lds, v.in, v.out, tw_all + ((size_t)v.g << (A + B)), pc, blockIdx.x);
 }
 
+// First forward pass of NTT(conv) with the ModDown base conversion as its
+// prologue: limb (c, i) of conv [2][nl][N] from the K P-limbs of ip[c].
+template <int A, int B, int KP>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesCols))) void ntt_cols_moddown_kernel(
+    const uint64_t *ip, uint64_t *conv, const TwPair *__restrict__ tw_all, const PrimeConst *__restrict__ pcs,
+    const uint64_t *__restrict__ cross, const uint64_t *__restrict__ negp, uint32_t nl, uint32_t L, uint32_t K) {
+    __shared__ uint64_t lds[(1 << A) * (kTile / (1 << A) + 1)];
+    constexpr int LOGN = A + B;
+    const uint32_t c = blockIdx.y & 1, i = blockIdx.y >> 1;  // polynomials interleaved
+    const PrimeConst pc = pcs[i];
+    ModdownPro<KP> pro;
+    pro.src = ip + (((size_t)c * (nl + K) + nl) << LOGN);
+    pro.stride = (size_t)1 << LOGN;
+    pro.K = K;
+#pragma unroll
+    for (int a = 0; a < KP; ++a) {
+        pro.half[a] = a < (int)K ? pcs[L + a].q >> 1 : 0;
+        pro.cross[a] = a < (int)K ? cross[(size_t)i * K + a] : 0;
+    }
+    pro.negp = negp[i];
+    pro.q = pc.q;
+    pro.r64 = pc.r64;
+    pro.r64_p = pc.r64_p;
+    pro.one_p = pc.one_p;
+    ntt_cols_unit_pro<A, B, true>(lds, conv + (((size_t)c * nl + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
+                                  blockIdx.x, pro);
+}
+
+// First forward pass of NTT(lift) with the rescale lift as its prologue: limb
+// (c, i) of lift [2][l][N], l = nl - 1, from the last limb last[c].
+template <int A, int B, bool KEEP_T>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesCols))) void ntt_cols_lift_kernel(
+    const uint64_t *last, uint64_t *lift, const TwPair *__restrict__ tw_all, const PrimeConst *__restrict__ pcs,
+    const uint64_t *__restrict__ tab, uint32_t nl, uint32_t L) {
+    __shared__ uint64_t lds[(1 << A) * (kTile / (1 << A) + 1)];
+    constexpr int LOGN = A + B;
+    const uint32_t l = nl - 1;
+    const uint32_t c = blockIdx.y & 1, i = blockIdx.y >> 1;  // polynomials interleaved
+    const PrimeConst pl = pcs[l];
+    const PrimeConst pc = pcs[i];
+    LiftPro<KEEP_T> pro;
+    pro.last = last + ((size_t)c << LOGN);
+    pro.ql = pl.q;
+    pro.ql_half = pl.q >> 1;
+    pro.tinv = pl.tinv;
+    pro.tinv_p = pl.tinv_p;
+    pro.q = pc.q;
+    pro.one_p = pc.one_p;
+    pro.corr = tab[((size_t)l * L + i) * 3 + 2];
+    pro.tmod = pc.tmod;
+    pro.tmod_p = pc.tmod_p;
+    ntt_cols_unit_pro<A, B, true>(lds, lift + (((size_t)c * l + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
+                                  blockIdx.x, pro);
+}
+
 // Last forward pass of NTT(conv) with the ModDown tail: limb (c, i) of conv
 // [2][nl][N] -> out[c][i] = (ip[c][i] - NTT(conv)[c][i]) P^-1 (+ add_c[i]).
 template <int A, int B>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesRows))) void ntt_rows_moddown_kernel(
     const uint64_t *conv, const TwPair *__restrict__ tw_all, const PrimeConst *__restrict__ pcs, const uint64_t *ip,
     const uint64_t *add0, const uint64_t *add1, uint64_t *out, const uint64_t *__restrict__ pinv, uint32_t nl,
-    uint32_t K) {
+    uint32_t K, uint32_t galois0) {
     __shared__ uint64_t lds[(1 << B) * (kTile / (1 << B) + 1)];
     constexpr int LOGN = A + B;
-    const uint32_t c = blockIdx.y / nl, i = blockIdx.y - c * nl;
+    const uint32_t c = blockIdx.y & 1, i = blockIdx.y >> 1;  // polynomials interleaved
     const PrimeConst pc = pcs[i];
     const uint64_t *add = c == 0 ? add0 : add1;
     ModdownTailEpi epi{ip + (((size_t)c * (nl + K) + i) << LOGN), add ? add + ((size_t)i << LOGN) : nullptr,
-                       out + (((size_t)c * nl + i) << LOGN), pinv[2 * i], pinv[2 * i + 1], pc.q};
+                       out + (((size_t)c * nl + i) << LOGN), pinv[2 * i], pinv[2 * i + 1], pc.q,
+                       c == 0 ? galois0 : 0u, (uint32_t)LOGN};
     ntt_rows_unit_epi<A, B, true>(lds, conv + (((size_t)c * nl + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
                                   blockIdx.x, epi);
+}
+
+// First inverse pass of INTT(d2) with the HMult tensor product as its prologue:
+// limb i of a, b ([2][nl][N], NTT domain) gives d0, d1 (into d01 = [2][nl][N]),
+// d2 (into d2 [nl][N]); the row pass of d2 goes to dc.
+template <int A, int B>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesRows))) void ntt_inv_rows_tensor_kernel(
+    const uint64_t *a, const uint64_t *b, uint64_t *d01, uint64_t *d2, uint64_t *dc, const TwPair *__restrict__ tw_all,
+    const PrimeConst *__restrict__ pcs, uint32_t nl) {
+    __shared__ uint64_t lds[(1 << B) * (kTile / (1 << B) + 1)];
+    constexpr int LOGN = A + B;
+    const uint32_t i = blockIdx.y;
+    const PrimeConst pc = pcs[i];
+    const size_t li = (size_t)i << LOGN, poly = (size_t)nl << LOGN;
+    const TensorPro pro{a + li, a + poly + li, b + li, b + poly + li, d01 + li, d01 + poly + li, d2 + li,
+                        pc.q, pc.mu1, pc.mu0};
+    ntt_rows_unit_pe<A, B, false>(lds, pro, tw_all + li, pc, blockIdx.x, StoreEpi{dc + li});
+}
+
+// First inverse pass of INTT(sigma_g(a1)) with the automorphism as its
+// prologue: limb i of a1 ([nl][N], NTT domain) permuted into d, row pass into dc.
+template <int A, int B>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesRows))) void ntt_inv_rows_gather_kernel(
+    const uint64_t *a1, uint64_t *d, uint64_t *dc, uint32_t galois, const TwPair *__restrict__ tw_all,
+    const PrimeConst *__restrict__ pcs) {
+    __shared__ uint64_t lds[(1 << B) * (kTile / (1 << B) + 1)];
+    constexpr int LOGN = A + B;
+    const uint32_t i = blockIdx.y;
+    const PrimeConst pc = pcs[i];
+    const size_t li = (size_t)i << LOGN;
+    const GatherPro pro{a1 + li, d + li, galois, (uint32_t)LOGN};
+    ntt_rows_unit_pe<A, B, false>(lds, pro, tw_all + li, pc, blockIdx.x, StoreEpi{dc + li});
 }
 
 // Last forward pass of NTT(lift) with the rescale tail: limb (c, i) of lift
@@ -67,7 +160,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
     __shared__ uint64_t lds[(1 << B) * (kTile / (1 << B) + 1)];
     constexpr int LOGN = A + B;
     const uint32_t l = nl - 1;
-    const uint32_t c = blockIdx.y / l, i = blockIdx.y - c * l;
+    const uint32_t c = blockIdx.y & 1, i = blockIdx.y >> 1;  // polynomials interleaved
     const PrimeConst pc = pcs[i];
     const uint64_t *t = tab + ((size_t)l * L + i) * 3;
     RescaleTailEpi epi{in + (((size_t)c * nl + i) << LOGN), out + (((size_t)c * l + i) << LOGN), t[0], t[1], pc.q};
@@ -103,7 +196,8 @@ __global__ __launch_bounds__(kThreads) void ntt_single_kernel(NttBatch b, const 
 }
 
 template <int A, int B>
-static void launch_two_pass(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s) {
+static void launch_two_pass(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s,
+                            const PrimeConst *pcs) {
     const uint32_t limbs = b.per_poly * b.n_polys;
     const dim3 block(kThreads);
     const dim3 grid_cols((1u << B) / (kTile >> A), limbs);
@@ -114,39 +208,44 @@ static void launch_two_pass(const rf_ctx *c, const NttBatch &b, bool forward, hi
     if (forward) {
         {
             ProfScope p("ntt_fwd_cols", s);
-            hipLaunchKernelGGL((ntt_cols_kernel<A, B, true>), grid_cols, block, 0, s, b, c->d_tw_fwd, c->d_pc);
+            hipLaunchKernelGGL((ntt_cols_kernel<A, B, true>), grid_cols, block, 0, s, b, c->d_tw_fwd, pcs);
         }
         ProfScope p("ntt_fwd_rows", s);
-        hipLaunchKernelGGL((ntt_rows_kernel<A, B, true>), grid_rows, block, 0, s, b2, c->d_tw_fwd, c->d_pc);
+        hipLaunchKernelGGL((ntt_rows_kernel<A, B, true>), grid_rows, block, 0, s, b2, c->d_tw_fwd, pcs);
     } else {
         {
             ProfScope p("ntt_inv_rows", s);
-            hipLaunchKernelGGL((ntt_rows_kernel<A, B, false>), grid_rows, block, 0, s, b, c->d_tw_inv, c->d_pc);
+            hipLaunchKernelGGL((ntt_rows_kernel<A, B, false>), grid_rows, block, 0, s, b, c->d_tw_inv, pcs);
         }
         ProfScope p("ntt_inv_cols", s);
-        hipLaunchKernelGGL((ntt_cols_kernel<A, B, false>), grid_cols, block, 0, s, b2, c->d_tw_inv, c->d_pc);
+        hipLaunchKernelGGL((ntt_cols_kernel<A, B, false>), grid_cols, block, 0, s, b2, c->d_tw_inv, pcs);
     }
 }
 
-template <int A, int B>
-static void launch_cols_fwd(const rf_ctx *c, const NttBatch &b, hipStream_t s) {
-    ProfScope p("ntt_fwd_cols", s);
-    hipLaunchKernelGGL((ntt_cols_kernel<A, B, true>), dim3((1u << B) / (kTile >> A), b.per_poly * b.n_polys),
-                       dim3(kThreads), 0, s, b, c->d_tw_fwd, c->d_pc);
-}
-
 int launch_ntt_fwd_moddown(const rf_ctx *c, uint64_t *conv, const uint64_t *ip, const uint64_t *add0,
-                           const uint64_t *add1, uint64_t *out, uint32_t nl, hipStream_t s) {
-    const uint64_t stride = (uint64_t)nl * c->n;
-    NttBatch b{conv, conv, stride, stride, nl, 2, 0, nullptr};
+                           const uint64_t *add1, uint64_t *out, uint32_t nl, hipStream_t s, uint32_t galois0) {
+    const uint64_t *tab = c->scheme == RF_BGV ? c->d_moddown_t : c->d_moddown;
+    const uint64_t *cross = tab + moddown_cross_off(c), *negp = tab + moddown_negp_off(c);
     const uint64_t *pinv = c->d_moddown + moddown_pinv_off(c);
     const dim3 g(c->n / kTile, 2 * nl);
-#define RF_MD(A, B)                                                                                             \
+#define RF_MDK(A, B, KP)                                                                                         \
+    hipLaunchKernelGGL((ntt_cols_moddown_kernel<A, B, KP>), dim3((1u << B) / (kTile >> A), 2 * nl), dim3(kThreads), \
+                       0, s, ip, conv, c->d_tw_fwd, c->d_pc, cross, negp, nl, c->L, c->K)
+#define RF_MD(A, B)                                                                                              \
     {                                                                                                            \
-        launch_cols_fwd<A, B>(c, b, s);                                                                          \
+        {                                                                                                        \
+            ProfScope p("ntt_fwd_cols_moddown", s);                                                              \
+            switch (c->K) {                                                                                      \
+                case 1: RF_MDK(A, B, 1); break;                                                                  \
+                case 2: RF_MDK(A, B, 2); break;                                                                  \
+                case 3: RF_MDK(A, B, 3); break;                                                                  \
+                case 4: RF_MDK(A, B, 4); break;                                                                  \
+                default: RF_MDK(A, B, 8); break;                                                                 \
+            }                                                                                                    \
+        }                                                                                                        \
         ProfScope p("ntt_fwd_rows_moddown", s);                                                                  \
         hipLaunchKernelGGL((ntt_rows_moddown_kernel<A, B>), g, dim3(kThreads), 0, s, conv, c->d_tw_fwd, c->d_pc, ip, \
-                           add0, add1, out, pinv, nl, c->K);                                                     \
+                           add0, add1, out, pinv, nl, c->K, galois0);                                            \
     }
     switch (c->log_n) {
         case 13: RF_MD(7, 6) break;
@@ -156,20 +255,28 @@ int launch_ntt_fwd_moddown(const rf_ctx *c, uint64_t *conv, const uint64_t *ip, 
         default: return fail(RF_EUNSUPPORTED, "fused ModDown NTT: ring degree");
     }
 #undef RF_MD
+#undef RF_MDK
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(RF_EHIP, std::string("NTT launch: ") + hipGetErrorString(e));
     return RF_OK;
 }
 
-int launch_ntt_fwd_rescale(const rf_ctx *c, uint64_t *lift, const uint64_t *in, uint64_t *out, uint32_t nl,
-                           hipStream_t s) {
+int launch_ntt_fwd_rescale(const rf_ctx *c, const uint64_t *last, uint64_t *lift, const uint64_t *in,
+                           uint64_t *out, uint32_t nl, bool keep_t, hipStream_t s) {
     const uint32_t l = nl - 1;
-    const uint64_t stride = (uint64_t)l * c->n;
-    NttBatch b{lift, lift, stride, stride, l, 2, 0, nullptr};
     const dim3 g(c->n / kTile, 2 * l);
 #define RF_RS(A, B)                                                                                              \
     {                                                                                                            \
-        launch_cols_fwd<A, B>(c, b, s);                                                                          \
+        {                                                                                                        \
+            ProfScope p("ntt_fwd_cols_lift", s);                                                                 \
+            const dim3 gc((1u << B) / (kTile >> A), 2 * l);                                                      \
+            if (keep_t)                                                                                          \
+                hipLaunchKernelGGL((ntt_cols_lift_kernel<A, B, true>), gc, dim3(kThreads), 0, s, last, lift,     \
+                                   c->d_tw_fwd, c->d_pc, c->d_rescale, nl, c->L);                                \
+            else                                                                                                 \
+                hipLaunchKernelGGL((ntt_cols_lift_kernel<A, B, false>), gc, dim3(kThreads), 0, s, last, lift,    \
+                                   c->d_tw_fwd, c->d_pc, c->d_rescale, nl, c->L);                                \
+        }                                                                                                        \
         ProfScope p("ntt_fwd_rows_rescale", s);                                                                  \
         hipLaunchKernelGGL((ntt_rows_rescale_kernel<A, B>), g, dim3(kThreads), 0, s, lift, c->d_tw_fwd, c->d_pc, in, \
                            out, c->d_rescale, nl, c->L);                                                         \
@@ -187,8 +294,42 @@ int launch_ntt_fwd_rescale(const rf_ctx *c, uint64_t *lift, const uint64_t *in, 
     return RF_OK;
 }
 
-int launch_ntt(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s) {
+int launch_intt_first(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *d01, uint64_t *d,
+                      uint64_t *dc, uint32_t galois, uint32_t nl, hipStream_t s) {
+    const uint64_t N = c->n;
+#define RF_IF(A, B)                                                                                              \
+    {                                                                                                            \
+        const dim3 gr((1u << A) / (kTile >> B), nl);                                                             \
+        if (galois) {                                                                                            \
+            ProfScope p("ntt_inv_rows_gather", s);                                                               \
+            hipLaunchKernelGGL((ntt_inv_rows_gather_kernel<A, B>), gr, dim3(kThreads), 0, s, a + (size_t)nl * N, d, \
+                               dc, galois, c->d_tw_inv, c->d_pc);                                                \
+        } else {                                                                                                 \
+            ProfScope p("ntt_inv_rows_tensor", s);                                                               \
+            hipLaunchKernelGGL((ntt_inv_rows_tensor_kernel<A, B>), gr, dim3(kThreads), 0, s, a, b, d01, d, dc,   \
+                               c->d_tw_inv, c->d_pc, nl);                                                        \
+        }                                                                                                        \
+        NttBatch bc{dc, dc, 0, 0, nl, 1, 0, nullptr};                                                            \
+        ProfScope p("ntt_inv_cols", s);                                                                          \
+        hipLaunchKernelGGL((ntt_cols_kernel<A, B, false>), dim3((1u << B) / (kTile >> A), nl), dim3(kThreads), 0, \
+                           s, bc, c->d_tw_inv, c->d_pc);                                                         \
+    }
+    switch (c->log_n) {
+        case 13: RF_IF(7, 6) break;
+        case 14: RF_IF(7, 7) break;
+        case 15: RF_IF(8, 7) break;
+        case 16: RF_IF(8, 8) break;
+        default: return fail(RF_EUNSUPPORTED, "fused first INTT: ring degree");
+    }
+#undef RF_IF
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(RF_EHIP, std::string("NTT launch: ") + hipGetErrorString(e));
+    return RF_OK;
+}
+
+int launch_ntt(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s, const PrimeConst *pcs) {
     const uint32_t limbs = b.per_poly * b.n_polys;
+    if (!pcs) pcs = c->d_pc;
     if (limbs == 0) return RF_OK;
     if (limbs > 65535) return fail(RF_EUNSUPPORTED, "too many limbs in one NTT launch");
     switch (c->log_n) {
@@ -196,16 +337,16 @@ int launch_ntt(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s) 
             ProfScope p(forward ? "ntt_fwd_single" : "ntt_inv_single", s);
             if (forward)
                 hipLaunchKernelGGL((ntt_single_kernel<12, true>), dim3(1, limbs), dim3(kThreads), 0, s, b,
-                                   c->d_tw_fwd, c->d_pc);
+                                   c->d_tw_fwd, pcs);
             else
                 hipLaunchKernelGGL((ntt_single_kernel<12, false>), dim3(1, limbs), dim3(kThreads), 0, s, b,
-                                   c->d_tw_inv, c->d_pc);
+                                   c->d_tw_inv, pcs);
             break;
         }
-        case 13: launch_two_pass<7, 6>(c, b, forward, s); break;
-        case 14: launch_two_pass<7, 7>(c, b, forward, s); break;
-        case 15: launch_two_pass<8, 7>(c, b, forward, s); break;
-        case 16: launch_two_pass<8, 8>(c, b, forward, s); break;
+        case 13: launch_two_pass<7, 6>(c, b, forward, s, pcs); break;
+        case 14: launch_two_pass<7, 7>(c, b, forward, s, pcs); break;
+        case 15: launch_two_pass<8, 7>(c, b, forward, s, pcs); break;
+        case 16: launch_two_pass<8, 8>(c, b, forward, s, pcs); break;
         default: return fail(RF_EUNSUPPORTED, "ring degree");
     }
     hipError_t e = hipGetLastError();

@@ -150,10 +150,13 @@ __device__ __forceinline__ void ntt_rounds(uint64_t *lds, int ldu, int u, int t,
 // Column pass unit: sub-transforms are columns (2^A rows, stride 2^B), tile
 // `tile` covers 4096 / 2^A consecutive columns.  Forward: the first A stages
 // (output lazy in [0, 4q)); inverse: the last A stages with the N^-1 scaling
-// (output in [0, q)).  Ends with a barrier, so lds may be reused at once.
-template <int A, int B, bool FWD>
-__device__ __forceinline__ void ntt_cols_unit(uint64_t *lds, const uint64_t *in, uint64_t *out,
-                                              const TwPair *__restrict__ tw, const PrimeConst &pc, int tile) {
+// (output in [0, q)).  The input residue of limb index idx is pro(idx) (a
+// plain load, or an element-wise step that precedes the transform: forward
+// inputs may lie anywhere in [0, 4q)).  Ends with a barrier, so lds may be
+// reused at once.
+template <int A, int B, bool FWD, typename Pro>
+__device__ __forceinline__ void ntt_cols_unit_pro(uint64_t *lds, uint64_t *out, const TwPair *__restrict__ tw,
+                                                  const PrimeConst &pc, int tile, const Pro &pro) {
     constexpr int S = 1 << A;
     constexpr int U = kTile / S;
     constexpr int LDU = U + 1;
@@ -162,7 +165,7 @@ __device__ __forceinline__ void ntt_cols_unit(uint64_t *lds, const uint64_t *in,
     for (int r = 0; r < kTile / kThreads; ++r) {
         const int idx = threadIdx.x + r * kThreads;
         const int row = idx / U, col = idx % U;
-        lds[row * LDU + col] = in[((size_t)row << B) + col0 + col];
+        lds[row * LDU + col] = pro(((size_t)row << B) + col0 + col);
     }
     __syncthreads();
     const int u = threadIdx.x % U, t = threadIdx.x / U;
@@ -178,6 +181,65 @@ __device__ __forceinline__ void ntt_cols_unit(uint64_t *lds, const uint64_t *in,
     __syncthreads();
 }
 
+struct LoadPro {
+    const uint64_t *in;
+    __device__ __forceinline__ uint64_t operator()(size_t idx) const { return in[idx]; }
+};
+
+template <int A, int B, bool FWD>
+__device__ __forceinline__ void ntt_cols_unit(uint64_t *lds, const uint64_t *in, uint64_t *out,
+                                              const TwPair *__restrict__ tw, const PrimeConst &pc, int tile) {
+    ntt_cols_unit_pro<A, B, FWD>(lds, out, tw, pc, tile, LoadPro{in});
+}
+
+// Rescale / modulus-switch lift as the prologue of the NTT of the lifted limb:
+// the last limb x (coefficient domain, in [0, q_l)) taken from its centred
+// representative into prime q: [x]_q, + (q - [q_l]_q) when x > q_l / 2, lazy in
+// [0, 3q).  KEEP_T (BGV): x is first replaced by [x t^-1]_{q_l} and the result
+// multiplied by t (lazy in [0, 2q)), so the lift is 0 mod t as well.
+template <bool KEEP_T>
+struct LiftPro {
+    const uint64_t *last;
+    uint64_t ql, ql_half, tinv, tinv_p;  // dropped prime q_l, t^-1 mod q_l
+    uint64_t q, one_p, corr, tmod, tmod_p;
+    __device__ __forceinline__ uint64_t operator()(size_t idx) const {
+        uint64_t x = last[idx];
+        if (KEEP_T) x = shoup(x, tinv, tinv_p, ql);
+        uint64_t r = x - mulhi64(x, one_p) * q;
+        if (x > ql_half) r += corr;
+        if (KEEP_T) r = shoup_lazy(r, tmod, tmod_p, q);
+        return r;
+    }
+};
+
+// ModDown base conversion P -> q_i as the prologue of the NTT of target i:
+// the K P-limbs y_a (coefficient domain, already multiplied by the input
+// factor [(P/p_a)^-1]_{p_a}) give sum_a y_a [P/p_a]_{q_i} + cnt (q_i - [P]_{q_i})
+// with cnt the number of y_a above p_a / 2 (centred digits), lazy in [0, 4q).
+// KP: the number of special primes K, or 8 for any K <= 8 (runtime K).
+template <int KP>
+struct ModdownPro {
+    const uint64_t *src;  // P-limb 0 of the polynomial; limb a at src + a * stride
+    size_t stride;
+    uint32_t K;
+    uint64_t half[KP], cross[KP];
+    uint64_t negp, q, r64, r64_p, one_p;
+    __device__ __forceinline__ uint64_t operator()(size_t idx) const {
+        MacAcc acc;
+        uint64_t cnt = 0;
+#pragma unroll
+        for (int a = 0; a < KP; ++a) {
+            if (KP < 8 || a < (int)K) {
+                const uint64_t y = src[a * stride + idx];
+                cnt += y > half[a] ? 1u : 0u;
+                acc.mac(y, cross[a]);
+            }
+        }
+        acc.add(cnt * negp);
+        return reduce128_lazy(acc.value(), q, r64, r64_p, one_p);
+    }
+};
+
 // Final store of a pass: out[idx] = x.  Passes take the store as a functor, so
 // an element-wise step that follows the transform (the ModDown or rescale
 // tail) runs in the pass's epilogue instead of another kernel.
@@ -190,9 +252,9 @@ struct StoreEpi {
 // covers 4096 / 2^B consecutive rows.  Forward: the last B stages (output in
 // [0, q)); inverse: the first B stages (output lazy in [0, 2q)).  The result
 // for limb index idx goes through epi(idx, value).
-template <int A, int B, bool FWD, typename Epi>
-__device__ __forceinline__ void ntt_rows_unit_epi(uint64_t *lds, const uint64_t *in, const TwPair *__restrict__ tw,
-                                                  const PrimeConst &pc, int tile, const Epi &epi) {
+template <int A, int B, bool FWD, typename Pro, typename Epi>
+__device__ __forceinline__ void ntt_rows_unit_pe(uint64_t *lds, const Pro &pro, const TwPair *__restrict__ tw,
+                                                 const PrimeConst &pc, int tile, const Epi &epi) {
     constexpr int S = 1 << B;
     constexpr int U = kTile / S;
     constexpr int LDU = U + 1;
@@ -201,7 +263,7 @@ __device__ __forceinline__ void ntt_rows_unit_epi(uint64_t *lds, const uint64_t 
     for (int r = 0; r < kTile / kThreads; ++r) {
         const int idx = threadIdx.x + r * kThreads;
         const int row = idx >> B, p = idx & (S - 1);
-        lds[p * LDU + row] = in[((size_t)(row0 + row) << B) + p];
+        lds[p * LDU + row] = pro(((size_t)(row0 + row) << B) + p);
     }
     __syncthreads();
     const int u = threadIdx.x % U, t = threadIdx.x / U;
@@ -218,22 +280,76 @@ __device__ __forceinline__ void ntt_rows_unit_epi(uint64_t *lds, const uint64_t 
     __syncthreads();
 }
 
+template <int A, int B, bool FWD, typename Epi>
+__device__ __forceinline__ void ntt_rows_unit_epi(uint64_t *lds, const uint64_t *in, const TwPair *__restrict__ tw,
+                                                  const PrimeConst &pc, int tile, const Epi &epi) {
+    ntt_rows_unit_pe<A, B, FWD>(lds, LoadPro{in}, tw, pc, tile, epi);
+}
+
 template <int A, int B, bool FWD>
 __device__ __forceinline__ void ntt_rows_unit(uint64_t *lds, const uint64_t *in, uint64_t *out,
                                               const TwPair *__restrict__ tw, const PrimeConst &pc, int tile) {
     ntt_rows_unit_epi<A, B, FWD>(lds, in, tw, pc, tile, StoreEpi{out});
 }
 
+// HMult tensor product as the prologue of the INTT of d2: for limb residue idx,
+// (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1) mod q; d0, d1 and d2 are stored
+// (d2 is needed again in the NTT domain by the inner product) and d2 enters
+// the transform.
+struct TensorPro {
+    const uint64_t *a0, *a1, *b0, *b1;  // limb i of each input polynomial
+    uint64_t *d0, *d1, *d2;
+    uint64_t q, mu1, mu0;
+    __device__ __forceinline__ uint64_t operator()(size_t idx) const {
+        const uint64_t x0 = a0[idx], x1 = a1[idx], y0 = b0[idx], y1 = b1[idx];
+        MacAcc s0, s1, s2;
+        s0.mac(x0, y0);
+        s1.mac(x0, y1);
+        s1.mac(x1, y0);
+        s2.mac(x1, y1);
+        d0[idx] = barrett128(s0.value(), mu1, mu0, q);
+        d1[idx] = barrett128(s1.value(), mu1, mu0, q);
+        const uint64_t r = barrett128(s2.value(), mu1, mu0, q);
+        d2[idx] = r;
+        return r;
+    }
+};
+
+// Index map of sigma_g in the NTT domain (output k holds a(psi^(2 brv(k) + 1))):
+// sigma_g(a)[k] = a[k'] with 2 brv(k') + 1 = (2 brv(k) + 1) g mod 2N.
+__device__ __forceinline__ uint32_t galois_src(uint32_t k, uint32_t galois, uint32_t log_n) {
+    const uint32_t mask2n = (2u << log_n) - 1;
+    const uint32_t rk = __brev(k) >> (32 - log_n);
+    const uint32_t e = ((2u * rk + 1u) * galois) & mask2n;
+    return __brev((e - 1u) >> 1) >> (32 - log_n);
+}
+
+// HRotate automorphism as the prologue of the INTT of sigma_g(a1): the
+// permuted residue is stored (the inner product needs it in the NTT domain)
+// and enters the transform.
+struct GatherPro {
+    const uint64_t *in;  // limb i of a1
+    uint64_t *dst;       // limb i of sigma_g(a1)
+    uint32_t galois, log_n;
+    __device__ __forceinline__ uint64_t operator()(size_t idx) const {
+        const uint64_t v = in[galois_src((uint32_t)idx, galois, log_n)];
+        dst[idx] = v;
+        return v;
+    }
+};
+
 // ModDown tail as the epilogue of the last forward pass of NTT(conv):
-// out = (ip - NTT(conv)) * P^-1 mod q (+ add).  add may alias out.
+// out = (ip - NTT(conv)) * P^-1 mod q (+ add).  add may alias out.  With a
+// Galois element (galois != 0, HRotate) the addend is sigma_g(add), gathered.
 struct ModdownTailEpi {
     const uint64_t *ip;
     const uint64_t *add;
     uint64_t *out;
     uint64_t pinv, pinv_p, q;
+    uint32_t galois, log_n;
     __device__ __forceinline__ void operator()(size_t idx, uint64_t conv) const {
         uint64_t r = shoup(submod(ip[idx], conv, q), pinv, pinv_p, q);
-        if (add) r = addmod(r, add[idx], q);
+        if (add) r = addmod(r, add[galois ? galois_src((uint32_t)idx, galois, log_n) : idx], q);
         out[idx] = r;
     }
 };

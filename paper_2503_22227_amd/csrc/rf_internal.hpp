@@ -85,6 +85,8 @@ struct rf_ctx {
 
     // device tables (owned)
     rf::PrimeConst *d_pc = nullptr;        // [L+K]
+    rf::PrimeConst *d_pc_md = nullptr;     // d_pc with the ModDown input factor [(P/p_a)^-1]_{p_a}
+                                           // folded into the last inverse stage of every special prime
     rf::TwPair *d_tw_fwd = nullptr;        // [L+K][N]: psi^brv(k)
     rf::TwPair *d_tw_inv = nullptr;        // [L+K][N]: psi^-brv(k)
     uint64_t *d_modup = nullptr;           // ModUp base-conversion constants, see context.hip
@@ -135,14 +137,29 @@ void set_error(const std::string &msg);
 int fail(int code, const std::string &msg);
 
 // kernel launchers (kernels.hip)
-int launch_ntt(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s);
-// Forward NTT of conv [2][nl][N] whose last pass applies the ModDown tail
-// (two-pass ring degrees only): out[c][i] = (ip[c][i] - NTT(conv)) P^-1 + add_c.
+// pcs: per-prime constants (null: the context's d_pc).
+int launch_ntt(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s, const PrimeConst *pcs = nullptr);
+// ModDown after the inner product, two-pass ring degrees only: ip = [2][nl + K][N]
+// whose K P-limbs hold the INTT with d_pc_md (so already scaled by the input
+// factor).  The first forward pass computes the base conversion of each Q
+// target in its prologue (into conv [2][nl][N]), the last applies the tail:
+// out[c][i] = (ip[c][i] - NTT(conv)) P^-1 + add_c.
+// galois0 != 0: add0 enters the tail as sigma_g(add0) (gathered, HRotate).
 int launch_ntt_fwd_moddown(const rf_ctx *c, uint64_t *conv, const uint64_t *ip, const uint64_t *add0,
-                           const uint64_t *add1, uint64_t *out, uint32_t nl, hipStream_t s);
-// Forward NTT of lift [2][nl-1][N] whose last pass applies the rescale tail.
-int launch_ntt_fwd_rescale(const rf_ctx *c, uint64_t *lift, const uint64_t *in, uint64_t *out, uint32_t nl,
-                           hipStream_t s);
+                           const uint64_t *add1, uint64_t *out, uint32_t nl, hipStream_t s, uint32_t galois = 0);
+// INTT of the polynomial to key-switch (two-pass ring degrees only), with the
+// step that produces it as the prologue of its first pass, into dc [nl][N]
+// (coefficient domain); the polynomial itself is also stored into d [nl][N]:
+//   galois == 0 (HMult): the tensor of a, b ([2][nl][N]); d0, d1 into d01 [2][nl][N], d2 into d;
+//   galois != 0 (HRotate): sigma_g of a's polynomial 1 into d.
+int launch_intt_first(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *d01, uint64_t *d,
+                      uint64_t *dc, uint32_t galois, uint32_t nl, hipStream_t s);
+// Rescale / modulus switch after the INTT of the last limb (last = [2][N]),
+// two-pass ring degrees only: the first forward pass lifts the last limb into
+// each remaining prime in its prologue (into lift [2][nl-1][N]; KEEP_T for BGV),
+// the last applies the tail out[c][i] = (in[c][i] - NTT(lift)) q_l^-1.
+int launch_ntt_fwd_rescale(const rf_ctx *c, const uint64_t *last, uint64_t *lift, const uint64_t *in,
+                           uint64_t *out, uint32_t nl, bool keep_t, hipStream_t s);
 int launch_tensor(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *d01,
                   uint64_t *d2, uint32_t nl, hipStream_t s);
 int launch_modup_bconv(const rf_ctx *c, const uint64_t *x, uint64_t *ext, uint32_t nl,
