@@ -229,29 +229,33 @@ def main():
                    "us_per_step": ms / prof_steps * 1e3} for k, (c, ms) in prof.items()}
     dominant = max(kernels, key=lambda k: kernels[k]["us_per_step"])
 
-    # roofline of the dominant kernel
-    roof = None
+    # roofline of the dominant kernel: its integer-ALU and HBM fractions, and
+    # the larger of the two is the bound it is closest to
     kd = kernels[dominant]
     traffic = _counter_traffic(dominant)
+    secs = kd["avg_us"] * 1e-6
     if dominant.startswith("ntt"):
-        # one pass of the two-pass NTT: half of the log2(N) stages of N/2 butterflies per limb;
-        # average limbs per launch over the step's launches of this pass
-        limbs_per_launch = _ntt_limbs_per_launch(dominant, L, K, alpha)
-        bfly = limbs_per_launch * (n // 2) * (w["log_n"] // 2)
-        ops = bfly * BFLY_OPS
-        achieved = ops / (kd["avg_us"] * 1e-6) / 1e12
-        peak = VALU_SLOTS_PER_S / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "Tops/s", "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel": dominant, "avg_us": round(kd["avg_us"], 3),
-                "work_per_launch": "%.0f butterflies x %d int32 VALU ops" % (bfly, BFLY_OPS)}
+        limbs, by = _ntt_launch_model(dominant, L, K, alpha, n)
+        bfly = limbs * (n // 2) * (w["log_n"] // 2)
+        alu = bfly * BFLY_OPS / secs / 1e12
+        alu_peak = VALU_SLOTS_PER_S / 1e12
+        work = "%.0f butterflies x %d int32 VALU ops; %.1f MB algorithmic HBM bytes" % (bfly, BFLY_OPS, by / 1e6)
     else:
         op = "rotate" if dominant == "automorphism" else "hmult"
         by = algorithmic_bytes(dominant, L, K, alpha, n, op)
-        achieved = by / (kd["avg_us"] * 1e-6) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dominant,
-                "avg_us": round(kd["avg_us"], 3)}
+        alu, alu_peak = 0.0, VALU_SLOTS_PER_S / 1e12
+        work = "%.1f MB algorithmic HBM bytes" % (by / 1e6)
+    hbm = by / secs / 1e9
+    alu_frac, hbm_frac = alu / alu_peak, hbm / HBM_PEAK_GBS
+    if alu_frac >= hbm_frac:
+        roof = {"bound": "alu", "achieved": round(alu, 3), "peak": round(alu_peak, 3), "unit": "Tops/s",
+                "frac": round(alu_frac, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm_frac, 4)}
+    roof.update({"traffic": traffic, "kernel": dominant, "avg_us": round(kd["avg_us"], 3),
+                 "alu_frac": round(alu_frac, 4), "hbm_frac": round(hbm_frac, 4),
+                 "algorithmic_bytes": round(by), "work_per_launch": work})
 
     batch = None
     if not args.no_batch:
@@ -330,25 +334,39 @@ def _kernel_symbol(name: str) -> str:
     table = {"ntt_fwd_cols": "ntt_cols_kernel<8, 8, true>", "ntt_fwd_rows": "ntt_rows_kernel<8, 8, true>",
              "ntt_inv_cols": "ntt_cols_kernel<8, 8, false>", "ntt_inv_rows": "ntt_rows_kernel<8, 8, false>",
              "ntt_fwd_rows_moddown": "ntt_rows_moddown_kernel<8, 8>",
-             "ntt_fwd_rows_rescale": "ntt_rows_rescale_kernel<8, 8>"}
+             "ntt_fwd_rows_rescale": "ntt_rows_rescale_kernel<8, 8>",
+             "ntt_fwd_cols_moddown": "ntt_cols_moddown_kernel<8, 8, 4>",
+             "ntt_fwd_cols_lift": "ntt_cols_lift_kernel<8, 8, false>",
+             "ntt_inv_rows_tensor": "ntt_inv_rows_tensor_kernel<8, 8>",
+             "ntt_inv_rows_gather": "ntt_inv_rows_gather_kernel<8, 8>"}
     return table.get(name, name + "_kernel")
 
 
-def _ntt_limbs_per_launch(name: str, L: int, K: int, alpha: int) -> float:
-    """Mean limbs per launch of an NTT pass in one step (HMult+Relin, rescale, HRotate at L limbs).
-    The forward row pass of NTT(conv) carries the ModDown tail and that of the
-    lifted limb the rescale tail; the other passes are plain."""
+def _ntt_launch_model(name: str, L: int, K: int, alpha: int, n: int):
+    """(mean limbs, mean algorithmic HBM bytes) per launch of an NTT pass kernel in
+    one step (HMult+Relin, rescale of its result, HRotate, at L limbs).  Bytes: every
+    residue the pass and its fused prologue / epilogue must read or write once
+    (8 B), plus, for row passes, each distinct prime's twiddle table once
+    (N pairs of 16 B; column passes use 2^A - 1 pairs per prime, negligible)."""
     dn = (L + alpha - 1) // alpha
     ext = sum(L - min(alpha, L - j * alpha) + K for j in range(dn))
+    limb, tw = 8.0 * n, 16.0 * n
+    # per launch: (limbs transformed, residues-limbs moved, distinct primes with a row twiddle table)
     launches = {
-        "ntt_fwd_cols": [ext, 2 * L] * 2 + [2 * (L - 1)],   # ModUp NTT, ModDown NTT (x2 ops), rescale
-        "ntt_fwd_rows": [ext, ext],
-        "ntt_fwd_rows_moddown": [2 * L, 2 * L],
-        "ntt_fwd_rows_rescale": [2 * (L - 1)],
-        "ntt_inv_rows": [L, 2 * K] * 2 + [2],              # INTT of d, of the P-limbs (x2 ops), rescale
-        "ntt_inv_cols": [L, 2 * K] * 2 + [2],
+        "ntt_inv_rows_tensor": [(L, 4 * L + 3 * L + L, L)],          # a, b in; d0, d1, d2, row pass out
+        "ntt_inv_rows_gather": [(L, L + L + L, L)],                   # a1 gathered in; sigma(a1), row out
+        "ntt_inv_rows": [(2 * K, 4 * K, K)] * 2 + [(2, 4, 1)],        # P-limbs (x2 ops), rescale's last limb
+        "ntt_inv_cols": [(L, 2 * L, 0)] * 2 + [(2 * K, 4 * K, 0)] * 2 + [(2, 4, 0)],
+        "ntt_fwd_cols": [(ext, 2 * ext, 0)] * 2,                      # ModUp NTT
+        "ntt_fwd_rows": [(ext, 2 * ext, L + K)] * 2,
+        "ntt_fwd_cols_moddown": [(2 * L, 2 * K + 2 * L, 0)] * 2,      # P-limbs in, conv out
+        "ntt_fwd_rows_moddown": [(2 * L, 8 * L, L), (2 * L, 7 * L, L)],  # conv, ip, addends in; out
+        "ntt_fwd_cols_lift": [(2 * (L - 1), 2 + 2 * (L - 1), 0)],     # last limb in, lift out
+        "ntt_fwd_rows_rescale": [(2 * (L - 1), 2 * (L - 1) * 3, L - 1)],
     }[name]
-    return sum(launches) / len(launches)
+    limbs = sum(x[0] for x in launches) / len(launches)
+    by = sum(x[1] * limb + x[2] * tw for x in launches) / len(launches)
+    return limbs, by
 
 
 def batch_section(reps: int):
