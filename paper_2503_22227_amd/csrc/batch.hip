@@ -147,8 +147,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
             // limb li of polynomial poly of conv [2][nl][N]: ModDown tail into out
             const size_t lo = ((size_t)poly * (J.nl + J.K) + li) << J.log_n;
             const size_t oo = ((size_t)poly * J.nl + li) << J.log_n;
-            const ModdownTailEpi epi{J.ip + lo, J.out + oo, J.out + oo, J.pinv[2 * li], J.pinv[2 * li + 1], pc.q,
-                                     0, J.log_n};
+            const ModdownTailEpi epi{J.ip + lo, J.out + oo, J.out + oo, J.pinv[2 * li], J.pinv[2 * li + 1], pc.q};
             switch (J.log_n) {
                 case 16: ntt_rows_unit_epi<8, 8, true>(lds, in, tw, pc, tile, epi); break;
                 case 15: ntt_rows_unit_epi<8, 7, true>(lds, in, tw, pc, tile, epi); break;

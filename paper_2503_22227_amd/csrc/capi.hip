@@ -85,17 +85,19 @@ int keyswitch_core(const rf_ctx *c, const uint64_t *d, const uint64_t *evk, uint
     if (!dc_ready && (rc = launch_ntt(c, batch(d, d_coeff, 0, 0, nl, 1, 0, nullptr), false, s))) return rc;
     if ((rc = launch_modup_bconv(c, d_coeff, ext, nl, s))) return rc;
     if ((rc = launch_ntt(c, batch(ext, ext, 0, 0, lv.ext_limbs, 1, 0, c->d_pmaps + lv.pmap_off), true, s))) return rc;
-    // inner product with the key over Q_l u P
-    if ((rc = launch_inner_product(c, d, ext, evk, ip, nl, s))) return rc;
     // ModDown: INTT of the P-limbs, base conversion to Q_l, NTT, subtract and scale by P^-1
     const uint64_t ip_stride = (uint64_t)(nl + c->K) * N;
     const NttBatch pl = batch(ip + (size_t)nl * N, ip + (size_t)nl * N, ip_stride, ip_stride, c->K, 2, c->L, nullptr);
     if (c->log_n > 12) {
-        // the INTT folds in the conversion's input factor; the conversion runs in
-        // the first pass of the NTT and the tail in its last pass
+        // the inner product applies P^-1 and the addends to its Q-limbs; the INTT
+        // of the P-limbs folds in the conversion's input factor; the conversion
+        // runs in the first pass of the NTT and the tail in its last pass
+        if ((rc = launch_inner_product(c, d, ext, evk, ip, nl, s, add0, add1, galois0, true))) return rc;
         if ((rc = launch_ntt(c, pl, false, s, c->d_pc_md))) return rc;
-        return launch_ntt_fwd_moddown(c, conv, ip, add0, add1, out, nl, s, galois0);
+        return launch_ntt_fwd_moddown(c, conv, ip, out, nl, s);
     }
+    // inner product with the key over Q_l u P
+    if ((rc = launch_inner_product(c, d, ext, evk, ip, nl, s))) return rc;
     if ((rc = launch_ntt(c, pl, false, s))) return rc;
     if ((rc = launch_moddown_bconv(c, ip, conv, nl, s))) return rc;
     if ((rc = launch_ntt(c, batch(conv, conv, (uint64_t)nl * N, (uint64_t)nl * N, nl, 2, 0, nullptr), true, s)))

@@ -54,8 +54,9 @@ __global__ __launch_bounds__(kEw) void inner_product_kernel(const uint64_t *__re
                                                             const uint64_t *__restrict__ evk,
                                                             uint64_t *__restrict__ ip,
                                                             const PrimeConst *__restrict__ pcs, uint32_t log_n,
-                                                            uint32_t nl, uint32_t L, uint32_t K, uint32_t alpha) {
-    inner_product_unit(d, ext, evk, ip, pcs, log_n, nl, L, K, alpha, blockIdx.x, blockIdx.y);
+                                                            uint32_t nl, uint32_t L, uint32_t K, uint32_t alpha,
+                                                            IpFold fold) {
+    inner_product_unit(d, ext, evk, ip, pcs, log_n, nl, L, K, alpha, blockIdx.x, blockIdx.y, fold);
 }
 
 __global__ __launch_bounds__(kEw) void moddown_bconv_kernel(const uint64_t *__restrict__ ip, uint64_t *__restrict__ conv,
@@ -146,10 +147,18 @@ int launch_modup_bconv(const rf_ctx *c, const uint64_t *x, uint64_t *ext, uint32
 }
 
 int launch_inner_product(const rf_ctx *c, const uint64_t *d, const uint64_t *ext, const uint64_t *evk, uint64_t *ip,
-                         uint32_t nl, hipStream_t s) {
+                         uint32_t nl, hipStream_t s, const uint64_t *add0, const uint64_t *add1, uint32_t galois0,
+                         bool fold) {
     ProfScope prof("inner_product", s);
+    IpFold f;
+    if (fold) {
+        f.pinv = c->d_moddown + moddown_pinv_off(c);
+        f.add0 = add0;
+        f.add1 = add1;
+        f.galois0 = galois0;
+    }
     hipLaunchKernelGGL(inner_product_kernel, ew_grid(c, nl + c->K), dim3(kEw), 0, s, d, ext, evk, ip, c->d_pc,
-                       c->log_n, nl, c->L, c->K, c->alpha);
+                       c->log_n, nl, c->L, c->K, c->alpha, f);
     return check_launch("inner_product");
 }
 

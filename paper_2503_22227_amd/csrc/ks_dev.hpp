@@ -106,6 +106,17 @@ __device__ __forceinline__ void modup_bconv_unit(const uint64_t *__restrict__ x,
     }
 }
 
+// What the inner product adds on the Q-limbs when the ModDown tail that follows
+// is reduced to out = ip' - NTT(conv) P^-1 (the fused two-pass path):
+// ip'[c][m] = ip[c][m] P^-1 + add_c[m], with add_c nullable and, when galois0 is
+// non-zero, add_0 read through sigma_g (HRotate's sigma_g(c0)).  pinv null: the
+// plain inner product.
+struct IpFold {
+    const uint64_t *pinv = nullptr;  // pairs (P^-1 mod q_i, companion)
+    const uint64_t *add0 = nullptr, *add1 = nullptr;
+    uint32_t galois0 = 0;
+};
+
 // Inner product with the key on every limb m of Q_l u P (grid.y = m):
 // ip[c][m] = sum_j src_j(m) * evk[j][c][g(m)], src_j(m) = d[m] if m is in digit j,
 // else the ModUp output of digit j.
@@ -114,7 +125,8 @@ __device__ __forceinline__ void inner_product_unit(const uint64_t *__restrict__ 
                                                             const uint64_t *__restrict__ evk,
                                                             uint64_t *__restrict__ ip,
                                                             const PrimeConst *__restrict__ pcs, uint32_t log_n,
-                                                            uint32_t nl, uint32_t L, uint32_t K, uint32_t alpha, uint32_t gx, uint32_t gy) {
+                                                            uint32_t nl, uint32_t L, uint32_t K, uint32_t alpha, uint32_t gx, uint32_t gy,
+                                                            const IpFold &fold = IpFold()) {
     const uint32_t m = gy;
     const size_t n = (size_t)gx * kEw + threadIdx.x;
     const uint32_t g = m < nl ? m : L + (m - nl);
@@ -138,8 +150,20 @@ __device__ __forceinline__ void inner_product_unit(const uint64_t *__restrict__ 
         mac(acc1, src, kj[key_poly]);
     }
     const size_t out_poly = (size_t)(nl + K) << log_n;
-    ip[((size_t)m << log_n) + n] = barrett128(acc0, pc.mu1, pc.mu0, pc.q);
-    ip[out_poly + ((size_t)m << log_n) + n] = barrett128(acc1, pc.mu1, pc.mu0, pc.q);
+    uint64_t r0 = barrett128(acc0, pc.mu1, pc.mu0, pc.q);
+    uint64_t r1 = barrett128(acc1, pc.mu1, pc.mu0, pc.q);
+    if (fold.pinv && m < nl) {
+        const uint64_t pinv = fold.pinv[2 * m], pinv_p = fold.pinv[2 * m + 1];
+        r0 = shoup(r0, pinv, pinv_p, pc.q);
+        r1 = shoup(r1, pinv, pinv_p, pc.q);
+        const size_t lo = (size_t)m << log_n;
+        if (fold.add0)
+            r0 = addmod(r0, fold.add0[lo + (fold.galois0 ? galois_src((uint32_t)n, fold.galois0, log_n) : n)],
+                        pc.q);
+        if (fold.add1) r1 = addmod(r1, fold.add1[lo + n], pc.q);
+    }
+    ip[((size_t)m << log_n) + n] = r0;
+    ip[out_poly + ((size_t)m << log_n) + n] = r1;
 }
 
 // ModDown conversion of one chunk of Q targets from KP special primes
@@ -263,12 +287,8 @@ __device__ __forceinline__ void rescale_tail_unit(const uint64_t *__restrict__ i
 __device__ __forceinline__ void automorphism_unit(const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
                                                            uint32_t galois, uint32_t log_n, uint32_t gx, uint32_t gy) {
     const uint32_t k = gx * kEw + threadIdx.x;
-    const uint32_t mask2n = (2u << log_n) - 1;
-    const uint32_t rk = __brev(k) >> (32 - log_n);
-    const uint32_t e = ((2u * rk + 1u) * galois) & mask2n;
-    const uint32_t src = __brev((e - 1u) >> 1) >> (32 - log_n);
     const size_t base = (size_t)gy << log_n;
-    out[base + k] = in[base + src];
+    out[base + k] = in[base + galois_src(k, galois, log_n)];
 }
 
 }  // namespace rf

@@ -105,16 +105,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
 template <int A, int B>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesRows))) void ntt_rows_moddown_kernel(
     const uint64_t *conv, const TwPair *__restrict__ tw_all, const PrimeConst *__restrict__ pcs, const uint64_t *ip,
-    const uint64_t *add0, const uint64_t *add1, uint64_t *out, const uint64_t *__restrict__ pinv, uint32_t nl,
-    uint32_t K, uint32_t galois0) {
+    uint64_t *out, const uint64_t *__restrict__ pinv, uint32_t nl, uint32_t K) {
     __shared__ uint64_t lds[(1 << B) * (kTile / (1 << B) + 1)];
     constexpr int LOGN = A + B;
     const uint32_t c = blockIdx.y & 1, i = blockIdx.y >> 1;  // polynomials interleaved
     const PrimeConst pc = pcs[i];
-    const uint64_t *add = c == 0 ? add0 : add1;
-    ModdownTailEpi epi{ip + (((size_t)c * (nl + K) + i) << LOGN), add ? add + ((size_t)i << LOGN) : nullptr,
-                       out + (((size_t)c * nl + i) << LOGN), pinv[2 * i], pinv[2 * i + 1], pc.q,
-                       c == 0 ? galois0 : 0u, (uint32_t)LOGN};
+    const ModdownFoldEpi epi{ip + (((size_t)c * (nl + K) + i) << LOGN), out + (((size_t)c * nl + i) << LOGN),
+                             pinv[2 * i], pinv[2 * i + 1], pc.q};
     ntt_rows_unit_epi<A, B, true>(lds, conv + (((size_t)c * nl + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
                                   blockIdx.x, epi);
 }
@@ -222,8 +219,8 @@ static void launch_two_pass(const rf_ctx *c, const NttBatch &b, bool forward, hi
     }
 }
 
-int launch_ntt_fwd_moddown(const rf_ctx *c, uint64_t *conv, const uint64_t *ip, const uint64_t *add0,
-                           const uint64_t *add1, uint64_t *out, uint32_t nl, hipStream_t s, uint32_t galois0) {
+int launch_ntt_fwd_moddown(const rf_ctx *c, uint64_t *conv, const uint64_t *ip, uint64_t *out, uint32_t nl,
+                           hipStream_t s) {
     const uint64_t *tab = c->scheme == RF_BGV ? c->d_moddown_t : c->d_moddown;
     const uint64_t *cross = tab + moddown_cross_off(c), *negp = tab + moddown_negp_off(c);
     const uint64_t *pinv = c->d_moddown + moddown_pinv_off(c);
@@ -245,7 +242,7 @@ int launch_ntt_fwd_moddown(const rf_ctx *c, uint64_t *conv, const uint64_t *ip, 
         }                                                                                                        \
         ProfScope p("ntt_fwd_rows_moddown", s);                                                                  \
         hipLaunchKernelGGL((ntt_rows_moddown_kernel<A, B>), g, dim3(kThreads), 0, s, conv, c->d_tw_fwd, c->d_pc, ip, \
-                           add0, add1, out, pinv, nl, c->K, galois0);                                            \
+                           out, pinv, nl, c->K);                                                                 \
     }
     switch (c->log_n) {
         case 13: RF_MD(7, 6) break;

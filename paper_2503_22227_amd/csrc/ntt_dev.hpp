@@ -315,15 +315,6 @@ struct TensorPro {
     }
 };
 
-// Index map of sigma_g in the NTT domain (output k holds a(psi^(2 brv(k) + 1))):
-// sigma_g(a)[k] = a[k'] with 2 brv(k') + 1 = (2 brv(k) + 1) g mod 2N.
-__device__ __forceinline__ uint32_t galois_src(uint32_t k, uint32_t galois, uint32_t log_n) {
-    const uint32_t mask2n = (2u << log_n) - 1;
-    const uint32_t rk = __brev(k) >> (32 - log_n);
-    const uint32_t e = ((2u * rk + 1u) * galois) & mask2n;
-    return __brev((e - 1u) >> 1) >> (32 - log_n);
-}
-
 // HRotate automorphism as the prologue of the INTT of sigma_g(a1): the
 // permuted residue is stored (the inner product needs it in the NTT domain)
 // and enters the transform.
@@ -339,18 +330,27 @@ struct GatherPro {
 };
 
 // ModDown tail as the epilogue of the last forward pass of NTT(conv):
-// out = (ip - NTT(conv)) * P^-1 mod q (+ add).  add may alias out.  With a
-// Galois element (galois != 0, HRotate) the addend is sigma_g(add), gathered.
+// out = (ip - NTT(conv)) * P^-1 mod q (+ add).  add may alias out.
 struct ModdownTailEpi {
     const uint64_t *ip;
     const uint64_t *add;
     uint64_t *out;
     uint64_t pinv, pinv_p, q;
-    uint32_t galois, log_n;
     __device__ __forceinline__ void operator()(size_t idx, uint64_t conv) const {
         uint64_t r = shoup(submod(ip[idx], conv, q), pinv, pinv_p, q);
-        if (add) r = addmod(r, add[galois ? galois_src((uint32_t)idx, galois, log_n) : idx], q);
+        if (add) r = addmod(r, add[idx], q);
         out[idx] = r;
+    }
+};
+
+// The same tail when the inner product already left ip' = ip P^-1 + add:
+// out = ip' - NTT(conv) P^-1 mod q (one stream read besides the transform).
+struct ModdownFoldEpi {
+    const uint64_t *ip;
+    uint64_t *out;
+    uint64_t pinv, pinv_p, q;
+    __device__ __forceinline__ void operator()(size_t idx, uint64_t conv) const {
+        out[idx] = submod(ip[idx], shoup(conv, pinv, pinv_p, q), q);
     }
 };
 

@@ -104,6 +104,15 @@ struct rf_ctx {
 
 namespace rf {
 
+// Index map of sigma_g in the NTT domain (output k holds a(psi^(2 brv(k) + 1))):
+// sigma_g(a)[k] = a[k'] with 2 brv(k') + 1 = (2 brv(k) + 1) g mod 2N.
+__device__ __forceinline__ uint32_t galois_src(uint32_t k, uint32_t galois, uint32_t log_n) {
+    const uint32_t mask2n = (2u << log_n) - 1;
+    const uint32_t rk = __brev(k) >> (32 - log_n);
+    const uint32_t e = ((2u * rk + 1u) * galois) & mask2n;
+    return __brev((e - 1u) >> 1) >> (32 - log_n);
+}
+
 // Offsets (in uint64 entries) inside the ModUp table block of (digit j, digit size s):
 //   [0, 2*alpha):            factor pairs (w, w') of [(Q_j/q_i)^-1]_{q_i}, i' < s
 //   [2*alpha, ...):          cross[g][i'] = [Q_j/q_i]_{prime g}, g in [0, L+K), target-major
@@ -144,9 +153,10 @@ int launch_ntt(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s, 
 // factor).  The first forward pass computes the base conversion of each Q
 // target in its prologue (into conv [2][nl][N]), the last applies the tail:
 // out[c][i] = (ip[c][i] - NTT(conv)) P^-1 + add_c.
-// galois0 != 0: add0 enters the tail as sigma_g(add0) (gathered, HRotate).
-int launch_ntt_fwd_moddown(const rf_ctx *c, uint64_t *conv, const uint64_t *ip, const uint64_t *add0,
-                           const uint64_t *add1, uint64_t *out, uint32_t nl, hipStream_t s, uint32_t galois = 0);
+// ip's Q-limbs must come from launch_inner_product with fold (P^-1 and the addends
+// applied), so the tail is out[c][i] = ip[c][i] - NTT(conv)[c][i] P^-1.
+int launch_ntt_fwd_moddown(const rf_ctx *c, uint64_t *conv, const uint64_t *ip, uint64_t *out, uint32_t nl,
+                           hipStream_t s);
 // INTT of the polynomial to key-switch (two-pass ring degrees only), with the
 // step that produces it as the prologue of its first pass, into dc [nl][N]
 // (coefficient domain); the polynomial itself is also stored into d [nl][N]:
@@ -164,8 +174,12 @@ int launch_tensor(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_
                   uint64_t *d2, uint32_t nl, hipStream_t s);
 int launch_modup_bconv(const rf_ctx *c, const uint64_t *x, uint64_t *ext, uint32_t nl,
                        hipStream_t s);
+// fold: the Q-limbs leave as ip P^-1 + add_c (add_0 through sigma_g when galois0 != 0),
+// for launch_ntt_fwd_moddown.
 int launch_inner_product(const rf_ctx *c, const uint64_t *d_ntt, const uint64_t *ext,
-                         const uint64_t *evk, uint64_t *ip, uint32_t nl, hipStream_t s);
+                         const uint64_t *evk, uint64_t *ip, uint32_t nl, hipStream_t s,
+                         const uint64_t *add0 = nullptr, const uint64_t *add1 = nullptr, uint32_t galois0 = 0,
+                         bool fold = false);
 int launch_moddown_bconv(const rf_ctx *c, const uint64_t *ip, uint64_t *conv, uint32_t nl,
                          hipStream_t s);  // uses the t-preserving table for BGV contexts
 int launch_moddown_tail(const rf_ctx *c, const uint64_t *ip, const uint64_t *conv,
