@@ -111,10 +111,15 @@ def algorithmic_bytes(kernel: str, nl: int, K: int, alpha: int, n: int, op: str)
     dn = (nl + alpha - 1) // alpha
     ext = sum(nl - min(alpha, nl - j * alpha) + K for j in range(dn))
     limb = 8.0 * n
+    # inner product: dn sources and 2 dn key limbs per limb of Q_l u P, 2 outputs;
+    # on the fused path it also reads a, b (HMult: 4 nl limbs, its own-digit
+    # residues and addends computed from them) or gathers c0, c1 (HRotate: 2 nl)
+    # in place of the nl own-digit source limbs
+    ip_base = dn * (nl + K) + 2 * dn * (nl + K) + 2 * (nl + K) - nl
     table = {
         "tensor": 7 * nl,
         "modup_bconv": nl + ext,
-        "inner_product": dn * (nl + K) + 2 * dn * (nl + K) + 2 * (nl + K),
+        "inner_product": ip_base + (4 * nl if op == "hmult" else 2 * nl),
         "moddown_bconv": 2 * K + 2 * nl,
         "moddown_tail": 8 * nl if op == "hmult" else 7 * nl,
         "rescale_lift": 2 + 2 * (nl - 1),
@@ -241,8 +246,11 @@ def main():
         alu_peak = VALU_SLOTS_PER_S / 1e12
         work = "%.0f butterflies x %d int32 VALU ops; %.1f MB algorithmic HBM bytes" % (bfly, BFLY_OPS, by / 1e6)
     else:
-        op = "rotate" if dominant == "automorphism" else "hmult"
-        by = algorithmic_bytes(dominant, L, K, alpha, n, op)
+        if dominant == "inner_product":  # one HMult+Relin and one HRotate launch per step
+            by = (algorithmic_bytes(dominant, L, K, alpha, n, "hmult") +
+                  algorithmic_bytes(dominant, L, K, alpha, n, "rotate")) / 2
+        else:
+            by = algorithmic_bytes(dominant, L, K, alpha, n, "rotate" if dominant == "automorphism" else "hmult")
         alu, alu_peak = 0.0, VALU_SLOTS_PER_S / 1e12
         work = "%.1f MB algorithmic HBM bytes" % (by / 1e6)
     hbm = by / secs / 1e9

@@ -70,19 +70,19 @@ NttBatch batch(const uint64_t *in, uint64_t *out, uint64_t in_stride, uint64_t o
 }
 
 // (KS_0(d), KS_1(d)) into out [2][nl][N]; add0/add1 (nullable) are added.
-// dc_ready: the workspace's d_coeff region already holds INTT(d) (written by a
-// fused first pass, launch_intt_first).  galois0 != 0: add0 is added as
-// sigma_g(add0) (two-pass ring degrees only).
+// fused (two-pass ring degrees only): d is not materialised; the workspace's
+// d_coeff region already holds INTT(d) (launch_intt_first) and the inner
+// product takes d's residues and the addends from fused's sources.
 int keyswitch_core(const rf_ctx *c, const uint64_t *d, const uint64_t *evk, uint64_t *out, uint32_t nl,
-                   const uint64_t *add0, const uint64_t *add1, uint64_t *ws, hipStream_t s, bool dc_ready = false,
-                   uint32_t galois0 = 0) {
+                   const uint64_t *add0, const uint64_t *add1, uint64_t *ws, hipStream_t s,
+                   const IpFold *fused = nullptr) {
     const KsLayout l = ks_layout(c, nl);
     const size_t N = c->n;
     const ModupLevel &lv = c->modup_levels[nl];
     uint64_t *d_coeff = ws + l.d_coeff, *ext = ws + l.ext, *ip = ws + l.ip, *conv = ws + l.conv;
     int rc;
     // ModUp: INTT of d, base conversion of each digit, NTT of the new limbs
-    if (!dc_ready && (rc = launch_ntt(c, batch(d, d_coeff, 0, 0, nl, 1, 0, nullptr), false, s))) return rc;
+    if (!fused && (rc = launch_ntt(c, batch(d, d_coeff, 0, 0, nl, 1, 0, nullptr), false, s))) return rc;
     if ((rc = launch_modup_bconv(c, d_coeff, ext, nl, s))) return rc;
     if ((rc = launch_ntt(c, batch(ext, ext, 0, 0, lv.ext_limbs, 1, 0, c->d_pmaps + lv.pmap_off), true, s))) return rc;
     // ModDown: INTT of the P-limbs, base conversion to Q_l, NTT, subtract and scale by P^-1
@@ -92,7 +92,14 @@ int keyswitch_core(const rf_ctx *c, const uint64_t *d, const uint64_t *evk, uint
         // the inner product applies P^-1 and the addends to its Q-limbs; the INTT
         // of the P-limbs folds in the conversion's input factor; the conversion
         // runs in the first pass of the NTT and the tail in its last pass
-        if ((rc = launch_inner_product(c, d, ext, evk, ip, nl, s, add0, add1, galois0, true))) return rc;
+        IpFold f;
+        if (fused) {
+            f = *fused;
+        } else {
+            f.add0 = add0;
+            f.add1 = add1;
+        }
+        if ((rc = launch_inner_product(c, d, ext, evk, ip, nl, s, &f))) return rc;
         if ((rc = launch_ntt(c, pl, false, s, c->d_pc_md))) return rc;
         return launch_ntt_fwd_moddown(c, conv, ip, out, nl, s);
     }
@@ -207,9 +214,14 @@ extern "C" int rf_hmult_relin(const rf_ctx *c, const uint64_t *a, const uint64_t
     uint64_t *d2 = (uint64_t *)ws;
     uint64_t *ks_ws = d2 + poly;
     if (c->log_n > 12) {
-        // the tensor runs in the first pass of INTT(d2)
-        if ((rc = launch_intt_first(c, a, b, out, d2, ks_ws + ks_layout(c, nl).d_coeff, 0, nl, s))) return rc;
-        return keyswitch_core(c, d2, rlk, out, nl, out, out + poly, ks_ws, s, true);
+        // d2 = a1 b1 is formed by the first pass of its INTT and, with d0 and d1,
+        // by the inner product
+        if ((rc = launch_intt_first(c, a, b, ks_ws + ks_layout(c, nl).d_coeff, 0, nl, s))) return rc;
+        IpFold f;
+        f.mode = 1;
+        f.a = a;
+        f.b = b;
+        return keyswitch_core(c, nullptr, rlk, out, nl, nullptr, nullptr, ks_ws, s, &f);
     }
     if ((rc = launch_tensor(c, a, b, out, d2, nl, s))) return rc;
     return keyswitch_core(c, d2, rlk, out, nl, out, out + poly, ks_ws, s);
@@ -231,10 +243,14 @@ extern "C" int rf_rotate(const rf_ctx *c, const uint64_t *in, uint32_t galois, c
     uint64_t *d = (uint64_t *)ws;
     uint64_t *ks_ws = d + poly;
     if (c->log_n > 12) {
-        // sigma_g(a1) is gathered by the first pass of its INTT, sigma_g(a0) by the ModDown tail
-        if ((rc = launch_intt_first(c, in, nullptr, nullptr, d, ks_ws + ks_layout(c, nl).d_coeff, galois, nl, s)))
-            return rc;
-        return keyswitch_core(c, d, gk, out, nl, in, nullptr, ks_ws, s, true, galois);
+        // sigma_g(a1) is gathered by the first pass of its INTT and, with sigma_g(a0),
+        // by the inner product
+        if ((rc = launch_intt_first(c, in, nullptr, ks_ws + ks_layout(c, nl).d_coeff, galois, nl, s))) return rc;
+        IpFold f;
+        f.mode = 2;
+        f.a = in;
+        f.galois = galois;
+        return keyswitch_core(c, nullptr, gk, out, nl, nullptr, nullptr, ks_ws, s, &f);
     }
     if ((rc = launch_automorphism(c, in, out, galois, nl, 1, s))) return rc;
     if ((rc = launch_automorphism(c, in + poly, d, galois, nl, 1, s))) return rc;

@@ -147,15 +147,12 @@ int launch_modup_bconv(const rf_ctx *c, const uint64_t *x, uint64_t *ext, uint32
 }
 
 int launch_inner_product(const rf_ctx *c, const uint64_t *d, const uint64_t *ext, const uint64_t *evk, uint64_t *ip,
-                         uint32_t nl, hipStream_t s, const uint64_t *add0, const uint64_t *add1, uint32_t galois0,
-                         bool fold) {
+                         uint32_t nl, hipStream_t s, const IpFold *fold) {
     ProfScope prof("inner_product", s);
     IpFold f;
     if (fold) {
+        f = *fold;
         f.pinv = c->d_moddown + moddown_pinv_off(c);
-        f.add0 = add0;
-        f.add1 = add1;
-        f.galois0 = galois0;
     }
     hipLaunchKernelGGL(inner_product_kernel, ew_grid(c, nl + c->K), dim3(kEw), 0, s, d, ext, evk, ip, c->d_pc,
                        c->log_n, nl, c->L, c->K, c->alpha, f);

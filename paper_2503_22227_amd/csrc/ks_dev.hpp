@@ -106,17 +106,6 @@ __device__ __forceinline__ void modup_bconv_unit(const uint64_t *__restrict__ x,
     }
 }
 
-// What the inner product adds on the Q-limbs when the ModDown tail that follows
-// is reduced to out = ip' - NTT(conv) P^-1 (the fused two-pass path):
-// ip'[c][m] = ip[c][m] P^-1 + add_c[m], with add_c nullable and, when galois0 is
-// non-zero, add_0 read through sigma_g (HRotate's sigma_g(c0)).  pinv null: the
-// plain inner product.
-struct IpFold {
-    const uint64_t *pinv = nullptr;  // pairs (P^-1 mod q_i, companion)
-    const uint64_t *add0 = nullptr, *add1 = nullptr;
-    uint32_t galois0 = 0;
-};
-
 // Inner product with the key on every limb m of Q_l u P (grid.y = m):
 // ip[c][m] = sum_j src_j(m) * evk[j][c][g(m)], src_j(m) = d[m] if m is in digit j,
 // else the ModUp output of digit j.
@@ -133,6 +122,27 @@ __device__ __forceinline__ void inner_product_unit(const uint64_t *__restrict__ 
     const PrimeConst pc = pcs[g];
     const uint32_t dn = (nl + alpha - 1) / alpha;
     const size_t key_poly = (size_t)(L + K) << log_n;
+    // HMult / HRotate sources of the Q-limbs (the P-limbs belong to no digit)
+    uint64_t own = 0, ad0 = 0, ad1 = 0;
+    if (fold.mode != 0 && m < nl) {
+        const size_t lo = (size_t)m << log_n, poly = (size_t)nl << log_n;
+        if (fold.mode == 1) {
+            const uint64_t x0 = fold.a[lo + n], x1 = fold.a[poly + lo + n];
+            const uint64_t y0 = fold.b[lo + n], y1 = fold.b[poly + lo + n];
+            MacAcc s2, s0, s1;
+            s2.mac(x1, y1);
+            s0.mac(x0, y0);
+            s1.mac(x0, y1);
+            s1.mac(x1, y0);
+            own = barrett128(s2.value(), pc.mu1, pc.mu0, pc.q);
+            ad0 = barrett128(s0.value(), pc.mu1, pc.mu0, pc.q);
+            ad1 = barrett128(s1.value(), pc.mu1, pc.mu0, pc.q);
+        } else {
+            const size_t src = lo + galois_src((uint32_t)n, fold.galois, log_n);
+            own = fold.a[poly + src];
+            ad0 = fold.a[src];
+        }
+    }
     u128 acc0 = {0, 0}, acc1 = {0, 0};
 #pragma unroll 4
     for (uint32_t j = 0; j < dn; ++j) {
@@ -140,7 +150,7 @@ __device__ __forceinline__ void inner_product_unit(const uint64_t *__restrict__ 
         const uint32_t s = min(alpha, nl - start);
         uint64_t src;
         if (m >= start && m < start + s) {
-            src = d[((size_t)m << log_n) + n];
+            src = fold.mode != 0 ? own : d[((size_t)m << log_n) + n];
         } else {
             const uint32_t tt = m < start ? m : m - s;
             src = ext[(((size_t)j * (nl + K - alpha) + tt) << log_n) + n];
@@ -157,10 +167,15 @@ __device__ __forceinline__ void inner_product_unit(const uint64_t *__restrict__ 
         r0 = shoup(r0, pinv, pinv_p, pc.q);
         r1 = shoup(r1, pinv, pinv_p, pc.q);
         const size_t lo = (size_t)m << log_n;
-        if (fold.add0)
-            r0 = addmod(r0, fold.add0[lo + (fold.galois0 ? galois_src((uint32_t)n, fold.galois0, log_n) : n)],
-                        pc.q);
-        if (fold.add1) r1 = addmod(r1, fold.add1[lo + n], pc.q);
+        if (fold.mode == 1) {
+            r0 = addmod(r0, ad0, pc.q);
+            r1 = addmod(r1, ad1, pc.q);
+        } else if (fold.mode == 2) {
+            r0 = addmod(r0, ad0, pc.q);
+        } else {
+            if (fold.add0) r0 = addmod(r0, fold.add0[lo + n], pc.q);
+            if (fold.add1) r1 = addmod(r1, fold.add1[lo + n], pc.q);
+        }
     }
     ip[((size_t)m << log_n) + n] = r0;
     ip[out_poly + ((size_t)m << log_n) + n] = r1;

@@ -116,35 +116,33 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
                                   blockIdx.x, epi);
 }
 
-// First inverse pass of INTT(d2) with the HMult tensor product as its prologue:
-// limb i of a, b ([2][nl][N], NTT domain) gives d0, d1 (into d01 = [2][nl][N]),
-// d2 (into d2 [nl][N]); the row pass of d2 goes to dc.
+// First inverse pass of INTT(d2) with d2 = a1 b1 as its prologue: limb i of a, b
+// ([2][nl][N], NTT domain); the row pass goes to dc [nl][N].
 template <int A, int B>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesRows))) void ntt_inv_rows_tensor_kernel(
-    const uint64_t *a, const uint64_t *b, uint64_t *d01, uint64_t *d2, uint64_t *dc, const TwPair *__restrict__ tw_all,
+    const uint64_t *a, const uint64_t *b, uint64_t *dc, const TwPair *__restrict__ tw_all,
     const PrimeConst *__restrict__ pcs, uint32_t nl) {
     __shared__ uint64_t lds[(1 << B) * (kTile / (1 << B) + 1)];
     constexpr int LOGN = A + B;
     const uint32_t i = blockIdx.y;
     const PrimeConst pc = pcs[i];
     const size_t li = (size_t)i << LOGN, poly = (size_t)nl << LOGN;
-    const TensorPro pro{a + li, a + poly + li, b + li, b + poly + li, d01 + li, d01 + poly + li, d2 + li,
-                        pc.q, pc.mu1, pc.mu0};
+    const TensorPro pro{a + poly + li, b + poly + li, pc.q, pc.mu1, pc.mu0};
     ntt_rows_unit_pe<A, B, false>(lds, pro, tw_all + li, pc, blockIdx.x, StoreEpi{dc + li});
 }
 
 // First inverse pass of INTT(sigma_g(a1)) with the automorphism as its
-// prologue: limb i of a1 ([nl][N], NTT domain) permuted into d, row pass into dc.
+// prologue: limb i of a1 ([nl][N], NTT domain) permuted, row pass into dc.
 template <int A, int B>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesRows))) void ntt_inv_rows_gather_kernel(
-    const uint64_t *a1, uint64_t *d, uint64_t *dc, uint32_t galois, const TwPair *__restrict__ tw_all,
+    const uint64_t *a1, uint64_t *dc, uint32_t galois, const TwPair *__restrict__ tw_all,
     const PrimeConst *__restrict__ pcs) {
     __shared__ uint64_t lds[(1 << B) * (kTile / (1 << B) + 1)];
     constexpr int LOGN = A + B;
     const uint32_t i = blockIdx.y;
     const PrimeConst pc = pcs[i];
     const size_t li = (size_t)i << LOGN;
-    const GatherPro pro{a1 + li, d + li, galois, (uint32_t)LOGN};
+    const GatherPro pro{a1 + li, galois, (uint32_t)LOGN};
     ntt_rows_unit_pe<A, B, false>(lds, pro, tw_all + li, pc, blockIdx.x, StoreEpi{dc + li});
 }
 
@@ -291,19 +289,19 @@ int launch_ntt_fwd_rescale(const rf_ctx *c, const uint64_t *last, uint64_t *lift
     return RF_OK;
 }
 
-int launch_intt_first(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *d01, uint64_t *d,
-                      uint64_t *dc, uint32_t galois, uint32_t nl, hipStream_t s) {
+int launch_intt_first(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *dc, uint32_t galois,
+                      uint32_t nl, hipStream_t s) {
     const uint64_t N = c->n;
 #define RF_IF(A, B)                                                                                              \
     {                                                                                                            \
         const dim3 gr((1u << A) / (kTile >> B), nl);                                                             \
         if (galois) {                                                                                            \
             ProfScope p("ntt_inv_rows_gather", s);                                                               \
-            hipLaunchKernelGGL((ntt_inv_rows_gather_kernel<A, B>), gr, dim3(kThreads), 0, s, a + (size_t)nl * N, d, \
-                               dc, galois, c->d_tw_inv, c->d_pc);                                                \
+            hipLaunchKernelGGL((ntt_inv_rows_gather_kernel<A, B>), gr, dim3(kThreads), 0, s, a + (size_t)nl * N, dc, \
+                               galois, c->d_tw_inv, c->d_pc);                                                    \
         } else {                                                                                                 \
             ProfScope p("ntt_inv_rows_tensor", s);                                                               \
-            hipLaunchKernelGGL((ntt_inv_rows_tensor_kernel<A, B>), gr, dim3(kThreads), 0, s, a, b, d01, d, dc,   \
+            hipLaunchKernelGGL((ntt_inv_rows_tensor_kernel<A, B>), gr, dim3(kThreads), 0, s, a, b, dc,           \
                                c->d_tw_inv, c->d_pc, nl);                                                        \
         }                                                                                                        \
         NttBatch bc{dc, dc, 0, 0, nl, 1, 0, nullptr};                                                            \

@@ -292,40 +292,24 @@ __device__ __forceinline__ void ntt_rows_unit(uint64_t *lds, const uint64_t *in,
     ntt_rows_unit_epi<A, B, FWD>(lds, in, tw, pc, tile, StoreEpi{out});
 }
 
-// HMult tensor product as the prologue of the INTT of d2: for limb residue idx,
-// (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1) mod q; d0, d1 and d2 are stored
-// (d2 is needed again in the NTT domain by the inner product) and d2 enters
-// the transform.
+// HMult: d2 = a1 b1 mod q as the prologue of the INTT of d2 (the inner product
+// computes d0, d1 and its own d2 residues from a and b itself).
 struct TensorPro {
-    const uint64_t *a0, *a1, *b0, *b1;  // limb i of each input polynomial
-    uint64_t *d0, *d1, *d2;
+    const uint64_t *a1, *b1;  // limb i of a1, b1
     uint64_t q, mu1, mu0;
     __device__ __forceinline__ uint64_t operator()(size_t idx) const {
-        const uint64_t x0 = a0[idx], x1 = a1[idx], y0 = b0[idx], y1 = b1[idx];
-        MacAcc s0, s1, s2;
-        s0.mac(x0, y0);
-        s1.mac(x0, y1);
-        s1.mac(x1, y0);
-        s2.mac(x1, y1);
-        d0[idx] = barrett128(s0.value(), mu1, mu0, q);
-        d1[idx] = barrett128(s1.value(), mu1, mu0, q);
-        const uint64_t r = barrett128(s2.value(), mu1, mu0, q);
-        d2[idx] = r;
-        return r;
+        MacAcc s2;
+        s2.mac(a1[idx], b1[idx]);
+        return barrett128(s2.value(), mu1, mu0, q);
     }
 };
 
-// HRotate automorphism as the prologue of the INTT of sigma_g(a1): the
-// permuted residue is stored (the inner product needs it in the NTT domain)
-// and enters the transform.
+// HRotate: sigma_g(a1) as the prologue of its INTT.
 struct GatherPro {
     const uint64_t *in;  // limb i of a1
-    uint64_t *dst;       // limb i of sigma_g(a1)
     uint32_t galois, log_n;
     __device__ __forceinline__ uint64_t operator()(size_t idx) const {
-        const uint64_t v = in[galois_src((uint32_t)idx, galois, log_n)];
-        dst[idx] = v;
-        return v;
+        return in[galois_src((uint32_t)idx, galois, log_n)];
     }
 };
 

@@ -104,6 +104,23 @@ struct rf_ctx {
 
 namespace rf {
 
+// What the inner product adds on the Q-limbs when the ModDown tail that follows
+// is reduced to out = ip' - NTT(conv) P^-1 (the fused two-pass path):
+// ip'[c][m] = ip[c][m] P^-1 + add_c[m].  pinv null: the plain inner product.
+struct IpFold {
+    const uint64_t *pinv = nullptr;  // pairs (P^-1 mod q_i, companion)
+    // Where the digit's own residue d[m] and the addends come from:
+    //   0: d and add0/add1 (nullable) as given;
+    //   1 (HMult+Relin): a, b = [2][nl][N] ciphertexts in the NTT domain:
+    //      d = a1 b1, add0 = a0 b0, add1 = a0 b1 + a1 b0 (the tensor), computed here;
+    //   2 (HRotate): a = the input ciphertext: d = sigma_g(a1), add0 = sigma_g(a0)
+    //      (g = galois), gathered here; no add1.
+    uint32_t mode = 0;
+    const uint64_t *add0 = nullptr, *add1 = nullptr;
+    const uint64_t *a = nullptr, *b = nullptr;
+    uint32_t galois = 0;
+};
+
 // Index map of sigma_g in the NTT domain (output k holds a(psi^(2 brv(k) + 1))):
 // sigma_g(a)[k] = a[k'] with 2 brv(k') + 1 = (2 brv(k) + 1) g mod 2N.
 __device__ __forceinline__ uint32_t galois_src(uint32_t k, uint32_t galois, uint32_t log_n) {
@@ -159,11 +176,11 @@ int launch_ntt_fwd_moddown(const rf_ctx *c, uint64_t *conv, const uint64_t *ip, 
                            hipStream_t s);
 // INTT of the polynomial to key-switch (two-pass ring degrees only), with the
 // step that produces it as the prologue of its first pass, into dc [nl][N]
-// (coefficient domain); the polynomial itself is also stored into d [nl][N]:
-//   galois == 0 (HMult): the tensor of a, b ([2][nl][N]); d0, d1 into d01 [2][nl][N], d2 into d;
-//   galois != 0 (HRotate): sigma_g of a's polynomial 1 into d.
-int launch_intt_first(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *d01, uint64_t *d,
-                      uint64_t *dc, uint32_t galois, uint32_t nl, hipStream_t s);
+// (coefficient domain):
+//   galois == 0 (HMult): d2 = a1 b1 of a, b ([2][nl][N]);
+//   galois != 0 (HRotate): sigma_g of a's polynomial 1.
+int launch_intt_first(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *dc, uint32_t galois,
+                      uint32_t nl, hipStream_t s);
 // Rescale / modulus switch after the INTT of the last limb (last = [2][N]),
 // two-pass ring degrees only: the first forward pass lifts the last limb into
 // each remaining prime in its prologue (into lift [2][nl-1][N]; KEEP_T for BGV),
@@ -174,12 +191,11 @@ int launch_tensor(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_
                   uint64_t *d2, uint32_t nl, hipStream_t s);
 int launch_modup_bconv(const rf_ctx *c, const uint64_t *x, uint64_t *ext, uint32_t nl,
                        hipStream_t s);
-// fold: the Q-limbs leave as ip P^-1 + add_c (add_0 through sigma_g when galois0 != 0),
-// for launch_ntt_fwd_moddown.
+// fold (non-null): the Q-limbs leave as ip P^-1 + add_c with the sources fold
+// names (its pinv is filled in here), for launch_ntt_fwd_moddown.
 int launch_inner_product(const rf_ctx *c, const uint64_t *d_ntt, const uint64_t *ext,
                          const uint64_t *evk, uint64_t *ip, uint32_t nl, hipStream_t s,
-                         const uint64_t *add0 = nullptr, const uint64_t *add1 = nullptr, uint32_t galois0 = 0,
-                         bool fold = false);
+                         const IpFold *fold = nullptr);
 int launch_moddown_bconv(const rf_ctx *c, const uint64_t *ip, uint64_t *conv, uint32_t nl,
                          hipStream_t s);  // uses the t-preserving table for BGV contexts
 int launch_moddown_tail(const rf_ctx *c, const uint64_t *ip, const uint64_t *conv,
