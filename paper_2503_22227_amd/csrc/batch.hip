@@ -53,7 +53,8 @@ struct KsJob {
 
 struct NttJob {
     NttBatch b;
-    const TwPair *tw_all;
+    const TwPair *tw_all;   // natural table (column passes)
+    const TwPair *tw_rows;  // row-pass layout (row passes)
     const PrimeConst *pcs;
     uint32_t log_n;
     uint32_t unit_begin;
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
         const uint64_t *in = base_in + (size_t)poly * in_stride + ((size_t)li << J.log_n);
         uint64_t *out = J.b.out + (size_t)poly * J.b.out_poly_stride + ((size_t)li << J.log_n);
         const PrimeConst pc = J.pcs[g];
-        const TwPair *tw = J.tw_all + ((size_t)g << J.log_n);
+        const TwPair *tw = (COLS ? J.tw_all : J.tw_rows) + ((size_t)g << J.log_n);
         if constexpr (TAIL) {
             // limb li of polynomial poly of conv [2][nl][N]: ModDown tail into out
             const size_t lo = ((size_t)poly * (J.nl + J.K) + li) << J.log_n;
@@ -339,6 +340,7 @@ extern "C" int rf_batch_create(const rf_batch_item *items, uint32_t n, void *ws,
         for (int k = 0; k < 4; ++k) {
             ntt[k][i].b = bs[k];
             ntt[k][i].tw_all = (k == 1 || k == 3) ? c->d_tw_fwd : c->d_tw_inv;
+            ntt[k][i].tw_rows = (k == 1 || k == 3) ? c->d_tw_fwd_rows : c->d_tw_inv_rows;
             ntt[k][i].pcs = c->d_pc;
             ntt[k][i].log_n = c->log_n;
             ntt[k][i].unit_begin = J.unit_begin[first_stage[k]];

@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "ntt_dev.hpp"
 #include "rf_internal.hpp"
 
 namespace {
@@ -104,6 +105,8 @@ static void free_tables(rf_ctx *c) {
     (void)hipFree(c->d_pc_md);
     (void)hipFree(c->d_tw_fwd);
     (void)hipFree(c->d_tw_inv);
+    (void)hipFree(c->d_tw_fwd_rows);
+    (void)hipFree(c->d_tw_inv_rows);
     (void)hipFree(c->d_modup);
     (void)hipFree(c->d_moddown);
     (void)hipFree(c->d_moddown_t);
@@ -178,6 +181,26 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
     // per-prime constants and twiddle tables
     std::vector<PrimeConst> pc(NP);
     std::vector<TwPair> twf((size_t)NP * N), twi((size_t)NP * N);
+    std::vector<TwPair> twrf, twri;
+    if (c->log_n > 12) {
+        // the row-pass layout must be a permutation of each stage block
+        const int A = ntt_split_a((int)c->log_n), B = (int)c->log_n - A;
+        for (int dir = 0; dir < 2; ++dir) {
+            std::vector<uint8_t> seen(N, 0);
+            for (int s = 0; s < B; ++s)
+                for (uint32_t r = 0; r < (1u << A); ++r)
+                    for (uint32_t j = 0; j < (1u << s); ++j) {
+                        const uint32_t k = row_tw_index(A, B, dir == 0, r, s, j);
+                        if (k < (1u << (A + s)) || k >= (2u << (A + s)) || seen[k]) {
+                            delete c;
+                            return fail(RF_EINVAL, "internal: row twiddle layout is not a permutation");
+                        }
+                        seen[k] = 1;
+                    }
+        }
+        twrf.assign((size_t)NP * N, TwPair{0, 0});
+        twri.assign((size_t)NP * N, TwPair{0, 0});
+    }
     std::vector<uint64_t> pw(N), pwi(N);
     for (uint32_t g = 0; g < NP; ++g) {
         uint64_t q = c->primes[g];
@@ -205,6 +228,17 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
             TwPair &b = twi[(size_t)g * N + k];
             b.w = pwi[r];
             b.wp = shoup_companion(b.w, q);
+        }
+        if (c->log_n > 12) {
+            // row-pass layout: entry (r, s, j) of the natural table moves to row_tw_index
+            const int A = ntt_split_a((int)c->log_n), B = (int)c->log_n - A;
+            for (int s = 0; s < B; ++s)
+                for (uint32_t r = 0; r < (1u << A); ++r)
+                    for (uint32_t j = 0; j < (1u << s); ++j) {
+                        const size_t nat = ((size_t)1 << (A + s)) + ((size_t)r << s) + j;
+                        twrf[(size_t)g * N + row_tw_index(A, B, true, r, s, j)] = twf[(size_t)g * N + nat];
+                        twri[(size_t)g * N + row_tw_index(A, B, false, r, s, j)] = twi[(size_t)g * N + nat];
+                    }
         }
         uint64_t wl = mulmod_h(twi[(size_t)g * N + 1].w, ninv, q);
         pc[g].wlast = wl;
@@ -447,7 +481,8 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
 
     int rc = RF_OK;
     if ((!bz.empty() && ((rc = upload(&c->d_behz, bz)) || (rc = upload(&c->d_pmap_qb, pmqb)))) ||
-        (rc = upload(&c->d_pc, pc)) || (rc = upload(&c->d_pc_md, pc_md)) || (rc = upload(&c->d_tw_fwd, twf)) || (rc = upload(&c->d_tw_inv, twi)) ||
+        (rc = upload(&c->d_pc, pc)) || (rc = upload(&c->d_pc_md, pc_md)) ||
+        (!twrf.empty() && ((rc = upload(&c->d_tw_fwd_rows, twrf)) || (rc = upload(&c->d_tw_inv_rows, twri)))) || (rc = upload(&c->d_tw_fwd, twf)) || (rc = upload(&c->d_tw_inv, twi)) ||
         (rc = upload(&c->d_modup, mu)) || (rc = upload(&c->d_moddown, md)) ||
         (!mdt.empty() && (rc = upload(&c->d_moddown_t, mdt))) || (rc = upload(&c->d_rescale, rs)) ||
         (rc = upload(&c->d_pmaps, pm))) {

@@ -206,11 +206,11 @@ static void launch_two_pass(const rf_ctx *c, const NttBatch &b, bool forward, hi
             hipLaunchKernelGGL((ntt_cols_kernel<A, B, true>), grid_cols, block, 0, s, b, c->d_tw_fwd, pcs);
         }
         ProfScope p("ntt_fwd_rows", s);
-        hipLaunchKernelGGL((ntt_rows_kernel<A, B, true>), grid_rows, block, 0, s, b2, c->d_tw_fwd, pcs);
+        hipLaunchKernelGGL((ntt_rows_kernel<A, B, true>), grid_rows, block, 0, s, b2, c->d_tw_fwd_rows, pcs);
     } else {
         {
             ProfScope p("ntt_inv_rows", s);
-            hipLaunchKernelGGL((ntt_rows_kernel<A, B, false>), grid_rows, block, 0, s, b, c->d_tw_inv, pcs);
+            hipLaunchKernelGGL((ntt_rows_kernel<A, B, false>), grid_rows, block, 0, s, b, c->d_tw_inv_rows, pcs);
         }
         ProfScope p("ntt_inv_cols", s);
         hipLaunchKernelGGL((ntt_cols_kernel<A, B, false>), grid_cols, block, 0, s, b2, c->d_tw_inv, pcs);
@@ -239,7 +239,7 @@ int launch_ntt_fwd_moddown(const rf_ctx *c, uint64_t *conv, const uint64_t *ip, 
             }                                                                                                    \
         }                                                                                                        \
         ProfScope p("ntt_fwd_rows_moddown", s);                                                                  \
-        hipLaunchKernelGGL((ntt_rows_moddown_kernel<A, B>), g, dim3(kThreads), 0, s, conv, c->d_tw_fwd, c->d_pc, ip, \
+        hipLaunchKernelGGL((ntt_rows_moddown_kernel<A, B>), g, dim3(kThreads), 0, s, conv, c->d_tw_fwd_rows, c->d_pc, ip, \
                            out, pinv, nl, c->K);                                                                 \
     }
     switch (c->log_n) {
@@ -273,7 +273,7 @@ int launch_ntt_fwd_rescale(const rf_ctx *c, const uint64_t *last, uint64_t *lift
                                    c->d_tw_fwd, c->d_pc, c->d_rescale, nl, c->L);                                \
         }                                                                                                        \
         ProfScope p("ntt_fwd_rows_rescale", s);                                                                  \
-        hipLaunchKernelGGL((ntt_rows_rescale_kernel<A, B>), g, dim3(kThreads), 0, s, lift, c->d_tw_fwd, c->d_pc, in, \
+        hipLaunchKernelGGL((ntt_rows_rescale_kernel<A, B>), g, dim3(kThreads), 0, s, lift, c->d_tw_fwd_rows, c->d_pc, in, \
                            out, c->d_rescale, nl, c->L);                                                         \
     }
     switch (c->log_n) {
@@ -298,11 +298,11 @@ int launch_intt_first(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uin
         if (galois) {                                                                                            \
             ProfScope p("ntt_inv_rows_gather", s);                                                               \
             hipLaunchKernelGGL((ntt_inv_rows_gather_kernel<A, B>), gr, dim3(kThreads), 0, s, a + (size_t)nl * N, dc, \
-                               galois, c->d_tw_inv, c->d_pc);                                                    \
+                               galois, c->d_tw_inv_rows, c->d_pc);                                                    \
         } else {                                                                                                 \
             ProfScope p("ntt_inv_rows_tensor", s);                                                               \
             hipLaunchKernelGGL((ntt_inv_rows_tensor_kernel<A, B>), gr, dim3(kThreads), 0, s, a, b, dc,           \
-                               c->d_tw_inv, c->d_pc, nl);                                                        \
+                               c->d_tw_inv_rows, c->d_pc, nl);                                                        \
         }                                                                                                        \
         NttBatch bc{dc, dc, 0, 0, nl, 1, 0, nullptr};                                                            \
         ProfScope p("ntt_inv_cols", s);                                                                          \

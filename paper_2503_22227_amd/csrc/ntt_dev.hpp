@@ -17,12 +17,11 @@
 //   * a workgroup owns a 4096-residue tile (32 KiB + padding): 16 columns x
 //     256 rows, or 16 rows x 256, so every global access of a wavefront is a
 //     run of whole 128-byte lines;
-//   * inside the tile every thread holds kElems residues in registers and
-//     performs up to log2(kElems) butterfly stages on them (a radix-kElems
-//     round), then the tile is exchanged through LDS for the next round.
-//     kElems = 16 (256-thread workgroups, radix-16 rounds) is the default:
-//     on MI355X, 8 (512 threads, radix-8 rounds) is no faster on small
-//     launches and slower on large ones;
+//   * inside the tile every thread holds kElems = 16 residues in registers and
+//     performs up to 4 butterfly stages on them (a radix-16 round), then the
+//     tile is exchanged through LDS for the next round, so a pass of up to 8
+//     stages takes two rounds (256-thread workgroups; 8 residues per thread
+//     with radix-8 rounds was measured no faster on MI355X);
 //   * values stay in Harvey's lazy ranges ([0, 4q) forward, [0, 2q) inverse)
 //     between stages and passes and are reduced to [0, q) at the last store.
 // N <= 4096 is done in one pass by one workgroup per limb.
@@ -35,13 +34,36 @@
 namespace rf {
 
 constexpr int kTile = 4096;
-#ifndef RF_NTT_ELEMS
-#define RF_NTT_ELEMS 16
-#endif
-constexpr int kElems = RF_NTT_ELEMS;               // residues per thread
-constexpr int kElemsLog = kElems == 16 ? 4 : 3;    // stages per round
+constexpr int kElems = 16;                         // residues per thread
+constexpr int kElemsLog = 4;                       // stages per round
 constexpr int kThreads = kTile / kElems;           // threads per workgroup
-static_assert(kElems == 8 || kElems == 16, "8 or 16 residues per thread");
+
+// Twiddle layout of the row passes.  A row pass of N = 2^(A+B) works on 2^A rows
+// of S = 2^B residues, a tile of U = 4096 / S consecutive rows per workgroup,
+// T = S / kElems threads per row.  At local stage s (0..B-1) row r uses the
+// twiddles j < 2^s of psi^(+-brv(2^(A+s) + r 2^s + j)).  In the round whose
+// butterflies only depend on e (the first forward round, the last inverse
+// round) j is the same for the T threads of a row; in the other round thread t
+// of a row uses j = t R + k, k < R = kElems 2^s / S.  The row table stores them
+// so that one wave instruction (consecutive rows u of a tile, then threads t)
+// reads consecutive entries:
+//   uniform stage: 2^(A+s) + (r_hi 2^s + j) U + u
+//   ranged stage:  2^(A+s) + ((r_hi R + k) T + t) U + u,   r = r_hi U + u.
+// The entries below 2^A are unused.  A ranged stage is, forward: s >= kElemsLog
+// (the stages after the first round); inverse: s >= B - kElemsLog (the stages
+// of the first round).
+__host__ __device__ constexpr bool row_tw_ranged(int B, bool fwd, int s) {
+    return fwd ? s >= kElemsLog : s >= B - kElemsLog;
+}
+
+__host__ __device__ inline uint32_t row_tw_index(int A, int B, bool fwd, uint32_t r, int s, uint32_t j) {
+    const uint32_t U = (uint32_t)kTile >> B, T = (1u << B) / kElems;
+    const uint32_t r_hi = r / U, u = r % U;
+    if (!row_tw_ranged(B, fwd, s)) return (1u << (A + s)) + ((r_hi << s) + j) * U + u;
+    const uint32_t R = ((uint32_t)kElems << s) >> B;
+    const uint32_t t = j / R, k = j % R;
+    return (1u << (A + s)) + ((r_hi * R + k) * T + t) * U + u;
+}
 
 __device__ __forceinline__ void ct_bfly(uint64_t &x, uint64_t &y, uint64_t w, uint64_t wp, uint64_t q,
                                         uint64_t q2) {
@@ -67,11 +89,28 @@ __device__ __forceinline__ void gs_bfly_last(uint64_t &x, uint64_t &y, const Pri
     y = shoup_lazy(d, pc.wlast, pc.wlast_p, pc.q);
 }
 
+// Table index of twiddle j of local stage s: the natural index (tw_base << s) + j
+// (column passes, ROW_A == 0) or the row-pass layout above, with tw_base = 2^A + r
+// and t the thread's index within its row.
+template <int S_LOG, int ROW_A, bool FWD>
+__device__ __forceinline__ uint32_t row_or_natural(uint32_t tw_base, int s, int t, uint32_t j) {
+    if constexpr (ROW_A == 0) {
+        return (tw_base << s) + j;
+    } else {
+        constexpr uint32_t U = (uint32_t)kTile >> S_LOG, T = (1u << S_LOG) / kElems;
+        const uint32_t r = tw_base - (1u << ROW_A);
+        const uint32_t r_hi = r / U, uu = r % U;
+        if (!row_tw_ranged(S_LOG, FWD, s)) return (1u << (ROW_A + s)) + ((r_hi << s) + j) * U + uu;
+        const uint32_t R = ((uint32_t)kElems << s) >> S_LOG;
+        return (1u << (ROW_A + s)) + ((r_hi * R + (j - (uint32_t)t * R)) * T + (uint32_t)t) * U + uu;
+    }
+}
+
 // One round of C butterfly stages of a size-2^S_LOG sub-transform held in LDS
 // (element p of sub-transform u at lds[p * ldu + u]).  Thread t of the
 // sub-transform owns kElems residues: kElems / 2^C groups of 2^C residues spaced by
 // the round's smallest distance 2^DL.
-template <int S_LOG, int ST0, int C, bool FWD, bool SCALE_LAST>
+template <int S_LOG, int ST0, int C, bool FWD, bool SCALE_LAST, int ROW_A>
 __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, uint32_t tw_base,
                                           const TwPair *__restrict__ tw, const PrimeConst &pc) {
     constexpr int G = 1 << C;
@@ -97,9 +136,9 @@ __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, 
                     if (e & h) continue;
                     // in the first round every group starts below 2^DL, so the twiddle
                     // index depends on e only (uniform across the sub-transform)
-                    const uint32_t idx = ST0 == 0 ? (tw_base << st) + (uint32_t)(e >> (C - c))
-                                                  : (tw_base << st) + (uint32_t)((base + (e << DL)) >> (S_LOG - st));
-                    const TwPair w = tw[idx];
+                    const uint32_t j = ST0 == 0 ? (uint32_t)(e >> (C - c))
+                                                : (uint32_t)((base + (e << DL)) >> (S_LOG - st));
+                    const TwPair w = tw[row_or_natural<S_LOG, ROW_A, true>(tw_base, st, t, j)];
                     ct_bfly(v[e], v[e + h], w.w, w.wp, q, q2);
                 }
             }
@@ -117,7 +156,7 @@ __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, 
                         // in the last round every group starts below 2^DL: index from e only
                         const uint32_t lo_part = ST0 + C == S_LOG ? (uint32_t)(e >> (c + 1))
                                                                   : (uint32_t)((base + (e << DL)) >> (us + 1));
-                        const TwPair w = tw[(tw_base << (S_LOG - us - 1)) + lo_part];
+                        const TwPair w = tw[row_or_natural<S_LOG, ROW_A, false>(tw_base, S_LOG - us - 1, t, lo_part)];
                         gs_bfly(v[e], v[e + h], w.w, w.wp, q, q2);
                     }
                 }
@@ -130,21 +169,24 @@ __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, 
 
 // Rounds of a size-2^S_LOG sub-transform from stage ST0 on: radix-kElems rounds,
 // the last one shorter when kElemsLog does not divide S_LOG.
-template <int S_LOG, int ST0, bool FWD, bool SCALE_LAST>
+template <int S_LOG, int ST0, bool FWD, bool SCALE_LAST, int ROW_A>
 __device__ __forceinline__ void ntt_rounds_from(uint64_t *lds, int ldu, int u, int t, uint32_t tw_base,
                                                 const TwPair *__restrict__ tw, const PrimeConst &pc) {
     constexpr int C = (S_LOG - ST0) < kElemsLog ? (S_LOG - ST0) : kElemsLog;
     constexpr bool LAST = ST0 + C == S_LOG;
-    ntt_round<S_LOG, ST0, C, FWD, SCALE_LAST && LAST>(lds, ldu, u, t, tw_base, tw, pc);
+    ntt_round<S_LOG, ST0, C, FWD, SCALE_LAST && LAST, ROW_A>(lds, ldu, u, t, tw_base, tw, pc);
     __syncthreads();
-    if constexpr (!LAST) ntt_rounds_from<S_LOG, ST0 + C, FWD, SCALE_LAST>(lds, ldu, u, t, tw_base, tw, pc);
+    if constexpr (!LAST) ntt_rounds_from<S_LOG, ST0 + C, FWD, SCALE_LAST, ROW_A>(lds, ldu, u, t, tw_base, tw, pc);
 }
 
-template <int S_LOG, bool FWD, bool SCALE_LAST>
+// ROW_A: 0 for the natural twiddle table; A for a row pass reading the row table
+// (which needs exactly two rounds: S_LOG in (kElemsLog, 2 kElemsLog]).
+template <int S_LOG, bool FWD, bool SCALE_LAST, int ROW_A = 0>
 __device__ __forceinline__ void ntt_rounds(uint64_t *lds, int ldu, int u, int t, uint32_t tw_base,
                                            const TwPair *__restrict__ tw, const PrimeConst &pc) {
     static_assert(S_LOG >= 5 && S_LOG <= 12, "sub-transform size");
-    ntt_rounds_from<S_LOG, 0, FWD, SCALE_LAST>(lds, ldu, u, t, tw_base, tw, pc);
+    static_assert(ROW_A == 0 || (S_LOG > kElemsLog && S_LOG <= 2 * kElemsLog), "row table: two rounds");
+    ntt_rounds_from<S_LOG, 0, FWD, SCALE_LAST, ROW_A>(lds, ldu, u, t, tw_base, tw, pc);
 }
 
 // Column pass unit: sub-transforms are columns (2^A rows, stride 2^B), tile
@@ -267,7 +309,7 @@ __device__ __forceinline__ void ntt_rows_unit_pe(uint64_t *lds, const Pro &pro, 
     }
     __syncthreads();
     const int u = threadIdx.x % U, t = threadIdx.x / U;
-    ntt_rounds<B, FWD, false>(lds, LDU, u, t, (1u << A) + row0 + u, tw, pc);
+    ntt_rounds<B, FWD, false, A>(lds, LDU, u, t, (1u << A) + row0 + u, tw, pc);
     const uint64_t q2 = 2 * pc.q;
 #pragma unroll
     for (int r = 0; r < kTile / kThreads; ++r) {

@@ -89,6 +89,8 @@ struct rf_ctx {
                                            // folded into the last inverse stage of every special prime
     rf::TwPair *d_tw_fwd = nullptr;        // [L+K][N]: psi^brv(k)
     rf::TwPair *d_tw_inv = nullptr;        // [L+K][N]: psi^-brv(k)
+    rf::TwPair *d_tw_fwd_rows = nullptr;   // the same twiddles in the row-pass layout (ntt_dev.hpp)
+    rf::TwPair *d_tw_inv_rows = nullptr;
     uint64_t *d_modup = nullptr;           // ModUp base-conversion constants, see context.hip
     uint64_t *d_moddown = nullptr;         // ModDown constants
     uint64_t *d_moddown_t = nullptr;       // ModDown constants keeping the message mod t (BGV)
