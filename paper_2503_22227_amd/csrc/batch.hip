@@ -1,7 +1,13 @@
 // Batched HMult+Relin over many ciphertexts of different ring degrees and
-// levels: every step of the chain (tensor, INTT, ModUp conversion, NTT, inner
-// product, INTT of the P-limbs, ModDown conversion, NTT, tail) is ONE launch
-// of a persistent kernel that walks the work units of all items.
+// levels: every step of the chain is ONE launch of a persistent kernel that
+// walks the work units of all items.  The chain is the single-operation one:
+// INTT of d2 = a1 b1 (formed in the first pass), ModUp conversion, NTT, inner
+// product (which forms d0, d1 and the own-digit d2 residues itself and leaves
+// its Q-limbs as ip P^-1 + d_c), INTT of the P-limbs (with the conversion's
+// input factor in its last stage), NTT of the ModDown conversion (computed in
+// the first pass, the tail out = ip' - NTT(conv) P^-1 in the last).  The
+// tensor, ModDown-conversion and tail steps keep their stage numbers with no
+// work units.
 //
 // Work units: an NTT pass unit is one 4096-residue tile of one limb
 // (N / 4096 tiles per limb); an element-wise unit is 256 coefficients of one
@@ -58,11 +64,14 @@ struct NttJob {
     const PrimeConst *pcs;
     uint32_t log_n;
     uint32_t unit_begin;
-    // ModDown tail applied by the last pass of NTT(conv): out = (ip - .) P^-1 + out
+    // prologue of the INTT of d2: the item's ciphertexts a, b ([2][nl][N])
+    const uint64_t *ct_a, *ct_b;
+    // ModDown in NTT(conv): conversion from the P-limbs of ip in the first pass,
+    // tail out = ip' - NTT(conv) P^-1 in the last
     const uint64_t *ip;
     uint64_t *out;
-    const uint64_t *pinv;
-    uint32_t nl, K;
+    const uint64_t *pinv, *md_cross, *md_negp;
+    uint32_t nl, K, L;
 };
 
 template <typename J>
@@ -107,7 +116,12 @@ __global__ __launch_bounds__(kEw) void ks_batched_kernel(const KsJob *__restrict
             modup_bconv_unit(J.d_coeff, J.ext, J.pcs, J.modup_tab, J.modup_stride, J.log_n, J.nl, J.L, J.K, J.alpha,
                              gx, gy);
         } else if constexpr (STAGE == kInnerProduct) {
-            inner_product_unit(J.d2, J.ext, J.evk, J.ip, J.pcs, J.log_n, J.nl, J.L, J.K, J.alpha, gx, gy);
+            IpFold f;
+            f.pinv = J.pinv;
+            f.mode = 1;
+            f.a = J.a;
+            f.b = J.b;
+            inner_product_unit(J.d2, J.ext, J.evk, J.ip, J.pcs, J.log_n, J.nl, J.L, J.K, J.alpha, gx, gy, f);
         } else if constexpr (STAGE == kModdownConv) {
             moddown_bconv_unit(J.ip, J.conv, J.pcs, J.moddown_tab, J.log_n, J.nl, J.L, J.K, gx, gy);
         } else if constexpr (STAGE == kTail) {
@@ -117,63 +131,105 @@ __global__ __launch_bounds__(kEw) void ks_batched_kernel(const KsJob *__restrict
     }
 }
 
-// One pass of a batched (I)NTT: FIRST = the pass that reads b.in (forward:
-// columns; inverse: rows); the second pass works in place on b.out.  TAIL (the
-// forward row pass of NTT(conv)) writes the ModDown result instead.
-template <bool FWD, bool FIRST, bool TAIL = false>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesCols))) void ntt_batched_kernel(const NttJob *__restrict__ jobs, uint32_t njobs,
-                                                               uint32_t total, uint32_t per_wg) {
-    __shared__ uint64_t lds[kNttLdsWords];
+// First pass of NTT(conv) of target li of polynomial poly with the ModDown
+// conversion from the item's P-limbs as its prologue (KP: see ModdownPro).
+template <int A, int B, int KP>
+__device__ __forceinline__ void moddown_cols_pass(uint64_t *lds, const NttJob &J, uint32_t poly, uint32_t li,
+                                                  uint64_t *out, const TwPair *tw, const PrimeConst &pc, uint32_t tile) {
+    constexpr int LOGN = A + B;
+    ModdownPro<KP> pro;
+    pro.src = J.ip + (((size_t)poly * (J.nl + J.K) + J.nl) << LOGN);
+    pro.stride = (size_t)1 << LOGN;
+    pro.K = J.K;
+#pragma unroll
+    for (int a = 0; a < KP; ++a) {
+        pro.half[a] = a < (int)J.K ? J.pcs[J.L + a].q >> 1 : 0;
+        pro.cross[a] = a < (int)J.K ? J.md_cross[(size_t)li * J.K + a] : 0;
+    }
+    pro.negp = J.md_negp[li];
+    pro.q = pc.q;
+    pro.r64 = pc.r64;
+    pro.r64_p = pc.r64_p;
+    pro.one_p = pc.one_p;
+    ntt_cols_unit_pro<A, B, true>(lds, out, tw, pc, tile, pro);
+}
+
+// One pass of a batched (I)NTT over the items of one ring degree 2^(A+B) (the
+// plan launches each NTT step once per ring degree present: one transform
+// shape per kernel keeps the unrolled rounds free of register spills).
+// FIRST = the pass that reads b.in (forward: columns; inverse: rows); the
+// second pass works in place on b.out.  TAIL (the forward row pass of
+// NTT(conv)) writes the ModDown result instead.  PRO: the first pass computes
+// its input: 1 = d2 from a, b (INTT of d2), 2 = the ModDown conversion (NTT of
+// conv).  Units [unit0, unit0 + total) of the step; jobs = the items of the
+// ring degree, whose unit_begin values are absolute.
+template <int A, int B, bool FWD, bool FIRST, bool TAIL, int PRO>
+__device__ __forceinline__ void ntt_batched_unit(uint64_t *lds, const NttJob &J, uint32_t u) {
+    constexpr int LOGN = A + B;
     constexpr bool COLS = FWD == FIRST;
+    const uint32_t local = u - J.unit_begin;
+    constexpr uint32_t tshift = LOGN - 12;  // N / 4096 tiles per limb
+    const uint32_t limb = local >> tshift, tile = local & ((1u << tshift) - 1);
+    const uint32_t poly = limb / J.b.per_poly, li = limb - poly * J.b.per_poly;
+    const uint32_t g = J.b.pmap ? (uint32_t)J.b.pmap[li] : J.b.prime_base + li;
+    const uint64_t *base_in = FIRST ? J.b.in : J.b.out;
+    const uint64_t in_stride = FIRST ? J.b.in_poly_stride : J.b.out_poly_stride;
+    const uint64_t *in = base_in + (size_t)poly * in_stride + ((size_t)li << LOGN);
+    uint64_t *out = J.b.out + (size_t)poly * J.b.out_poly_stride + ((size_t)li << LOGN);
+    const PrimeConst pc = J.pcs[g];
+    const TwPair *tw = (COLS ? J.tw_all : J.tw_rows) + ((size_t)g << LOGN);
+    if constexpr (PRO == 1) {
+        // first pass of INTT(d2): d2 = a1 b1 of limb li
+        const size_t poly1 = ((size_t)J.nl + li) << LOGN;
+        const TensorPro pro{J.ct_a + poly1, J.ct_b + poly1, pc.q, pc.mu1, pc.mu0};
+        ntt_rows_unit_pe<A, B, false>(lds, pro, tw, pc, tile, StoreEpi{out});
+    } else if constexpr (PRO == 2) {
+        // first pass of NTT(conv): ModDown conversion of target li of polynomial poly
+        // (specialised for 4 special primes, the generic variant otherwise)
+        if (J.K == 4) moddown_cols_pass<A, B, 4>(lds, J, poly, li, out, tw, pc, tile);
+        else moddown_cols_pass<A, B, 8>(lds, J, poly, li, out, tw, pc, tile);
+    } else if constexpr (TAIL) {
+        // limb li of polynomial poly of conv [2][nl][N]: ModDown tail into out
+        const size_t lo = ((size_t)poly * (J.nl + J.K) + li) << LOGN;
+        const size_t oo = ((size_t)poly * J.nl + li) << LOGN;
+        const ModdownFoldEpi epi{J.ip + lo, J.out + oo, J.pinv[2 * li], J.pinv[2 * li + 1], pc.q};
+        ntt_rows_unit_epi<A, B, true>(lds, in, tw, pc, tile, epi);
+    } else if constexpr (COLS) {
+        ntt_cols_unit<A, B, FWD>(lds, in, out, tw, pc, tile);
+    } else {
+        ntt_rows_unit<A, B, FWD>(lds, in, out, tw, pc, tile);
+    }
+}
+
+// One pass of a batched (I)NTT over the items of one ring degree 2^(A+B) (the
+// plan launches each NTT step once per ring degree present: one transform
+// shape per kernel keeps the unrolled rounds free of register spills).
+// FIRST = the pass that reads b.in (forward: columns; inverse: rows); the
+// second pass works in place on b.out.  TAIL (the forward row pass of
+// NTT(conv)) writes the ModDown result instead.  PRO: the first pass computes
+// its input: 1 = d2 from a, b (INTT of d2), 2 = the ModDown conversion (NTT of
+// conv).  Units [unit0, unit0 + total) of the step; jobs = the items of the
+// ring degree, whose unit_begin values are absolute.  LOOP: workgroups walk
+// per_wg consecutive units; otherwise each takes one unit (per_wg == 1).
+template <int A, int B, bool FWD, bool FIRST, bool TAIL, int PRO, bool LOOP>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesCols))) void ntt_batched_kernel(
+    const NttJob *__restrict__ jobs, uint32_t njobs, uint32_t unit0, uint32_t total, uint32_t per_wg) {
+    constexpr bool COLS = FWD == FIRST;
+    __shared__ uint64_t lds[COLS ? (1 << A) * (kTile / (1 << A) + 1) : (1 << B) * (kTile / (1 << B) + 1)];
     static_assert(!TAIL || (FWD && !FIRST), "the tail follows the forward row pass");
-    const uint32_t u0 = blockIdx.x * per_wg;
-    const uint32_t u1 = min(total, u0 + per_wg);
-    if (u0 >= u1) return;
-    uint32_t j = find_job(jobs, njobs, u0, 0);
-    for (uint32_t u = u0; u < u1; ++u) {
-        while (j + 1 < njobs && jobs[j + 1].unit_begin <= u) ++j;
-        const NttJob &J = jobs[j];
-        const uint32_t local = u - J.unit_begin;
-        const uint32_t tshift = J.log_n - 12;  // N / 4096 tiles per limb
-        const uint32_t limb = local >> tshift, tile = local & ((1u << tshift) - 1);
-        const uint32_t poly = limb / J.b.per_poly, li = limb - poly * J.b.per_poly;
-        const uint32_t g = J.b.pmap ? (uint32_t)J.b.pmap[li] : J.b.prime_base + li;
-        const uint64_t *base_in = FIRST ? J.b.in : J.b.out;
-        const uint64_t in_stride = FIRST ? J.b.in_poly_stride : J.b.out_poly_stride;
-        const uint64_t *in = base_in + (size_t)poly * in_stride + ((size_t)li << J.log_n);
-        uint64_t *out = J.b.out + (size_t)poly * J.b.out_poly_stride + ((size_t)li << J.log_n);
-        const PrimeConst pc = J.pcs[g];
-        const TwPair *tw = (COLS ? J.tw_all : J.tw_rows) + ((size_t)g << J.log_n);
-        if constexpr (TAIL) {
-            // limb li of polynomial poly of conv [2][nl][N]: ModDown tail into out
-            const size_t lo = ((size_t)poly * (J.nl + J.K) + li) << J.log_n;
-            const size_t oo = ((size_t)poly * J.nl + li) << J.log_n;
-            const ModdownTailEpi epi{J.ip + lo, J.out + oo, J.out + oo, J.pinv[2 * li], J.pinv[2 * li + 1], pc.q};
-            switch (J.log_n) {
-                case 16: ntt_rows_unit_epi<8, 8, true>(lds, in, tw, pc, tile, epi); break;
-                case 15: ntt_rows_unit_epi<8, 7, true>(lds, in, tw, pc, tile, epi); break;
-                case 14: ntt_rows_unit_epi<7, 7, true>(lds, in, tw, pc, tile, epi); break;
-                default: ntt_rows_unit_epi<7, 6, true>(lds, in, tw, pc, tile, epi); break;
-            }
-            continue;
-        }
-        switch (J.log_n) {
-            case 16:
-                if constexpr (COLS) ntt_cols_unit<8, 8, FWD>(lds, in, out, tw, pc, tile);
-                else ntt_rows_unit<8, 8, FWD>(lds, in, out, tw, pc, tile);
-                break;
-            case 15:
-                if constexpr (COLS) ntt_cols_unit<8, 7, FWD>(lds, in, out, tw, pc, tile);
-                else ntt_rows_unit<8, 7, FWD>(lds, in, out, tw, pc, tile);
-                break;
-            case 14:
-                if constexpr (COLS) ntt_cols_unit<7, 7, FWD>(lds, in, out, tw, pc, tile);
-                else ntt_rows_unit<7, 7, FWD>(lds, in, out, tw, pc, tile);
-                break;
-            default:
-                if constexpr (COLS) ntt_cols_unit<7, 6, FWD>(lds, in, out, tw, pc, tile);
-                else ntt_rows_unit<7, 6, FWD>(lds, in, out, tw, pc, tile);
-                break;
+    static_assert(PRO == 0 || FIRST, "prologues belong to the first pass");
+    if constexpr (!LOOP) {
+        if (blockIdx.x >= total) return;
+        const uint32_t u = unit0 + blockIdx.x;
+        ntt_batched_unit<A, B, FWD, FIRST, TAIL, PRO>(lds, jobs[find_job(jobs, njobs, u, 0)], u);
+    } else {
+        const uint32_t u0 = unit0 + blockIdx.x * per_wg;
+        const uint32_t u1 = unit0 + min(total, (blockIdx.x + 1) * per_wg);
+        if (u0 >= u1) return;
+        uint32_t j = find_job(jobs, njobs, u0, 0);
+        for (uint32_t u = u0; u < u1; ++u) {
+            while (j + 1 < njobs && jobs[j + 1].unit_begin <= u) ++j;
+            ntt_batched_unit<A, B, FWD, FIRST, TAIL, PRO>(lds, jobs[j], u);
         }
     }
 }
@@ -185,6 +241,13 @@ using namespace rf;
 struct rf_batch {
     int device = 0;
     uint32_t n_items = 0;
+    // items sorted by ring degree; group: [job0, job1) with one log_n, and the
+    // first unit / unit count of every step inside the group
+    struct Group {
+        uint32_t log_n, job0, job1;
+        uint32_t unit0[kStages], units[kStages];
+    };
+    std::vector<Group> groups;
     KsJob *d_jobs = nullptr;
     NttJob *d_ntt[4] = {nullptr, nullptr, nullptr, nullptr};  // INTT d2, NTT ext, INTT P, NTT conv
     uint32_t total[kStages] = {0};
@@ -221,13 +284,13 @@ uint32_t stage_units(const rf_ctx *c, uint32_t nl, int stage) {
     const uint32_t chunks = c->n / kEw, tiles = c->n / kTile;
     const uint32_t dn = (nl + c->alpha - 1) / c->alpha;
     switch (stage) {
-        case kTensor: return nl * chunks;
+        case kTensor: return 0;  // formed by the INTT of d2 and the inner product
         case kInttD0: case kInttD1: return nl * tiles;
         case kModupConv: return dn * modup_chunks(nl, c->K) * chunks;
         case kNttExt0: case kNttExt1: return c->modup_levels[nl].ext_limbs * tiles;
         case kInnerProduct: return (nl + c->K) * chunks;
         case kInttP0: case kInttP1: return 2 * c->K * tiles;
-        case kModdownConv: return 2 * moddown_chunks(nl) * chunks;
+        case kModdownConv: return 0;  // computed in the first pass of NTT(conv)
         case kNttConv0: case kNttConv1: return 2 * nl * tiles;
         case kTail: return 0;  // applied by the last pass of NTT(conv)
     }
@@ -235,33 +298,71 @@ uint32_t stage_units(const rf_ctx *c, uint32_t nl, int stage) {
 }
 
 int enqueue(rf_batch *p, hipStream_t s, bool profile) {
-    static const char *names[kStages] = {"batch_tensor", "batch_ntt_inv_rows", "batch_ntt_inv_cols",
+    static const char *names[kStages] = {"batch_tensor", "batch_ntt_inv_rows_tensor", "batch_ntt_inv_cols",
                                          "batch_modup_bconv", "batch_ntt_fwd_cols", "batch_ntt_fwd_rows",
                                          "batch_inner_product", "batch_ntt_inv_rows", "batch_ntt_inv_cols",
-                                         "batch_moddown_bconv", "batch_ntt_fwd_cols", "batch_ntt_fwd_rows_moddown",
+                                         "batch_moddown_bconv", "batch_ntt_fwd_cols_moddown", "batch_ntt_fwd_rows_moddown",
                                          "batch_moddown_tail"};
     for (int st = 0; st < kStages; ++st) {
         const uint32_t total = p->total[st];
         if (total == 0) continue;
-        const uint32_t g = p->grid[st] == 0 ? total : std::min(total, p->grid[st]);
-        const uint32_t per = (total + g - 1) / g;
-        const uint32_t blocks = (total + per - 1) / per;
-        const uint32_t nj = p->n_items;
         ProfScope prof(profile ? names[st] : nullptr, s);
-        switch (st) {
-            case kTensor: hipLaunchKernelGGL(ks_batched_kernel<kTensor>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
-            case kModupConv: hipLaunchKernelGGL(ks_batched_kernel<kModupConv>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
-            case kInnerProduct: hipLaunchKernelGGL(ks_batched_kernel<kInnerProduct>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
-            case kModdownConv: hipLaunchKernelGGL(ks_batched_kernel<kModdownConv>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
-            case kTail: hipLaunchKernelGGL(ks_batched_kernel<kTail>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
-            case kInttD0: hipLaunchKernelGGL((ntt_batched_kernel<false, true>), blocks, kThreads, 0, s, p->d_ntt[0], nj, total, per); break;
-            case kInttD1: hipLaunchKernelGGL((ntt_batched_kernel<false, false>), blocks, kThreads, 0, s, p->d_ntt[0], nj, total, per); break;
-            case kNttExt0: hipLaunchKernelGGL((ntt_batched_kernel<true, true>), blocks, kThreads, 0, s, p->d_ntt[1], nj, total, per); break;
-            case kNttExt1: hipLaunchKernelGGL((ntt_batched_kernel<true, false>), blocks, kThreads, 0, s, p->d_ntt[1], nj, total, per); break;
-            case kInttP0: hipLaunchKernelGGL((ntt_batched_kernel<false, true>), blocks, kThreads, 0, s, p->d_ntt[2], nj, total, per); break;
-            case kInttP1: hipLaunchKernelGGL((ntt_batched_kernel<false, false>), blocks, kThreads, 0, s, p->d_ntt[2], nj, total, per); break;
-            case kNttConv0: hipLaunchKernelGGL((ntt_batched_kernel<true, true>), blocks, kThreads, 0, s, p->d_ntt[3], nj, total, per); break;
-            case kNttConv1: hipLaunchKernelGGL((ntt_batched_kernel<true, false, true>), blocks, kThreads, 0, s, p->d_ntt[3], nj, total, per); break;
+        const bool ntt_step = st != kTensor && st != kModupConv && st != kInnerProduct && st != kModdownConv &&
+                              st != kTail;
+        if (!ntt_step) {
+            const uint32_t g = p->grid[st] == 0 ? total : std::min(total, p->grid[st]);
+            const uint32_t per = (total + g - 1) / g;
+            const uint32_t blocks = (total + per - 1) / per;
+            const uint32_t nj = p->n_items;
+            switch (st) {
+                case kTensor: hipLaunchKernelGGL(ks_batched_kernel<kTensor>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
+                case kModupConv: hipLaunchKernelGGL(ks_batched_kernel<kModupConv>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
+                case kInnerProduct: hipLaunchKernelGGL(ks_batched_kernel<kInnerProduct>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
+                case kModdownConv: hipLaunchKernelGGL(ks_batched_kernel<kModdownConv>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
+                case kTail: hipLaunchKernelGGL(ks_batched_kernel<kTail>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
+            }
+        } else {
+            // one launch per ring degree; the step's workgroups are shared out in
+            // proportion to the units of each degree
+            for (const rf_batch::Group &G : p->groups) {
+                const uint32_t units = G.units[st];
+                if (units == 0) continue;
+                uint32_t g = units;
+                if (p->grid[st] != 0)
+                    g = std::max(1u, std::min(units, (uint32_t)(((uint64_t)p->grid[st] * units + total - 1) / total)));
+                const uint32_t per = (units + g - 1) / g;
+                const uint32_t blocks = (units + per - 1) / per;
+                const int k = st == kInttD0 || st == kInttD1 ? 0 : st == kNttExt0 || st == kNttExt1 ? 1
+                            : st == kInttP0 || st == kInttP1 ? 2 : 3;
+                const NttJob *jobs = p->d_ntt[k] + G.job0;
+                const uint32_t nj = G.job1 - G.job0, u0 = G.unit0[st];
+#define RF_BLK(A, B, FWD, FIRST, TAIL, PRO)                                                                      \
+    if (per == 1)                                                                                                \
+        hipLaunchKernelGGL((ntt_batched_kernel<A, B, FWD, FIRST, TAIL, PRO, false>), blocks, kThreads, 0, s, jobs, \
+                           nj, u0, units, per);                                                                  \
+    else                                                                                                         \
+        hipLaunchKernelGGL((ntt_batched_kernel<A, B, FWD, FIRST, TAIL, PRO, true>), blocks, kThreads, 0, s, jobs, \
+                           nj, u0, units, per)
+#define RF_BL(A, B)                                                                                              \
+    switch (st) {                                                                                                \
+        case kInttD0: RF_BLK(A, B, false, true, false, 1); break;                                                \
+        case kInttD1: RF_BLK(A, B, false, false, false, 0); break;                                               \
+        case kNttExt0: RF_BLK(A, B, true, true, false, 0); break;                                                \
+        case kNttExt1: RF_BLK(A, B, true, false, false, 0); break;                                               \
+        case kInttP0: RF_BLK(A, B, false, true, false, 0); break;                                                \
+        case kInttP1: RF_BLK(A, B, false, false, false, 0); break;                                               \
+        case kNttConv0: RF_BLK(A, B, true, true, false, 2); break;                                               \
+        case kNttConv1: RF_BLK(A, B, true, false, true, 0); break;                                               \
+    }
+                switch (G.log_n) {
+                    case 16: RF_BL(8, 8) break;
+                    case 15: RF_BL(8, 7) break;
+                    case 14: RF_BL(7, 7) break;
+                    default: RF_BL(7, 6) break;
+                }
+#undef RF_BL
+#undef RF_BLK
+            }
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail(RF_EHIP, std::string("batched launch: ") + hipGetErrorString(e));
@@ -299,9 +400,26 @@ extern "C" int rf_batch_create(const rf_batch_item *items, uint32_t n, void *ws,
     for (auto &v : ntt) v.resize(n);
     uint32_t acc[kStages] = {0};
     uint64_t *w = (uint64_t *)ws;
+    // items in order of ring degree (the NTT steps run one launch per degree)
+    std::vector<uint32_t> order(n);
+    for (uint32_t i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t x, uint32_t y) { return items[x].ctx->log_n < items[y].ctx->log_n; });
+    std::vector<rf_batch::Group> groups;
     for (uint32_t i = 0; i < n; ++i) {
-        const rf_batch_item &it = items[i];
+        const rf_batch_item &it = items[order[i]];
         const rf_ctx *c = it.ctx;
+        if (groups.empty() || groups.back().log_n != c->log_n) {
+            if (!groups.empty()) {
+                groups.back().job1 = i;
+                for (int st = 0; st < kStages; ++st) groups.back().units[st] = acc[st] - groups.back().unit0[st];
+            }
+            rf_batch::Group G{};
+            G.log_n = c->log_n;
+            G.job0 = i;
+            for (int st = 0; st < kStages; ++st) G.unit0[st] = acc[st];
+            groups.push_back(G);
+        }
         const uint32_t nl = it.n_limbs;
         const size_t N = c->n;
         const ModupLevel &lv = c->modup_levels[nl];
@@ -341,19 +459,28 @@ extern "C" int rf_batch_create(const rf_batch_item *items, uint32_t n, void *ws,
             ntt[k][i].b = bs[k];
             ntt[k][i].tw_all = (k == 1 || k == 3) ? c->d_tw_fwd : c->d_tw_inv;
             ntt[k][i].tw_rows = (k == 1 || k == 3) ? c->d_tw_fwd_rows : c->d_tw_inv_rows;
-            ntt[k][i].pcs = c->d_pc;
+            // the INTT of the P-limbs folds the ModDown input factor into its last stage
+            ntt[k][i].pcs = k == 2 ? c->d_pc_md : c->d_pc;
             ntt[k][i].log_n = c->log_n;
             ntt[k][i].unit_begin = J.unit_begin[first_stage[k]];
+            ntt[k][i].ct_a = it.a;
+            ntt[k][i].ct_b = it.b;
             ntt[k][i].ip = J.ip;
             ntt[k][i].out = J.out;
             ntt[k][i].pinv = J.pinv;
+            ntt[k][i].md_cross = J.moddown_tab + moddown_cross_off(c);
+            ntt[k][i].md_negp = J.moddown_tab + moddown_negp_off(c);
             ntt[k][i].nl = nl;
             ntt[k][i].K = c->K;
+            ntt[k][i].L = c->L;
         }
     }
+    groups.back().job1 = n;
+    for (int st = 0; st < kStages; ++st) groups.back().units[st] = acc[st] - groups.back().unit0[st];
     rf_batch *p = new rf_batch();
     p->device = items[0].ctx->device;
     p->n_items = n;
+    p->groups = groups;
     for (int st = 0; st < kStages; ++st) p->total[st] = acc[st];
     int prev = 0;
     (void)hipGetDevice(&prev);
