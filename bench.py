@@ -361,14 +361,14 @@ def _ntt_launch_model(name: str, L: int, K: int, alpha: int, n: int):
     limb, tw = 8.0 * n, 16.0 * n
     # per launch: (limbs transformed, residues-limbs moved, distinct primes with a row twiddle table)
     launches = {
-        "ntt_inv_rows_tensor": [(L, 4 * L + 3 * L + L, L)],          # a, b in; d0, d1, d2, row pass out
-        "ntt_inv_rows_gather": [(L, L + L + L, L)],                   # a1 gathered in; sigma(a1), row out
+        "ntt_inv_rows_tensor": [(L, 2 * L + L, L)],                   # a1, b1 in; row pass of d2 = a1 b1 out
+        "ntt_inv_rows_gather": [(L, L + L, L)],                       # c1 gathered in; row pass out
         "ntt_inv_rows": [(2 * K, 4 * K, K)] * 2 + [(2, 4, 1)],        # P-limbs (x2 ops), rescale's last limb
         "ntt_inv_cols": [(L, 2 * L, 0)] * 2 + [(2 * K, 4 * K, 0)] * 2 + [(2, 4, 0)],
         "ntt_fwd_cols": [(ext, 2 * ext, 0)] * 2,                      # ModUp NTT
         "ntt_fwd_rows": [(ext, 2 * ext, L + K)] * 2,
         "ntt_fwd_cols_moddown": [(2 * L, 2 * K + 2 * L, 0)] * 2,      # P-limbs in, conv out
-        "ntt_fwd_rows_moddown": [(2 * L, 8 * L, L), (2 * L, 7 * L, L)],  # conv, ip, addends in; out
+        "ntt_fwd_rows_moddown": [(2 * L, 6 * L, L)] * 2,              # conv, folded ip in; out
         "ntt_fwd_cols_lift": [(2 * (L - 1), 2 + 2 * (L - 1), 0)],     # last limb in, lift out
         "ntt_fwd_rows_rescale": [(2 * (L - 1), 2 * (L - 1) * 3, L - 1)],
     }[name]
