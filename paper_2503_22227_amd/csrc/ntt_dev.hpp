@@ -110,9 +110,14 @@ __device__ __forceinline__ uint32_t row_or_natural(uint32_t tw_base, int s, int 
 // (element p of sub-transform u at lds[p * ldu + u]).  Thread t of the
 // sub-transform owns kElems residues: kElems / 2^C groups of 2^C residues spaced by
 // the round's smallest distance 2^DL.
-template <int S_LOG, int ST0, int C, bool FWD, bool SCALE_LAST, int ROW_A>
+//
+// IN_REGS / OUT_REGS: the round takes its residues from regs / leaves them in
+// regs (group gi, element e at regs[gi * 2^C + e]) instead of LDS.
+template <int S_LOG, int ST0, int C, bool FWD, bool SCALE_LAST, int ROW_A, bool IN_REGS = false,
+          bool OUT_REGS = false>
 __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, uint32_t tw_base,
-                                          const TwPair *__restrict__ tw, const PrimeConst &pc) {
+                                          const TwPair *__restrict__ tw, const PrimeConst &pc,
+                                          uint64_t *regs = nullptr) {
     constexpr int G = 1 << C;
     constexpr int NG = kElems / G;
     constexpr int DL = FWD ? (S_LOG - ST0 - C) : ST0;
@@ -125,7 +130,7 @@ __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, 
         const int base = (hi << (DL + C)) + lo;
         uint64_t v[G];
 #pragma unroll
-        for (int e = 0; e < G; ++e) v[e] = lds[(base + (e << DL)) * ldu + u];
+        for (int e = 0; e < G; ++e) v[e] = IN_REGS ? regs[gi * G + e] : lds[(base + (e << DL)) * ldu + u];
         if constexpr (FWD) {
 #pragma unroll
             for (int c = 0; c < C; ++c) {
@@ -163,7 +168,10 @@ __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, 
             }
         }
 #pragma unroll
-        for (int e = 0; e < G; ++e) lds[(base + (e << DL)) * ldu + u] = v[e];
+        for (int e = 0; e < G; ++e) {
+            if constexpr (OUT_REGS) regs[gi * G + e] = v[e];
+            else lds[(base + (e << DL)) * ldu + u] = v[e];
+        }
     }
 }
 
@@ -199,26 +207,51 @@ __device__ __forceinline__ void ntt_rounds(uint64_t *lds, int ldu, int u, int t,
 template <int A, int B, bool FWD, typename Pro>
 __device__ __forceinline__ void ntt_cols_unit_pro(uint64_t *lds, uint64_t *out, const TwPair *__restrict__ tw,
                                                   const PrimeConst &pc, int tile, const Pro &pro) {
+    static_assert(A > kElemsLog && A <= 2 * kElemsLog, "two rounds");
     constexpr int S = 1 << A;
     constexpr int U = kTile / S;
     constexpr int LDU = U + 1;
+    constexpr int C2 = A - kElemsLog;  // stages of the second round
     const int col0 = tile * U;
-#pragma unroll
-    for (int r = 0; r < kTile / kThreads; ++r) {
-        const int idx = threadIdx.x + r * kThreads;
-        const int row = idx / U, col = idx % U;
-        lds[row * LDU + col] = pro(((size_t)row << B) + col0 + col);
-    }
-    __syncthreads();
     const int u = threadIdx.x % U, t = threadIdx.x / U;
-    ntt_rounds<A, FWD, !FWD>(lds, LDU, u, t, 1u, tw, pc);
+    uint64_t regs[kElems];
+    if constexpr (FWD) {
+        // The first forward round works on rows t + e 2^(A-4) of column u, the
+        // order in which the tile arrives: it starts from registers.
 #pragma unroll
-    for (int r = 0; r < kTile / kThreads; ++r) {
-        const int idx = threadIdx.x + r * kThreads;
-        const int row = idx / U, col = idx % U;
-        uint64_t x = lds[row * LDU + col];
-        if (!FWD) x = csub(x, pc.q);
-        out[((size_t)row << B) + col0 + col] = x;
+        for (int e = 0; e < kElems; ++e)
+            regs[e] = pro(((size_t)(t + (e << C2)) << B) + col0 + u);
+        ntt_round<A, 0, kElemsLog, true, false, 0, true, false>(lds, LDU, u, t, 1u, tw, pc, regs);
+        __syncthreads();
+        ntt_round<A, kElemsLog, C2, true, false, 0>(lds, LDU, u, t, 1u, tw, pc);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kTile / kThreads; ++r) {
+            const int idx = threadIdx.x + r * kThreads;
+            const int row = idx / U, col = idx % U;
+            out[((size_t)row << B) + col0 + col] = lds[row * LDU + col];
+        }
+    } else {
+        // The last inverse round leaves rows grp + 16 e (grp = t NG + gi) of
+        // column u in registers, the order of a coalesced store.
+#pragma unroll
+        for (int r = 0; r < kTile / kThreads; ++r) {
+            const int idx = threadIdx.x + r * kThreads;
+            const int row = idx / U, col = idx % U;
+            lds[row * LDU + col] = pro(((size_t)row << B) + col0 + col);
+        }
+        __syncthreads();
+        ntt_round<A, 0, kElemsLog, false, false, 0>(lds, LDU, u, t, 1u, tw, pc);
+        __syncthreads();
+        ntt_round<A, kElemsLog, C2, false, true, 0, false, true>(lds, LDU, u, t, 1u, tw, pc, regs);
+        constexpr int G = 1 << C2, NG = kElems / G;
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi)
+#pragma unroll
+            for (int e = 0; e < G; ++e) {
+                const int row = t * NG + gi + (e << kElemsLog);
+                out[((size_t)row << B) + col0 + u] = csub(regs[gi * G + e], pc.q);
+            }
     }
     __syncthreads();
 }
