@@ -58,6 +58,8 @@ bool is_prime_h(uint64_t n) {
 }
 
 uint64_t shoup_companion(uint64_t w, uint64_t q) { return (uint64_t)(((u128h)w << 64) / q); }
+// companion of the NTT twiddles, scaled by 2^62 (shoup62_lazy)
+uint64_t shoup_companion62(uint64_t w, uint64_t q) { return (uint64_t)(((u128h)w << 62) / q); }
 
 uint32_t bitrev_h(uint32_t x, int bits) {
     uint32_t r = 0;
@@ -224,10 +226,10 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
             uint32_t r = bitrev_h(k, c->log_n);
             TwPair &f = twf[(size_t)g * N + k];
             f.w = pw[r];
-            f.wp = shoup_companion(f.w, q);
+            f.wp = shoup_companion62(f.w, q);
             TwPair &b = twi[(size_t)g * N + k];
             b.w = pwi[r];
-            b.wp = shoup_companion(b.w, q);
+            b.wp = shoup_companion62(b.w, q);
         }
         if (c->log_n > 12) {
             // row-pass layout: entry (r, s, j) of the natural table moves to row_tw_index

@@ -65,21 +65,23 @@ __host__ __device__ inline uint32_t row_tw_index(int A, int B, bool fwd, uint32_
     return (1u << (A + s)) + ((r_hi * R + k) * T + t) * U + u;
 }
 
-__device__ __forceinline__ void ct_bfly(uint64_t &x, uint64_t &y, uint64_t w, uint64_t wp, uint64_t q,
+// Butterflies with twiddle w and its 2^62-scaled companion wp (shoup62_lazy);
+// nq = 2^64 - q.
+__device__ __forceinline__ void ct_bfly(uint64_t &x, uint64_t &y, uint64_t w, uint64_t wp, uint64_t nq,
                                         uint64_t q2) {
     uint64_t xr = x >= q2 ? x - q2 : x;       // [0, 2q)
-    uint64_t t = shoup_lazy(y, w, wp, q);     // [0, 2q)
+    uint64_t t = shoup62_lazy(y, w, wp, nq);  // [0, 2q); y < 4q < 2^62
     x = xr + t;                               // [0, 4q)
     y = xr - t + q2;                          // (0, 4q)
 }
 
-__device__ __forceinline__ void gs_bfly(uint64_t &x, uint64_t &y, uint64_t w, uint64_t wp, uint64_t q,
+__device__ __forceinline__ void gs_bfly(uint64_t &x, uint64_t &y, uint64_t w, uint64_t wp, uint64_t nq,
                                         uint64_t q2) {
     uint64_t s = x + y;                       // x, y in [0, 2q)
     s = s >= q2 ? s - q2 : s;
     uint64_t d = x - y + q2;                  // (0, 4q)
     x = s;
-    y = shoup_lazy(d, w, wp, q);              // [0, 2q)
+    y = shoup62_lazy(d, w, wp, nq);           // [0, 2q)
 }
 
 __device__ __forceinline__ void gs_bfly_last(uint64_t &x, uint64_t &y, const PrimeConst &pc, uint64_t q2) {
@@ -121,7 +123,7 @@ __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, 
     constexpr int G = 1 << C;
     constexpr int NG = kElems / G;
     constexpr int DL = FWD ? (S_LOG - ST0 - C) : ST0;
-    const uint64_t q = pc.q, q2 = 2 * q;
+    const uint64_t q = pc.q, q2 = 2 * q, nq = 0 - q;
 #pragma unroll
     for (int gi = 0; gi < NG; ++gi) {
         const int grp = t * NG + gi;
@@ -144,7 +146,7 @@ __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, 
                     const uint32_t j = ST0 == 0 ? (uint32_t)(e >> (C - c))
                                                 : (uint32_t)((base + (e << DL)) >> (S_LOG - st));
                     const TwPair w = tw[row_or_natural<S_LOG, ROW_A, true>(tw_base, st, t, j)];
-                    ct_bfly(v[e], v[e + h], w.w, w.wp, q, q2);
+                    ct_bfly(v[e], v[e + h], w.w, w.wp, nq, q2);
                 }
             }
         } else {
@@ -162,7 +164,7 @@ __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, 
                         const uint32_t lo_part = ST0 + C == S_LOG ? (uint32_t)(e >> (c + 1))
                                                                   : (uint32_t)((base + (e << DL)) >> (us + 1));
                         const TwPair w = tw[row_or_natural<S_LOG, ROW_A, false>(tw_base, S_LOG - us - 1, t, lo_part)];
-                        gs_bfly(v[e], v[e + h], w.w, w.wp, q, q2);
+                        gs_bfly(v[e], v[e + h], w.w, w.wp, nq, q2);
                     }
                 }
             }

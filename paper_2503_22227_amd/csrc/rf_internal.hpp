@@ -27,7 +27,7 @@ struct PrimeConst {
 };
 
 struct __align__(16) TwPair {
-    uint64_t w, wp;  // twiddle and floor(w 2^64 / q)
+    uint64_t w, wp;  // twiddle and floor(w 2^62 / q) (the companion of shoup62_lazy)
 };
 
 // Launch description of a batched (I)NTT over limbs laid out as
