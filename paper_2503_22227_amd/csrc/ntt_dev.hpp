@@ -199,30 +199,50 @@ __device__ __forceinline__ void ntt_rounds(uint64_t *lds, int ldu, int u, int t,
     ntt_rounds_from<S_LOG, 0, FWD, SCALE_LAST, ROW_A>(lds, ldu, u, t, tw_base, tw, pc);
 }
 
-// Column pass unit: sub-transforms are columns (2^A rows, stride 2^B), tile
+// Column pass: sub-transforms are columns (2^A rows, stride 2^B), tile
 // `tile` covers 4096 / 2^A consecutive columns.  Forward: the first A stages
 // (output lazy in [0, 4q)); inverse: the last A stages with the N^-1 scaling
 // (output in [0, q)).  The input residue of limb index idx is pro(idx) (a
 // plain load, or an element-wise step that precedes the transform: forward
-// inputs may lie anywhere in [0, 4q)).  Ends with a barrier, so lds may be
-// reused at once.
+// inputs may lie anywhere in [0, 4q)).
+//
+// A pass is split into its loads (ntt_cols_load: the kElems input residues of
+// this thread, in registers, prologue included) and the rest
+// (ntt_cols_compute): the prologue's temporaries are dead before the transform
+// starts, which keeps the multi-pass batched kernels within their register
+// budget.
 template <int A, int B, bool FWD, typename Pro>
-__device__ __forceinline__ void ntt_cols_unit_pro(uint64_t *lds, uint64_t *out, const TwPair *__restrict__ tw,
-                                                  const PrimeConst &pc, int tile, const Pro &pro) {
+__device__ __forceinline__ void ntt_cols_load(uint64_t (&regs)[kElems], int tile, const Pro &pro) {
     static_assert(A > kElemsLog && A <= 2 * kElemsLog, "two rounds");
-    constexpr int S = 1 << A;
-    constexpr int U = kTile / S;
-    constexpr int LDU = U + 1;
+    constexpr int U = kTile >> A;
     constexpr int C2 = A - kElemsLog;  // stages of the second round
     const int col0 = tile * U;
     const int u = threadIdx.x % U, t = threadIdx.x / U;
-    uint64_t regs[kElems];
     if constexpr (FWD) {
         // The first forward round works on rows t + e 2^(A-4) of column u, the
         // order in which the tile arrives: it starts from registers.
 #pragma unroll
-        for (int e = 0; e < kElems; ++e)
-            regs[e] = pro(((size_t)(t + (e << C2)) << B) + col0 + u);
+        for (int e = 0; e < kElems; ++e) regs[e] = pro(((size_t)(t + (e << C2)) << B) + col0 + u);
+    } else {
+#pragma unroll
+        for (int r = 0; r < kTile / kThreads; ++r) {
+            const int idx = threadIdx.x + r * kThreads;
+            regs[r] = pro(((size_t)(idx / U) << B) + col0 + idx % U);
+        }
+    }
+}
+
+// Ends with a barrier, so lds may be reused at once.
+template <int A, int B, bool FWD>
+__device__ __forceinline__ void ntt_cols_compute(uint64_t *lds, uint64_t *out, const TwPair *__restrict__ tw,
+                                                 const PrimeConst &pc, int tile, uint64_t (&regs)[kElems]) {
+    constexpr int S = 1 << A;
+    constexpr int U = kTile / S;
+    constexpr int LDU = U + 1;
+    constexpr int C2 = A - kElemsLog;
+    const int col0 = tile * U;
+    const int u = threadIdx.x % U, t = threadIdx.x / U;
+    if constexpr (FWD) {
         ntt_round<A, 0, kElemsLog, true, false, 0, true, false>(lds, LDU, u, t, 1u, tw, pc, regs);
         __syncthreads();
         ntt_round<A, kElemsLog, C2, true, false, 0>(lds, LDU, u, t, 1u, tw, pc);
@@ -234,17 +254,16 @@ __device__ __forceinline__ void ntt_cols_unit_pro(uint64_t *lds, uint64_t *out, 
             out[((size_t)row << B) + col0 + col] = lds[row * LDU + col];
         }
     } else {
-        // The last inverse round leaves rows grp + 16 e (grp = t NG + gi) of
-        // column u in registers, the order of a coalesced store.
 #pragma unroll
         for (int r = 0; r < kTile / kThreads; ++r) {
             const int idx = threadIdx.x + r * kThreads;
-            const int row = idx / U, col = idx % U;
-            lds[row * LDU + col] = pro(((size_t)row << B) + col0 + col);
+            lds[(idx / U) * LDU + idx % U] = regs[r];
         }
         __syncthreads();
         ntt_round<A, 0, kElemsLog, false, false, 0>(lds, LDU, u, t, 1u, tw, pc);
         __syncthreads();
+        // The last inverse round leaves rows grp + 16 e (grp = t NG + gi) of
+        // column u in registers, the order of a coalesced store.
         ntt_round<A, kElemsLog, C2, false, true, 0, false, true>(lds, LDU, u, t, 1u, tw, pc, regs);
         constexpr int G = 1 << C2, NG = kElems / G;
 #pragma unroll
@@ -256,6 +275,14 @@ __device__ __forceinline__ void ntt_cols_unit_pro(uint64_t *lds, uint64_t *out, 
             }
     }
     __syncthreads();
+}
+
+template <int A, int B, bool FWD, typename Pro>
+__device__ __forceinline__ void ntt_cols_unit_pro(uint64_t *lds, uint64_t *out, const TwPair *__restrict__ tw,
+                                                  const PrimeConst &pc, int tile, const Pro &pro) {
+    uint64_t regs[kElems];
+    ntt_cols_load<A, B, FWD>(regs, tile, pro);
+    ntt_cols_compute<A, B, FWD>(lds, out, tw, pc, tile, regs);
 }
 
 struct LoadPro {
@@ -325,13 +352,26 @@ struct StoreEpi {
     __device__ __forceinline__ void operator()(size_t idx, uint64_t x) const { out[idx] = x; }
 };
 
-// Row pass unit: sub-transforms are rows (2^B contiguous residues), tile `tile`
+// Row pass: sub-transforms are rows (2^B contiguous residues), tile `tile`
 // covers 4096 / 2^B consecutive rows.  Forward: the last B stages (output in
 // [0, q)); inverse: the first B stages (output lazy in [0, 2q)).  The result
-// for limb index idx goes through epi(idx, value).
-template <int A, int B, bool FWD, typename Pro, typename Epi>
-__device__ __forceinline__ void ntt_rows_unit_pe(uint64_t *lds, const Pro &pro, const TwPair *__restrict__ tw,
-                                                 const PrimeConst &pc, int tile, const Epi &epi) {
+// for limb index idx goes through epi(idx, value).  Split into loads and the
+// rest like the column pass.
+template <int A, int B, typename Pro>
+__device__ __forceinline__ void ntt_rows_load(uint64_t (&regs)[kElems], int tile, const Pro &pro) {
+    constexpr int S = 1 << B;
+    constexpr int U = kTile / S;
+    const int row0 = tile * U;
+#pragma unroll
+    for (int r = 0; r < kTile / kThreads; ++r) {
+        const int idx = threadIdx.x + r * kThreads;
+        regs[r] = pro(((size_t)(row0 + (idx >> B)) << B) + (idx & (S - 1)));
+    }
+}
+
+template <int A, int B, bool FWD, typename Epi>
+__device__ __forceinline__ void ntt_rows_compute(uint64_t *lds, const TwPair *__restrict__ tw, const PrimeConst &pc,
+                                                 int tile, const Epi &epi, uint64_t (&regs)[kElems]) {
     constexpr int S = 1 << B;
     constexpr int U = kTile / S;
     constexpr int LDU = U + 1;
@@ -339,8 +379,7 @@ __device__ __forceinline__ void ntt_rows_unit_pe(uint64_t *lds, const Pro &pro, 
 #pragma unroll
     for (int r = 0; r < kTile / kThreads; ++r) {
         const int idx = threadIdx.x + r * kThreads;
-        const int row = idx >> B, p = idx & (S - 1);
-        lds[p * LDU + row] = pro(((size_t)(row0 + row) << B) + p);
+        lds[(idx & (S - 1)) * LDU + (idx >> B)] = regs[r];
     }
     __syncthreads();
     const int u = threadIdx.x % U, t = threadIdx.x / U;
@@ -355,6 +394,14 @@ __device__ __forceinline__ void ntt_rows_unit_pe(uint64_t *lds, const Pro &pro, 
         epi(((size_t)(row0 + row) << B) + p, x);
     }
     __syncthreads();
+}
+
+template <int A, int B, bool FWD, typename Pro, typename Epi>
+__device__ __forceinline__ void ntt_rows_unit_pe(uint64_t *lds, const Pro &pro, const TwPair *__restrict__ tw,
+                                                 const PrimeConst &pc, int tile, const Epi &epi) {
+    uint64_t regs[kElems];
+    ntt_rows_load<A, B>(regs, tile, pro);
+    ntt_rows_compute<A, B, FWD>(lds, tw, pc, tile, epi, regs);
 }
 
 template <int A, int B, bool FWD, typename Epi>
