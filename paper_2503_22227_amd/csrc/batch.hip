@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kEw) void ks_batched_kernel(const KsJob *__restrict
         if constexpr (STAGE == kTensor) {
             tensor_unit(J.a, J.b, J.out, J.d2, J.pcs, J.log_n, J.nl, nullptr, gx, gy);
         } else if constexpr (STAGE == kModupConv) {
-            modup_bconv_unit(J.d_coeff, J.ext, J.pcs, J.modup_tab, J.modup_stride, J.log_n, J.nl, J.L, J.K, J.alpha,
+            modup_bconv_unit<true>(J.d_coeff, J.ext, J.pcs, J.modup_tab, J.modup_stride, J.log_n, J.nl, J.L, J.K, J.alpha,
                              gx, gy);
         } else if constexpr (STAGE == kInnerProduct) {
             IpFold f;
@@ -459,8 +459,9 @@ extern "C" int rf_batch_create(const rf_batch_item *items, uint32_t n, void *ws,
             ntt[k][i].b = bs[k];
             ntt[k][i].tw_all = (k == 1 || k == 3) ? c->d_tw_fwd : c->d_tw_inv;
             ntt[k][i].tw_rows = (k == 1 || k == 3) ? c->d_tw_fwd_rows : c->d_tw_inv_rows;
-            // the INTT of the P-limbs folds the ModDown input factor into its last stage
-            ntt[k][i].pcs = k == 2 ? c->d_pc_md : c->d_pc;
+            // the INTT of d2 folds the ModUp input factor, the INTT of the P-limbs the
+            // ModDown input factor into its last stage
+            ntt[k][i].pcs = k == 0 ? pc_modup(c, nl) : k == 2 ? c->d_pc_md : c->d_pc;
             ntt[k][i].log_n = c->log_n;
             ntt[k][i].unit_begin = J.unit_begin[first_stage[k]];
             ntt[k][i].ct_a = it.a;

@@ -81,9 +81,14 @@ int keyswitch_core(const rf_ctx *c, const uint64_t *d, const uint64_t *evk, uint
     const ModupLevel &lv = c->modup_levels[nl];
     uint64_t *d_coeff = ws + l.d_coeff, *ext = ws + l.ext, *ip = ws + l.ip, *conv = ws + l.conv;
     int rc;
-    // ModUp: INTT of d, base conversion of each digit, NTT of the new limbs
-    if (!fused && (rc = launch_ntt(c, batch(d, d_coeff, 0, 0, nl, 1, 0, nullptr), false, s))) return rc;
-    if ((rc = launch_modup_bconv(c, d_coeff, ext, nl, s))) return rc;
+    // ModUp: INTT of d, base conversion of each digit, NTT of the new limbs.
+    // Two-pass ring degrees: the INTT folds in the conversion's input factor
+    // (pc_modup; launch_intt_first does the same for the fused callers).
+    const bool scaled = c->log_n > 12;
+    if (!fused && (rc = launch_ntt(c, batch(d, d_coeff, 0, 0, nl, 1, 0, nullptr), false, s,
+                                   scaled ? pc_modup(c, nl) : nullptr)))
+        return rc;
+    if ((rc = launch_modup_bconv(c, d_coeff, ext, nl, s, scaled))) return rc;
     if ((rc = launch_ntt(c, batch(ext, ext, 0, 0, lv.ext_limbs, 1, 0, c->d_pmaps + lv.pmap_off), true, s))) return rc;
     // ModDown: INTT of the P-limbs, base conversion to Q_l, NTT, subtract and scale by P^-1
     const uint64_t ip_stride = (uint64_t)(nl + c->K) * N;

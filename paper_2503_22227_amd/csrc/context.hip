@@ -3,6 +3,7 @@
 // middle tier, section III), and uploaded once.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -105,6 +106,7 @@ const char *last_error() { return g_last_error.c_str(); }
 static void free_tables(rf_ctx *c) {
     (void)hipFree(c->d_pc);
     (void)hipFree(c->d_pc_md);
+    (void)hipFree(c->d_pc_mu);
     (void)hipFree(c->d_tw_fwd);
     (void)hipFree(c->d_tw_inv);
     (void)hipFree(c->d_tw_fwd_rows);
@@ -348,6 +350,25 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
         e.wlast_p = shoup_companion(e.wlast, pa);
     }
 
+    // INTT constants of every level with the ModUp input factor of each Q-limb
+    // folded into the last stage (the factor of limb i depends on the size of
+    // its digit, which the level truncates)
+    const size_t npc = (size_t)c->L + c->K;
+    std::vector<PrimeConst> pc_mu((size_t)c->L * npc);
+    for (uint32_t nl = 1; nl <= c->L; ++nl) {
+        PrimeConst *row = pc_mu.data() + (size_t)(nl - 1) * npc;
+        std::copy(pc.begin(), pc.begin() + npc, row);
+        for (uint32_t i = 0; i < nl; ++i) {
+            const uint32_t j = i / A, start = j * A, sz = std::min(A, nl - start);
+            const uint64_t f = mu[modup_block(c, j, sz) + 2 * (i - start)];
+            PrimeConst &e = row[i];
+            e.ninv = mulmod_h(e.ninv, f, e.q);
+            e.ninv_p = shoup_companion(e.ninv, e.q);
+            e.wlast = mulmod_h(e.wlast, f, e.q);
+            e.wlast_p = shoup_companion(e.wlast, e.q);
+        }
+    }
+
     // Rescale: drop q_l (l >= 1) into every q_i, i < l
     std::vector<uint64_t> rs((size_t)c->L * c->L * 3, 0);
     for (uint32_t l = 1; l < c->L; ++l) {
@@ -483,7 +504,7 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
 
     int rc = RF_OK;
     if ((!bz.empty() && ((rc = upload(&c->d_behz, bz)) || (rc = upload(&c->d_pmap_qb, pmqb)))) ||
-        (rc = upload(&c->d_pc, pc)) || (rc = upload(&c->d_pc_md, pc_md)) ||
+        (rc = upload(&c->d_pc, pc)) || (rc = upload(&c->d_pc_md, pc_md)) || (rc = upload(&c->d_pc_mu, pc_mu)) ||
         (!twrf.empty() && ((rc = upload(&c->d_tw_fwd_rows, twrf)) || (rc = upload(&c->d_tw_inv_rows, twri)))) || (rc = upload(&c->d_tw_fwd, twf)) || (rc = upload(&c->d_tw_inv, twi)) ||
         (rc = upload(&c->d_modup, mu)) || (rc = upload(&c->d_moddown, md)) ||
         (!mdt.empty() && (rc = upload(&c->d_moddown_t, mdt))) || (rc = upload(&c->d_rescale, rs)) ||

@@ -41,12 +41,13 @@ __global__ __launch_bounds__(kEw) void behz_floor_sk_kernel(const uint64_t *tens
     behz_floor_sk_unit(tens, out01, out2, pcs, tab, o, kb, log_n, blockIdx.x, blockIdx.y);
 }
 
+template <bool SCALED>
 __global__ __launch_bounds__(kEw) void modup_bconv_kernel(const uint64_t *__restrict__ x, uint64_t *__restrict__ ext,
                                                           const PrimeConst *__restrict__ pcs,
                                                           const uint64_t *__restrict__ tab, size_t tab_stride,
                                                           uint32_t log_n, uint32_t nl, uint32_t L, uint32_t K,
                                                           uint32_t alpha) {
-    modup_bconv_unit(x, ext, pcs, tab, tab_stride, log_n, nl, L, K, alpha, blockIdx.x, blockIdx.y);
+    modup_bconv_unit<SCALED>(x, ext, pcs, tab, tab_stride, log_n, nl, L, K, alpha, blockIdx.x, blockIdx.y);
 }
 
 __global__ __launch_bounds__(kEw) void inner_product_kernel(const uint64_t *__restrict__ d,
@@ -138,11 +139,16 @@ int launch_behz_floor_sk(const rf_ctx *c, const uint64_t *tens, uint64_t *out01,
     return check_launch("behz_floor_sk");
 }
 
-int launch_modup_bconv(const rf_ctx *c, const uint64_t *x, uint64_t *ext, uint32_t nl, hipStream_t s) {
+int launch_modup_bconv(const rf_ctx *c, const uint64_t *x, uint64_t *ext, uint32_t nl, hipStream_t s, bool scaled) {
     const uint32_t dn = (nl + c->alpha - 1) / c->alpha;
     ProfScope prof("modup_bconv", s);
-    hipLaunchKernelGGL(modup_bconv_kernel, ew_grid(c, dn * modup_chunks(nl, c->K)), dim3(kEw), 0, s, x, ext, c->d_pc, c->d_modup,
-                       c->modup_stride, c->log_n, nl, c->L, c->K, c->alpha);
+    const dim3 grid = ew_grid(c, dn * modup_chunks(nl, c->K));
+    if (scaled)
+        hipLaunchKernelGGL(modup_bconv_kernel<true>, grid, dim3(kEw), 0, s, x, ext, c->d_pc, c->d_modup,
+                           c->modup_stride, c->log_n, nl, c->L, c->K, c->alpha);
+    else
+        hipLaunchKernelGGL(modup_bconv_kernel<false>, grid, dim3(kEw), 0, s, x, ext, c->d_pc, c->d_modup,
+                           c->modup_stride, c->log_n, nl, c->L, c->K, c->alpha);
     return check_launch("modup_bconv");
 }
 

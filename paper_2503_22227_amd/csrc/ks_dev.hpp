@@ -45,8 +45,10 @@ __host__ __device__ inline uint32_t moddown_chunks(uint32_t nl) { return (nl + k
 // ModUp conversion of one chunk of targets for a digit of S primes (S a
 // compile-time constant, so the S multiply-accumulates per target are fully
 // unrolled and the target's S constants, stored contiguously, can be fetched
-// with wide scalar loads ahead of use).
-template <int S>
+// with wide scalar loads ahead of use).  SCALED: x already holds
+// y_i = [x_i (Q_j/q_i)^-1]_{q_i} (an INTT with that factor folded into its last
+// stage), so the digit's input products are skipped.
+template <int S, bool SCALED>
 __device__ __forceinline__ void modup_conv_s(const uint64_t *__restrict__ x, uint64_t *__restrict__ dst,
                                              const PrimeConst *__restrict__ pcs, const uint64_t *__restrict__ blk,
                                              uint32_t alpha, uint32_t start, uint32_t ntarget, uint32_t t0,
@@ -54,8 +56,8 @@ __device__ __forceinline__ void modup_conv_s(const uint64_t *__restrict__ x, uin
     uint32_t yl[S], yh[S];
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-        const uint64_t q = pcs[start + i].q;
-        const uint64_t y = shoup(x[((size_t)(start + i) << log_n) + n], blk[2 * i], blk[2 * i + 1], q);
+        const uint64_t xi = x[((size_t)(start + i) << log_n) + n];
+        const uint64_t y = SCALED ? xi : shoup(xi, blk[2 * i], blk[2 * i + 1], pcs[start + i].q);
         yl[i] = (uint32_t)y & 0x3fffffffu;
         yh[i] = (uint32_t)(y >> 30);
     }
@@ -79,6 +81,8 @@ __device__ __forceinline__ void modup_conv_s(const uint64_t *__restrict__ x, uin
 // digits back to back, digit j holding nl - s_j + K limbs ordered as the basis
 // Q_l u P without the digit's own primes, each residue in [0, 4q) (the forward
 // NTT that follows accepts that range).  gy = digit * modup_chunks + chunk.
+// SCALED: x holds the digits' input factors already (see modup_conv_s).
+template <bool SCALED>
 __device__ __forceinline__ void modup_bconv_unit(const uint64_t *__restrict__ x, uint64_t *__restrict__ ext,
                                                  const PrimeConst *__restrict__ pcs,
                                                  const uint64_t *__restrict__ tab, size_t tab_stride,
@@ -95,14 +99,14 @@ __device__ __forceinline__ void modup_bconv_unit(const uint64_t *__restrict__ x,
     const uint64_t *blk = tab + ((size_t)j * alpha + (s - 1)) * tab_stride;
     uint64_t *dst = ext + (((size_t)j * (nl + K - alpha)) << log_n) + n;
     switch (s) {
-        case 1: modup_conv_s<1>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
-        case 2: modup_conv_s<2>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
-        case 3: modup_conv_s<3>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
-        case 4: modup_conv_s<4>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
-        case 5: modup_conv_s<5>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
-        case 6: modup_conv_s<6>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
-        case 7: modup_conv_s<7>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
-        default: modup_conv_s<8>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 1: modup_conv_s<1, SCALED>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 2: modup_conv_s<2, SCALED>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 3: modup_conv_s<3, SCALED>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 4: modup_conv_s<4, SCALED>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 5: modup_conv_s<5, SCALED>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 6: modup_conv_s<6, SCALED>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 7: modup_conv_s<7, SCALED>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        default: modup_conv_s<8, SCALED>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
     }
 }
 

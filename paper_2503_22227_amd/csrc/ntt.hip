@@ -307,7 +307,7 @@ int launch_intt_first(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uin
         NttBatch bc{dc, dc, 0, 0, nl, 1, 0, nullptr};                                                            \
         ProfScope p("ntt_inv_cols", s);                                                                          \
         hipLaunchKernelGGL((ntt_cols_kernel<A, B, false>), dim3((1u << B) / (kTile >> A), nl), dim3(kThreads), 0, \
-                           s, bc, c->d_tw_inv, c->d_pc);                                                         \
+                           s, bc, c->d_tw_inv, pc_modup(c, nl));                                                 \
     }
     switch (c->log_n) {
         case 13: RF_IF(7, 6) break;

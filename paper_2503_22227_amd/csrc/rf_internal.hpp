@@ -87,6 +87,9 @@ struct rf_ctx {
     rf::PrimeConst *d_pc = nullptr;        // [L+K]
     rf::PrimeConst *d_pc_md = nullptr;     // d_pc with the ModDown input factor [(P/p_a)^-1]_{p_a}
                                            // folded into the last inverse stage of every special prime
+    rf::PrimeConst *d_pc_mu = nullptr;     // [L][L+K]: per level nl (row nl - 1), d_pc with the ModUp
+                                           // input factor [(Q_j/q_i)^-1]_{q_i} of limb i < nl (digit j
+                                           // at that level) folded into its last inverse stage
     rf::TwPair *d_tw_fwd = nullptr;        // [L+K][N]: psi^brv(k)
     rf::TwPair *d_tw_inv = nullptr;        // [L+K][N]: psi^-brv(k)
     rf::TwPair *d_tw_fwd_rows = nullptr;   // the same twiddles in the row-pass layout (ntt_dev.hpp)
@@ -138,6 +141,10 @@ __device__ __forceinline__ uint32_t galois_src(uint32_t k, uint32_t galois, uint
 inline size_t modup_block(const rf_ctx *c, uint32_t j, uint32_t s) {
     return ((size_t)j * c->alpha + (s - 1)) * c->modup_stride;
 }
+// INTT constants of level nl whose output is the ModUp input y_i = [x_i (Q_j/q_i)^-1]_{q_i}.
+inline const PrimeConst *pc_modup(const rf_ctx *c, uint32_t nl) {
+    return c->d_pc_mu + (size_t)(nl - 1) * (c->L + c->K);
+}
 // ModDown table: [K] factor pairs (w, w') of [(P/p)^-1]_p; [L][K] cross [P/p]_{q_i} (target-major);
 // [L] pairs P^-1 mod q_i; [L] (q_i - [P]_{q_i}).
 inline size_t moddown_cross_off(const rf_ctx *c) { return 2 * (size_t)c->K; }
@@ -178,7 +185,7 @@ int launch_ntt_fwd_moddown(const rf_ctx *c, uint64_t *conv, const uint64_t *ip, 
                            hipStream_t s);
 // INTT of the polynomial to key-switch (two-pass ring degrees only), with the
 // step that produces it as the prologue of its first pass, into dc [nl][N]
-// (coefficient domain):
+// (coefficient domain, scaled for ModUp by pc_modup(c, nl)):
 //   galois == 0 (HMult): d2 = a1 b1 of a, b ([2][nl][N]);
 //   galois != 0 (HRotate): sigma_g of a's polynomial 1.
 int launch_intt_first(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *dc, uint32_t galois,
@@ -191,8 +198,10 @@ int launch_ntt_fwd_rescale(const rf_ctx *c, const uint64_t *last, uint64_t *lift
                            uint64_t *out, uint32_t nl, bool keep_t, hipStream_t s);
 int launch_tensor(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *d01,
                   uint64_t *d2, uint32_t nl, hipStream_t s);
-int launch_modup_bconv(const rf_ctx *c, const uint64_t *x, uint64_t *ext, uint32_t nl,
-                       hipStream_t s);
+// scaled: x is an INTT taken with pc_modup(c, nl), so each limb already carries
+// its digit's input factor [(Q_j/q_i)^-1]_{q_i}.
+int launch_modup_bconv(const rf_ctx *c, const uint64_t *x, uint64_t *ext, uint32_t nl, hipStream_t s,
+                       bool scaled = false);
 // fold (non-null): the Q-limbs leave as ip P^-1 + add_c with the sources fold
 // names (its pinv is filled in here), for launch_ntt_fwd_moddown.
 int launch_inner_product(const rf_ctx *c, const uint64_t *d_ntt, const uint64_t *ext,
