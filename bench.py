@@ -128,6 +128,11 @@ def algorithmic_bytes(kernel: str, nl: int, K: int, alpha: int, n: int, op: str)
     return table[kernel] * limb if kernel in table else float("nan")
 
 
+def _progress(msg: str) -> None:
+    """One line per finished section on stderr (stdout carries only the result line)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -265,22 +270,27 @@ def main():
                  "alu_frac": round(alu_frac, 4), "hbm_frac": round(hbm_frac, 4),
                  "algorithmic_bytes": round(by), "work_per_launch": work})
 
+    _progress("timed steps and kernel roofline done")
     batch = None
     if not args.no_batch:
         del m_out, r_out, ro_out
         batch = batch_section(max(3, min(args.steps, 10)))
+        _progress("batched section done")
 
     exact = None
     if not args.no_bfv_bgv:
         exact = bfv_bgv_section(max(args.steps, 10))
+        _progress("BFV/BGV section done")
 
     serving = None
     if not args.no_pdq:
         serving = pdq_section(args.pdq_queries)
+        _progress("serving section done")
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
+        _progress("CPU oracle baseline done")
 
     line = {
         "metric": "CKKS HMult+Relin/HRotate per sec @N=2^16 L=24",

@@ -32,13 +32,20 @@ __device__ __forceinline__ void tensor_unit(const uint64_t *__restrict__ a, cons
 
 // Targets of a base conversion handled by one work unit: splitting the
 // targets over several units multiplies the parallelism of the conversion
-// (its inputs are re-read and re-scaled per chunk, which is cheap next to the
-// chunk's multiply-accumulates) and lets the unrolled target loop prefetch its
-// uniform constants.
+// (its inputs are re-read, from L2, and where not pre-scaled re-scaled per
+// chunk, which is cheap next to the chunk's multiply-accumulates) and lets the
+// unrolled target loop prefetch its uniform constants.
 constexpr int kConvChunk = 8;
+// ModUp targets per workgroup row.  Measured at N = 2^16, 24 + 4 primes,
+// alpha = 8 (20 targets per digit): 8 targets 18.4 us, 10 targets 19.1 us,
+// 20 targets 24.8 us per launch (fewer, longer waves hide less latency).
+#ifndef RF_MODUP_CHUNK
+#define RF_MODUP_CHUNK 8
+#endif
+constexpr int kModupChunk = RF_MODUP_CHUNK;
 
 __host__ __device__ inline uint32_t modup_chunks(uint32_t nl, uint32_t K) {
-    return (nl + K - 1 + kConvChunk - 1) / kConvChunk;
+    return (nl + K - 1 + kModupChunk - 1) / kModupChunk;
 }
 __host__ __device__ inline uint32_t moddown_chunks(uint32_t nl) { return (nl + kConvChunk - 1) / kConvChunk; }
 
@@ -63,7 +70,7 @@ __device__ __forceinline__ void modup_conv_s(const uint64_t *__restrict__ x, uin
     }
     const uint64_t *cross = blk + 2 * alpha;
 #pragma unroll
-    for (int k = 0; k < kConvChunk; ++k) {
+    for (int k = 0; k < kModupChunk; ++k) {
         const uint32_t tt = t0 + k;
         if (tt < ntarget) {
             const uint32_t g = tt < start ? tt : (tt < nl - S ? tt + S : L + (tt - (nl - S)));
@@ -93,7 +100,7 @@ __device__ __forceinline__ void modup_bconv_unit(const uint64_t *__restrict__ x,
     const uint32_t start = j * alpha;
     const uint32_t s = min(alpha, nl - start);
     const uint32_t ntarget = nl - s + K;
-    const uint32_t t0 = ch * kConvChunk;
+    const uint32_t t0 = ch * kModupChunk;
     if (t0 >= ntarget) return;
     const size_t n = (size_t)gx * kEw + threadIdx.x;
     const uint64_t *blk = tab + ((size_t)j * alpha + (s - 1)) * tab_stride;
