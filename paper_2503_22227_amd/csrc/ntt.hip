@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
 // First forward pass of NTT(conv) with the ModDown base conversion as its
 // prologue: limb (c, i) of conv [2][nl][N] from the K P-limbs of ip[c].
 template <int A, int B, int KP>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesCols))) void ntt_cols_moddown_kernel(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KP == 8 ? kNttWavesCols : kNttWavesFused))) void ntt_cols_moddown_kernel(
     const uint64_t *ip, uint64_t *conv, const TwPair *__restrict__ tw_all, const PrimeConst *__restrict__ pcs,
     const uint64_t *__restrict__ cross, const uint64_t *__restrict__ negp, uint32_t nl, uint32_t L, uint32_t K) {
     __shared__ uint64_t lds[(1 << A) * (kTile / (1 << A) + 1)];
@@ -69,14 +69,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
     pro.r64 = pc.r64;
     pro.r64_p = pc.r64_p;
     pro.one_p = pc.one_p;
-    ntt_cols_unit_pro<A, B, true>(lds, conv + (((size_t)c * nl + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
+    ntt_cols_unit_pro<A, B, true, true>(lds, conv + (((size_t)c * nl + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
                                   blockIdx.x, pro);
 }
 
 // First forward pass of NTT(lift) with the rescale lift as its prologue: limb
 // (c, i) of lift [2][l][N], l = nl - 1, from the last limb last[c].
 template <int A, int B, bool KEEP_T>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesCols))) void ntt_cols_lift_kernel(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesFused))) void ntt_cols_lift_kernel(
     const uint64_t *last, uint64_t *lift, const TwPair *__restrict__ tw_all, const PrimeConst *__restrict__ pcs,
     const uint64_t *__restrict__ tab, uint32_t nl, uint32_t L) {
     __shared__ uint64_t lds[(1 << A) * (kTile / (1 << A) + 1)];
@@ -96,14 +96,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
     pro.corr = tab[((size_t)l * L + i) * 3 + 2];
     pro.tmod = pc.tmod;
     pro.tmod_p = pc.tmod_p;
-    ntt_cols_unit_pro<A, B, true>(lds, lift + (((size_t)c * l + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
+    ntt_cols_unit_pro<A, B, true, true>(lds, lift + (((size_t)c * l + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
                                   blockIdx.x, pro);
 }
 
 // Last forward pass of NTT(conv) with the ModDown tail: limb (c, i) of conv
 // [2][nl][N] -> out[c][i] = (ip[c][i] - NTT(conv)[c][i]) P^-1 (+ add_c[i]).
 template <int A, int B>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesRows))) void ntt_rows_moddown_kernel(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesFused))) void ntt_rows_moddown_kernel(
     const uint64_t *conv, const TwPair *__restrict__ tw_all, const PrimeConst *__restrict__ pcs, const uint64_t *ip,
     uint64_t *out, const uint64_t *__restrict__ pinv, uint32_t nl, uint32_t K) {
     __shared__ uint64_t lds[(1 << B) * (kTile / (1 << B) + 1)];
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
     const PrimeConst pc = pcs[i];
     const ModdownFoldEpi epi{ip + (((size_t)c * (nl + K) + i) << LOGN), out + (((size_t)c * nl + i) << LOGN),
                              pinv[2 * i], pinv[2 * i + 1], pc.q};
-    ntt_rows_unit_epi<A, B, true>(lds, conv + (((size_t)c * nl + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
+    ntt_rows_unit_epi<A, B, true, true>(lds, conv + (((size_t)c * nl + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
                                   blockIdx.x, epi);
 }
 
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
 // Last forward pass of NTT(lift) with the rescale tail: limb (c, i) of lift
 // [2][l][N] -> out[c][i] = (in[c][i] - NTT(lift)[c][i]) q_l^-1, l = nl - 1.
 template <int A, int B>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesRows))) void ntt_rows_rescale_kernel(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesFused))) void ntt_rows_rescale_kernel(
     const uint64_t *lift, const TwPair *__restrict__ tw_all, const PrimeConst *__restrict__ pcs, const uint64_t *in,
     uint64_t *out, const uint64_t *__restrict__ tab, uint32_t nl, uint32_t L) {
     __shared__ uint64_t lds[(1 << B) * (kTile / (1 << B) + 1)];
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
     const PrimeConst pc = pcs[i];
     const uint64_t *t = tab + ((size_t)l * L + i) * 3;
     RescaleTailEpi epi{in + (((size_t)c * nl + i) << LOGN), out + (((size_t)c * l + i) << LOGN), t[0], t[1], pc.q};
-    ntt_rows_unit_epi<A, B, true>(lds, lift + (((size_t)c * l + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
+    ntt_rows_unit_epi<A, B, true, true>(lds, lift + (((size_t)c * l + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
                                   blockIdx.x, epi);
 }
 

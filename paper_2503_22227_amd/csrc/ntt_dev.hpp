@@ -67,29 +67,43 @@ __host__ __device__ inline uint32_t row_tw_index(int A, int B, bool fwd, uint32_
 
 // Butterflies with twiddle w and its 2^62-scaled companion wp (shoup62_lazy);
 // nq = 2^64 - q.
+//
+// LZ (primes below kLazyPrimeBound): no correction of the sum.  Forward
+// (Cooley-Tukey), x grows by less than 2q per stage, so after all stages of
+// both passes of N <= 2^16 every value stays below 36q < 2^56; inverse
+// (Gentleman-Sande), values at most double per stage, so at local stage k of a
+// pass (inputs below 2^(k+1) q) the difference is formed as x - y + off with
+// off = 2^(k+1) q, and each pass starts from inputs below 2q (the row pass
+// reduces its output once, see ntt_rows_compute).  Strict: Harvey's ranges,
+// inputs and outputs below 4q (forward) or 2q (inverse), off = 2q.
+template <bool LZ>
 __device__ __forceinline__ void ct_bfly(uint64_t &x, uint64_t &y, uint64_t w, uint64_t wp, uint64_t nq,
                                         uint64_t q2) {
-    uint64_t xr = x >= q2 ? x - q2 : x;       // [0, 2q)
-    uint64_t t = shoup62_lazy(y, w, wp, nq);  // [0, 2q); y < 4q < 2^62
-    x = xr + t;                               // [0, 4q)
-    y = xr - t + q2;                          // (0, 4q)
+    uint64_t xr = LZ ? x : (x >= q2 ? x - q2 : x);  // strict: [0, 2q)
+    uint64_t t = shoup62_lazy(y, w, wp, nq);         // [0, 2q); y < 2^62
+    x = xr + t;
+    y = xr - t + q2;
 }
 
+template <bool LZ>
 __device__ __forceinline__ void gs_bfly(uint64_t &x, uint64_t &y, uint64_t w, uint64_t wp, uint64_t nq,
-                                        uint64_t q2) {
-    uint64_t s = x + y;                       // x, y in [0, 2q)
-    s = s >= q2 ? s - q2 : s;
-    uint64_t d = x - y + q2;                  // (0, 4q)
+                                        uint64_t q2, uint64_t off) {
+    uint64_t s = x + y;
+    if (!LZ) s = s >= q2 ? s - q2 : s;
+    uint64_t d = x - y + off;                 // off >= any y of this stage
     x = s;
     y = shoup62_lazy(d, w, wp, nq);           // [0, 2q)
 }
 
-__device__ __forceinline__ void gs_bfly_last(uint64_t &x, uint64_t &y, const PrimeConst &pc, uint64_t q2) {
+__device__ __forceinline__ void gs_bfly_last(uint64_t &x, uint64_t &y, const PrimeConst &pc, uint64_t off) {
     uint64_t s = x + y;
-    uint64_t d = x - y + q2;
+    uint64_t d = x - y + off;
     x = shoup_lazy(s, pc.ninv, pc.ninv_p, pc.q);
     y = shoup_lazy(d, pc.wlast, pc.wlast_p, pc.q);
 }
+
+// Transforms of primes below this bound skip the sum corrections (LZ above).
+constexpr uint64_t kLazyPrimeBound = 1ull << 50;
 
 // Table index of twiddle j of local stage s: the natural index (tw_base << s) + j
 // (column passes, ROW_A == 0) or the row-pass layout above, with tw_base = 2^A + r
@@ -116,7 +130,7 @@ __device__ __forceinline__ uint32_t row_or_natural(uint32_t tw_base, int s, int 
 // IN_REGS / OUT_REGS: the round takes its residues from regs / leaves them in
 // regs (group gi, element e at regs[gi * 2^C + e]) instead of LDS.
 template <int S_LOG, int ST0, int C, bool FWD, bool SCALE_LAST, int ROW_A, bool IN_REGS = false,
-          bool OUT_REGS = false>
+          bool OUT_REGS = false, bool LZ = false>
 __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, uint32_t tw_base,
                                           const TwPair *__restrict__ tw, const PrimeConst &pc,
                                           uint64_t *regs = nullptr) {
@@ -146,7 +160,7 @@ __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, 
                     const uint32_t j = ST0 == 0 ? (uint32_t)(e >> (C - c))
                                                 : (uint32_t)((base + (e << DL)) >> (S_LOG - st));
                     const TwPair w = tw[row_or_natural<S_LOG, ROW_A, true>(tw_base, st, t, j)];
-                    ct_bfly(v[e], v[e + h], w.w, w.wp, nq, q2);
+                    ct_bfly<LZ>(v[e], v[e + h], w.w, w.wp, nq, q2);
                 }
             }
         } else {
@@ -154,17 +168,18 @@ __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, 
             for (int c = 0; c < C; ++c) {
                 const int us = ST0 + c;
                 const int h = 1 << c;
+                const uint64_t off = LZ ? q << (us + 1) : q2;
 #pragma unroll
                 for (int e = 0; e < G; ++e) {
                     if (e & h) continue;
                     if (SCALE_LAST && us == S_LOG - 1) {
-                        gs_bfly_last(v[e], v[e + h], pc, q2);
+                        gs_bfly_last(v[e], v[e + h], pc, off);
                     } else {
                         // in the last round every group starts below 2^DL: index from e only
                         const uint32_t lo_part = ST0 + C == S_LOG ? (uint32_t)(e >> (c + 1))
                                                                   : (uint32_t)((base + (e << DL)) >> (us + 1));
                         const TwPair w = tw[row_or_natural<S_LOG, ROW_A, false>(tw_base, S_LOG - us - 1, t, lo_part)];
-                        gs_bfly(v[e], v[e + h], w.w, w.wp, nq, q2);
+                        gs_bfly<LZ>(v[e], v[e + h], w.w, w.wp, nq, q2, off);
                     }
                 }
             }
@@ -179,24 +194,25 @@ __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, 
 
 // Rounds of a size-2^S_LOG sub-transform from stage ST0 on: radix-kElems rounds,
 // the last one shorter when kElemsLog does not divide S_LOG.
-template <int S_LOG, int ST0, bool FWD, bool SCALE_LAST, int ROW_A>
+template <int S_LOG, int ST0, bool FWD, bool SCALE_LAST, int ROW_A, bool LZ = false>
 __device__ __forceinline__ void ntt_rounds_from(uint64_t *lds, int ldu, int u, int t, uint32_t tw_base,
                                                 const TwPair *__restrict__ tw, const PrimeConst &pc) {
     constexpr int C = (S_LOG - ST0) < kElemsLog ? (S_LOG - ST0) : kElemsLog;
     constexpr bool LAST = ST0 + C == S_LOG;
-    ntt_round<S_LOG, ST0, C, FWD, SCALE_LAST && LAST, ROW_A>(lds, ldu, u, t, tw_base, tw, pc);
+    ntt_round<S_LOG, ST0, C, FWD, SCALE_LAST && LAST, ROW_A, false, false, LZ>(lds, ldu, u, t, tw_base, tw, pc);
     __syncthreads();
-    if constexpr (!LAST) ntt_rounds_from<S_LOG, ST0 + C, FWD, SCALE_LAST, ROW_A>(lds, ldu, u, t, tw_base, tw, pc);
+    if constexpr (!LAST)
+        ntt_rounds_from<S_LOG, ST0 + C, FWD, SCALE_LAST, ROW_A, LZ>(lds, ldu, u, t, tw_base, tw, pc);
 }
 
 // ROW_A: 0 for the natural twiddle table; A for a row pass reading the row table
 // (which needs exactly two rounds: S_LOG in (kElemsLog, 2 kElemsLog]).
-template <int S_LOG, bool FWD, bool SCALE_LAST, int ROW_A = 0>
+template <int S_LOG, bool FWD, bool SCALE_LAST, int ROW_A = 0, bool LZ = false>
 __device__ __forceinline__ void ntt_rounds(uint64_t *lds, int ldu, int u, int t, uint32_t tw_base,
                                            const TwPair *__restrict__ tw, const PrimeConst &pc) {
     static_assert(S_LOG >= 5 && S_LOG <= 12, "sub-transform size");
     static_assert(ROW_A == 0 || (S_LOG > kElemsLog && S_LOG <= 2 * kElemsLog), "row table: two rounds");
-    ntt_rounds_from<S_LOG, 0, FWD, SCALE_LAST, ROW_A>(lds, ldu, u, t, tw_base, tw, pc);
+    ntt_rounds_from<S_LOG, 0, FWD, SCALE_LAST, ROW_A, LZ>(lds, ldu, u, t, tw_base, tw, pc);
 }
 
 // Column pass: sub-transforms are columns (2^A rows, stride 2^B), tile
@@ -232,10 +248,11 @@ __device__ __forceinline__ void ntt_cols_load(uint64_t (&regs)[kElems], int tile
     }
 }
 
-// Ends with a barrier, so lds may be reused at once.
-template <int A, int B, bool FWD>
-__device__ __forceinline__ void ntt_cols_compute(uint64_t *lds, uint64_t *out, const TwPair *__restrict__ tw,
-                                                 const PrimeConst &pc, int tile, uint64_t (&regs)[kElems]) {
+// Ends with a barrier, so lds may be reused at once.  LZ: see ct_bfly; the
+// forward output is then lazy below (4 + 2A) q.
+template <int A, int B, bool FWD, bool LZ>
+__device__ __forceinline__ void ntt_cols_compute_t(uint64_t *lds, uint64_t *out, const TwPair *__restrict__ tw,
+                                                   const PrimeConst &pc, int tile, uint64_t (&regs)[kElems]) {
     constexpr int S = 1 << A;
     constexpr int U = kTile / S;
     constexpr int LDU = U + 1;
@@ -243,9 +260,9 @@ __device__ __forceinline__ void ntt_cols_compute(uint64_t *lds, uint64_t *out, c
     const int col0 = tile * U;
     const int u = threadIdx.x % U, t = threadIdx.x / U;
     if constexpr (FWD) {
-        ntt_round<A, 0, kElemsLog, true, false, 0, true, false>(lds, LDU, u, t, 1u, tw, pc, regs);
+        ntt_round<A, 0, kElemsLog, true, false, 0, true, false, LZ>(lds, LDU, u, t, 1u, tw, pc, regs);
         __syncthreads();
-        ntt_round<A, kElemsLog, C2, true, false, 0>(lds, LDU, u, t, 1u, tw, pc);
+        ntt_round<A, kElemsLog, C2, true, false, 0, false, false, LZ>(lds, LDU, u, t, 1u, tw, pc);
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < kTile / kThreads; ++r) {
@@ -260,11 +277,11 @@ __device__ __forceinline__ void ntt_cols_compute(uint64_t *lds, uint64_t *out, c
             lds[(idx / U) * LDU + idx % U] = regs[r];
         }
         __syncthreads();
-        ntt_round<A, 0, kElemsLog, false, false, 0>(lds, LDU, u, t, 1u, tw, pc);
+        ntt_round<A, 0, kElemsLog, false, false, 0, false, false, LZ>(lds, LDU, u, t, 1u, tw, pc);
         __syncthreads();
         // The last inverse round leaves rows grp + 16 e (grp = t NG + gi) of
         // column u in registers, the order of a coalesced store.
-        ntt_round<A, kElemsLog, C2, false, true, 0, false, true>(lds, LDU, u, t, 1u, tw, pc, regs);
+        ntt_round<A, kElemsLog, C2, false, true, 0, false, true, LZ>(lds, LDU, u, t, 1u, tw, pc, regs);
         constexpr int G = 1 << C2, NG = kElems / G;
 #pragma unroll
         for (int gi = 0; gi < NG; ++gi)
@@ -277,12 +294,24 @@ __device__ __forceinline__ void ntt_cols_compute(uint64_t *lds, uint64_t *out, c
     __syncthreads();
 }
 
-template <int A, int B, bool FWD, typename Pro>
+// LZOK: the butterflies skip the sum corrections for primes below
+// kLazyPrimeBound (the prime is uniform across the workgroup: a scalar
+// branch).  Worth it only in passes whose prologue or epilogue adds ALU work
+// (the two code paths cost registers, so occupancy); the forward column and
+// row passes of a limb must agree on it (the column output range differs).
+template <int A, int B, bool FWD, bool LZOK = false>
+__device__ __forceinline__ void ntt_cols_compute(uint64_t *lds, uint64_t *out, const TwPair *__restrict__ tw,
+                                                 const PrimeConst &pc, int tile, uint64_t (&regs)[kElems]) {
+    if (LZOK && pc.q < kLazyPrimeBound) ntt_cols_compute_t<A, B, FWD, true>(lds, out, tw, pc, tile, regs);
+    else ntt_cols_compute_t<A, B, FWD, false>(lds, out, tw, pc, tile, regs);
+}
+
+template <int A, int B, bool FWD, bool LZOK = false, typename Pro>
 __device__ __forceinline__ void ntt_cols_unit_pro(uint64_t *lds, uint64_t *out, const TwPair *__restrict__ tw,
                                                   const PrimeConst &pc, int tile, const Pro &pro) {
     uint64_t regs[kElems];
     ntt_cols_load<A, B, FWD>(regs, tile, pro);
-    ntt_cols_compute<A, B, FWD>(lds, out, tw, pc, tile, regs);
+    ntt_cols_compute<A, B, FWD, LZOK>(lds, out, tw, pc, tile, regs);
 }
 
 struct LoadPro {
@@ -369,9 +398,9 @@ __device__ __forceinline__ void ntt_rows_load(uint64_t (&regs)[kElems], int tile
     }
 }
 
-template <int A, int B, bool FWD, typename Epi>
-__device__ __forceinline__ void ntt_rows_compute(uint64_t *lds, const TwPair *__restrict__ tw, const PrimeConst &pc,
-                                                 int tile, const Epi &epi, uint64_t (&regs)[kElems]) {
+template <int A, int B, bool FWD, bool LZ, typename Epi>
+__device__ __forceinline__ void ntt_rows_compute_t(uint64_t *lds, const TwPair *__restrict__ tw, const PrimeConst &pc,
+                                                   int tile, const Epi &epi, uint64_t (&regs)[kElems]) {
     constexpr int S = 1 << B;
     constexpr int U = kTile / S;
     constexpr int LDU = U + 1;
@@ -383,31 +412,41 @@ __device__ __forceinline__ void ntt_rows_compute(uint64_t *lds, const TwPair *__
     }
     __syncthreads();
     const int u = threadIdx.x % U, t = threadIdx.x / U;
-    ntt_rounds<B, FWD, false, A>(lds, LDU, u, t, (1u << A) + row0 + u, tw, pc);
+    ntt_rounds<B, FWD, false, A, LZ>(lds, LDU, u, t, (1u << A) + row0 + u, tw, pc);
     const uint64_t q2 = 2 * pc.q;
 #pragma unroll
     for (int r = 0; r < kTile / kThreads; ++r) {
         const int idx = threadIdx.x + r * kThreads;
         const int row = idx >> B, p = idx & (S - 1);
         uint64_t x = lds[p * LDU + row];
-        if (FWD) x = csub(csub(x, q2), pc.q);
+        // LZ values lie below 2^59: one Shoup reduction by 1 brings them to [0, 2q)
+        if (LZ) x -= mulhi64(x, pc.one_p) * pc.q;
+        if (FWD) x = csub(LZ ? x : csub(x, q2), pc.q);
         epi(((size_t)(row0 + row) << B) + p, x);
     }
     __syncthreads();
 }
 
-template <int A, int B, bool FWD, typename Pro, typename Epi>
+// LZOK: as for ntt_cols_compute.
+template <int A, int B, bool FWD, typename Epi, bool LZOK = false>
+__device__ __forceinline__ void ntt_rows_compute(uint64_t *lds, const TwPair *__restrict__ tw, const PrimeConst &pc,
+                                                 int tile, const Epi &epi, uint64_t (&regs)[kElems]) {
+    if (LZOK && pc.q < kLazyPrimeBound) ntt_rows_compute_t<A, B, FWD, true>(lds, tw, pc, tile, epi, regs);
+    else ntt_rows_compute_t<A, B, FWD, false>(lds, tw, pc, tile, epi, regs);
+}
+
+template <int A, int B, bool FWD, bool LZOK = false, typename Pro, typename Epi>
 __device__ __forceinline__ void ntt_rows_unit_pe(uint64_t *lds, const Pro &pro, const TwPair *__restrict__ tw,
                                                  const PrimeConst &pc, int tile, const Epi &epi) {
     uint64_t regs[kElems];
     ntt_rows_load<A, B>(regs, tile, pro);
-    ntt_rows_compute<A, B, FWD>(lds, tw, pc, tile, epi, regs);
+    ntt_rows_compute<A, B, FWD, Epi, LZOK>(lds, tw, pc, tile, epi, regs);
 }
 
-template <int A, int B, bool FWD, typename Epi>
+template <int A, int B, bool FWD, bool LZOK = false, typename Epi>
 __device__ __forceinline__ void ntt_rows_unit_epi(uint64_t *lds, const uint64_t *in, const TwPair *__restrict__ tw,
                                                   const PrimeConst &pc, int tile, const Epi &epi) {
-    ntt_rows_unit_pe<A, B, FWD>(lds, LoadPro{in}, tw, pc, tile, epi);
+    ntt_rows_unit_pe<A, B, FWD, LZOK>(lds, LoadPro{in}, tw, pc, tile, epi);
 }
 
 template <int A, int B, bool FWD>
@@ -484,6 +523,13 @@ struct RescaleTailEpi {
 #endif
 constexpr int kNttWavesCols = RF_NTT_WAVES_COLS;
 constexpr int kNttWavesRows = RF_NTT_WAVES_ROWS;
+// The forward passes with the ModDown conversion / tail and the rescale lift /
+// tail (the lazy butterflies, two code paths): held to 4 waves per SIMD so
+// that they share the CUs with a concurrent stream as the other passes do.
+#ifndef RF_NTT_WAVES_FUSED
+#define RF_NTT_WAVES_FUSED 4
+#endif
+constexpr int kNttWavesFused = RF_NTT_WAVES_FUSED;
 
 // LDS words a column or row unit needs (the largest tile: 2^8 x 17 padded).
 constexpr int kNttLdsWords = 256 * 17;
