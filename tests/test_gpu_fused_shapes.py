@@ -95,3 +95,31 @@ def test_rescale_fused(log_n, k):
     ct = rand_ct(p, nl, rng)
     want = C.rescale(C.Ciphertext(ct, 2.0 ** 40), p).data
     assert np.array_equal(host(ctx.rescale(dev(ct))), want)
+
+
+# Primes just below 2^50 (the largest 50-bit primes) run the fused ModDown and
+# rescale passes' butterflies without sum corrections at the edge of their
+# range; 51-bit primes run the strict butterflies.  N = 2^16 gives the longest
+# chains of uncorrected stages.
+EDGE = dict(scheme="ckks", log_n=16, log_nmax=16, q_bits=[51, 50, 50, 51, 50], p_bits=[50, 51], alpha=2,
+            log_scale=40, seed=2503222290)
+
+
+def test_lazy_bound_edges():
+    from paper_2503_22227_amd import Context
+    p = P.make_params(EDGE)
+    assert max(q for q in p.q + p.p if q < 2 ** 50) > 2 ** 50 - 2 ** 24
+    assert any(q > 2 ** 50 for q in p.q + p.p)
+    ctx = Context(p.q, p.p, p.log_n, p.alpha, log_nmax=p.log_nmax)
+    nl = len(p.q)
+    print("lazy-bound edges log_n=16 nl=%d" % nl, flush=True)
+    rng = np.random.default_rng(77)
+    a, b = rand_ct(p, nl, rng), rand_ct(p, nl, rng)
+    rlk, gk = rand_key(p, rng), rand_key(p, rng)
+    m = ctx.hmult_relin(dev(a), dev(b), dev(rlk))
+    want_m = C.hmult_relin(C.Ciphertext(a, 1.0), C.Ciphertext(b, 1.0), rlk, p)
+    assert np.array_equal(host(m), want_m.data)
+    want_r = C.rescale(C.Ciphertext(want_m.data, 2.0 ** 40), p).data
+    assert np.array_equal(host(ctx.rescale(m)), want_r)
+    g = C.galois_element(synthetic.rotation_index(rng, p.n), p.n)
+    assert np.array_equal(host(ctx.rotate(dev(a), g, dev(gk))), C.rotate(C.Ciphertext(a, 1.0), g, gk, p).data)

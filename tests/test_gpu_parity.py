@@ -112,6 +112,7 @@ HMULT_CASES = [
     ("ckks_n12", None, 1),
     ("ckks_n16_l24", None, 24),   # alpha = 8, dnum = 3
     ("ckks_n16_l24", None, 13),   # a truncated last digit
+    ("ckks_n16_l24", None, 1),    # one digit of one prime (nl + k < alpha)
     ("ckks_n16_l24_a4", None, 24),  # alpha = 4, dnum = 6
     ("ckks_n16_l24_a4", None, 5),  # alpha = 4, digits of 4 and 1
 ]
