@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed-N batch section")
     ap.add_argument("--no-pdq", action="store_true", help="skip the private-query serving section")
     ap.add_argument("--pdq-queries", type=int, default=60, help="queries per arrival-rate point")
+    ap.add_argument("--latency-reps", type=int, default=50, help="individually timed reps per op and cache state")
     ap.add_argument("--no-bfv-bgv", action="store_true", help="skip the BFV/BGV section")
     ap.add_argument("--ntt-microbench", action="store_true",
                     help="only time forward and inverse NTTs of 60 limbs at N=2^16 (kernel profiling)")
@@ -126,6 +127,39 @@ def algorithmic_bytes(kernel: str, nl: int, K: int, alpha: int, n: int, op: str)
         "automorphism": 2 * nl,
     }
     return table[kernel] * limb if kernel in table else float("nan")
+
+
+def latency_section(stream, ops, reps: int):
+    """Per-operation latency distributions: every rep timed on its own with HIP
+    events on the launch stream; median, p10, p90 and the mean of the first 10
+    reps (the paper's protocol).  warm: reps back to back; cold: a 1 GiB buffer
+    is rewritten on the same stream before each rep, which evicts the 256 MiB
+    Infinity Cache and the L2s, so the op starts from HBM."""
+    import numpy as np
+    import torch
+
+    flush = torch.empty(1 << 27, dtype=torch.int64, device="cuda")  # 1 GiB
+    out = {"reps": reps, "flush_bytes": flush.numel() * 8}
+    for mode in ("warm", "cold"):
+        res = {}
+        for name, fn in ops.items():
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+            torch.cuda.synchronize()
+            for e0, e1 in ev:
+                if mode == "cold":
+                    flush.fill_(1)
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+            torch.cuda.synchronize()
+            us = np.array([e0.elapsed_time(e1) * 1e3 for e0, e1 in ev])
+            res[name] = {"median_us": round(float(np.median(us)), 2),
+                         "p10_us": round(float(np.percentile(us, 10)), 2),
+                         "p90_us": round(float(np.percentile(us, 90)), 2),
+                         "mean10_us": round(float(us[:10].mean()), 2)}
+        out[mode] = res
+    del flush
+    return out
 
 
 def _progress(msg: str) -> None:
@@ -225,6 +259,10 @@ def main():
     t_hm = timed(lambda: ctx.hmult_relin(a, b, rlk, out=m_out), reps)
     t_ro = timed(lambda: ctx.rotate(a, g, gk, out=ro_out), reps)
     t_rs = timed(lambda: ctx.rescale(m_out, out=r_out), reps)
+    latency = latency_section(stream, {"hmult_relin": lambda: ctx.hmult_relin(a, b, rlk, out=m_out),
+                                       "hrotate": lambda: ctx.rotate(a, g, gk, out=ro_out),
+                                       "rescale": lambda: ctx.rescale(m_out, out=r_out)}, args.latency_reps)
+    _progress("per-op latency distributions done")
 
     # per-kernel durations from HIP events on the launch stream
     _lib.profile_read()
@@ -313,6 +351,7 @@ def main():
                 "rescale_per_s": round(reps / t_rs, 2),
                 "hmult_relin_us": round(t_hm / reps * 1e6, 2), "hrotate_us": round(t_ro / reps * 1e6, 2),
                 "rescale_us": round(t_rs / reps * 1e6, 2)},
+        "latency": latency,
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in sorted(kernels.items())},
         "roofline": roof,
         "batch": batch,
