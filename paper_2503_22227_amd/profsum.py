@@ -2,10 +2,14 @@
 
     python -m paper_2503_22227_amd.profsum stats  <results.db>
     python -m paper_2503_22227_amd.profsum pmc    <results.db>
+    python -m paper_2503_22227_amd.profsum valu   <results.db>
     python -m paper_2503_22227_amd.profsum traffic <fetch.db> <write.db> <copy_fetch.db> <copy_write.db> <copy_bytes>
 
 ``stats``: per kernel, launches and average / min / max duration.
 ``pmc``: per kernel, launches and the average value of every collected counter.
+``valu``: per kernel, VALU instructions per launch, the fraction of the chip's
+VALU issue slots they take, mean resident waves per SIMD and LDS instructions
+(from SQ_INSTS_VALU, SQ_WAVE_CYCLES, SQ_INSTS_LDS of a --kernel-trace --pmc run).
 ``traffic``: per kernel, HBM bytes per launch from FETCH_SIZE and WRITE_SIZE
 (KiB per dispatch), each scaled by what the same counter reads for a plain
 device copy of ``copy_bytes`` bytes (expected: copy_bytes read and written).
@@ -65,6 +69,43 @@ def pmc(db: str) -> str:
     return "\n".join(lines)
 
 
+def valu(db: str) -> str:
+    """Per-kernel VALU work and occupancy from one rocprofv3 --kernel-trace --pmc run
+    with SQ_WAVES, SQ_INSTS_VALU, SQ_WAVE_CYCLES, SQ_INSTS_LDS (and others).  A
+    counter of a dispatch is the sum over the instances it is reported for.
+    VALU issue = wave-instructions x 4 cycles / (duration x 2.4 GHz x 1024 SIMDs),
+    the fraction of the chip's issue slots if every instruction took 4 cycles;
+    waves/SIMD = SQ_WAVE_CYCLES (quad-cycles) x 4 / (duration cycles x 1024),
+    the mean number of resident waves per SIMD over the kernel."""
+    con = sqlite3.connect(db)
+    disp = {did: (short(n), dur, vg, agpr, lds, scr, gx * gy * gz)
+            for did, n, dur, vg, agpr, lds, scr, gx, gy, gz in con.execute(
+                "select dispatch_id, name, duration, vgpr_count, accum_vgpr_count, lds_size, scratch_size, "
+                "grid_x, grid_y, grid_z from kernels")}
+    sums = defaultdict(lambda: defaultdict(float))
+    for did, cname, v in con.execute("select dispatch_id, counter_name, counter_value from pmc_events"):
+        sums[did][cname] += v
+    con.close()
+    per = defaultdict(list)
+    for did, (n, dur, vg, agpr, lds, scr, threads) in disp.items():
+        per[n].append((dur, vg + agpr, lds, scr, threads, sums.get(did, {})))
+    lines = ["| kernel | launches | avg us | LDS B | scratch B | waves/launch | VALU Minstr/launch "
+             "| VALU issue | waves/SIMD | LDS instr/launch |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+    for n, rows in sorted(per.items(), key=lambda kv: -sum(r[0] for r in kv[1])):
+        k = len(rows)
+        dur = sum(r[0] for r in rows) / k
+        valu_i = sum(r[5].get("SQ_INSTS_VALU", 0.0) for r in rows) / k
+        wcyc = sum(r[5].get("SQ_WAVE_CYCLES", 0.0) for r in rows) / k
+        lds_i = sum(r[5].get("SQ_INSTS_LDS", 0.0) for r in rows) / k
+        cycles = dur * 2.4  # ns -> cycles at 2.4 GHz
+        issue = valu_i * 4 / (cycles * 1024) if cycles else float("nan")
+        occ = wcyc * 4 / (cycles * 1024) if cycles else float("nan")
+        lines.append("| %s | %d | %.2f | %d | %d | %d | %.2f | %.2f | %.2f | %.0f |" % (
+            n, k, dur / 1e3, rows[0][2], rows[0][3], rows[0][4] // 64, valu_i / 1e6, issue, occ, lds_i))
+    return "\n".join(lines)
+
+
 def _avg(per, kernel_pred, cname):
     vals = [v for n, cs in per.items() if kernel_pred(n) for v in cs.get(cname, [])]
     return sum(vals) / len(vals) if vals else float("nan")
@@ -112,6 +153,8 @@ def main(argv):
         print(stats(argv[2]))
     elif mode == "pmc":
         print(pmc(argv[2]))
+    elif mode == "valu":
+        print(valu(argv[2]))
     elif mode == "traffic":
         print(traffic(argv[2], argv[3], argv[4], argv[5], int(argv[6])))
         print()
