@@ -123,8 +123,12 @@ int rf_hmult_relin(const rf_ctx *ctx, const uint64_t *a, const uint64_t *b, cons
 
 /* HRotate: out = (sigma_g(c0) + KS_0(sigma_g(c1)), KS_1(sigma_g(c1))) with
  * sigma_g : a(X) -> a(X^g), g odd in [1, 2N), and gk the key from s(X^g) to s.
- * g = 5^r mod 2N rotates the slots left by r; g = 2N - 1 conjugates.
- * out must not overlap in. */
+ * g = 5^r mod 2N rotates the CKKS slots left by r; g = 2N - 1 conjugates.
+ *   CKKS / BGV: NTT-domain ciphertexts with `n_limbs` Q-limbs.
+ *   BFV: coefficient-domain ciphertexts with all L limbs (RF_ELEVEL otherwise);
+ *   the result decrypts to m(X^g) mod t, a permutation of the batched slots
+ *   (the row and column rotations of the paper's BFV table are such g).
+ * out must not overlap in; workspace of rf_workspace_bytes(RF_OP_ROTATE). */
 int rf_rotate(const rf_ctx *ctx, const uint64_t *in, uint32_t galois_elt, const uint64_t *gk,
               uint64_t *out, uint32_t n_limbs, void *workspace, size_t workspace_bytes,
               void *stream);

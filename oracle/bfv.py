@@ -39,7 +39,8 @@ from .rns import centered, crt, product, to_rns
 
 MTILDE = 1 << 32
 
-__all__ = ["encode", "decode", "encrypt", "decrypt", "hmult_relin", "behz_tensor", "relin_key"]
+__all__ = ["encode", "decode", "encrypt", "decrypt", "hmult_relin", "behz_tensor", "relin_key", "galois_key",
+           "rotate"]
 
 
 def qb_moduli(params: Params):
@@ -165,3 +166,21 @@ def hmult_relin(a: np.ndarray, b: np.ndarray, rlk: np.ndarray, params: Params) -
     k0, k1 = C.keyswitch(ntt_limbs(d2, q, params), rlk, params)
     return np.stack([C.poly_add(d0, intt_limbs(k0, q, params), q),
                      C.poly_add(d1, intt_limbs(k1, q, params), q)])
+
+
+def galois_key(params: Params, s: np.ndarray, g: int, rng) -> np.ndarray:
+    """Key switching key from s(X^g) to s (the hybrid key of the relinearisation)."""
+    return C.galois_key(params, s, g, rng)
+
+
+def rotate(ct: np.ndarray, g: int, gk: np.ndarray, params: Params) -> np.ndarray:
+    """Galois automorphism sigma_g: a(X) -> a(X^g) of both coefficient-domain
+    polynomials (X^(g j) reduced mod X^N + 1), then the key switch of
+    sigma_g(c1) from s(X^g) back to s, in the NTT domain as in the
+    relinearisation: (sigma_g(c0) + KS_0, KS_1).  Decrypts to m(X^g) mod t,
+    which permutes the slots."""
+    q = params.q
+    c0 = np.stack([_core.automorphism_coeff(ct[0, i], params.log_n, g, q[i]) for i in range(len(q))])
+    c1 = np.stack([_core.automorphism_coeff(ct[1, i], params.log_n, g, q[i]) for i in range(len(q))])
+    k0, k1 = C.keyswitch(ntt_limbs(c1, q, params), gk, params)
+    return np.stack([C.poly_add(c0, intt_limbs(k0, q, params), q), intt_limbs(k1, q, params)])

@@ -132,8 +132,9 @@ extern "C" size_t rf_workspace_bytes(const rf_ctx *c, int op, uint32_t nl) {
     if (c->scheme == RF_BFV && op == RF_OP_HMULT_RELIN) return nl == c->L ? bfv_ws_limbs(c) * N * 8 : 0;
     switch (op) {
         case RF_OP_KEYSWITCH: return ks_layout(c, nl).total * 8;
-        case RF_OP_HMULT_RELIN:
-        case RF_OP_ROTATE: return (ks_layout(c, nl).total + (size_t)nl * N) * 8;
+        case RF_OP_HMULT_RELIN: return (ks_layout(c, nl).total + (size_t)nl * N) * 8;
+        // BFV: the NTT of the coefficient-domain input comes first
+        case RF_OP_ROTATE: return (ks_layout(c, nl).total + (size_t)(c->scheme == RF_BFV ? 3 : 1) * nl * N) * 8;
         case RF_OP_RESCALE: return nl < 2 ? 0 : (2 + 2 * (size_t)(nl - 1)) * N * 8;
         case RF_OP_MODSWITCH: return (nl < 2 || c->scheme != RF_BGV) ? 0 : (2 + 2 * (size_t)(nl - 1)) * N * 8;
         default: return 0;
@@ -232,20 +233,13 @@ extern "C" int rf_hmult_relin(const rf_ctx *c, const uint64_t *a, const uint64_t
     return keyswitch_core(c, d2, rlk, out, nl, out, out + poly, ks_ws, s);
 }
 
-extern "C" int rf_rotate(const rf_ctx *c, const uint64_t *in, uint32_t galois, const uint64_t *gk, uint64_t *out,
-                         uint32_t nl, void *ws, size_t ws_bytes, void *stream) {
+// HRotate of an NTT-domain ciphertext (CKKS, BGV) into out; ws holds the
+// automorphism of polynomial 1 and the key-switch workspace.
+static int rotate_ntt(const rf_ctx *c, const uint64_t *in, uint32_t galois, const uint64_t *gk, uint64_t *out,
+                      uint32_t nl, uint64_t *ws, hipStream_t s) {
     int rc;
-    if ((rc = check_level(c, nl))) return rc;
-    if (!in || !gk || !out) return fail(RF_EINVAL, "rf_rotate: null argument");
-    if (overlaps(out, 2 * (size_t)nl * c->n, in, 2 * (size_t)nl * c->n))
-        return fail(RF_EINVAL, "rf_rotate: out overlaps in");
-    if ((galois & 1u) == 0 || galois >= 2u * c->n) return fail(RF_EINVAL, "rf_rotate: Galois element must be odd and < 2N");
-    if (c->scheme == RF_BFV) return fail(RF_EUNSUPPORTED, "rf_rotate: CKKS or BGV (NTT-domain ciphertexts)");
-    if ((rc = check_ws(c, RF_OP_ROTATE, nl, ws, ws_bytes))) return rc;
-    DeviceGuard g(c->device);
-    hipStream_t s = (hipStream_t)stream;
     const size_t poly = (size_t)nl * c->n;
-    uint64_t *d = (uint64_t *)ws;
+    uint64_t *d = ws;
     uint64_t *ks_ws = d + poly;
     if (c->log_n > 12) {
         // sigma_g(a1) is gathered by the first pass of its INTT and, with sigma_g(a0),
@@ -260,6 +254,29 @@ extern "C" int rf_rotate(const rf_ctx *c, const uint64_t *in, uint32_t galois, c
     if ((rc = launch_automorphism(c, in, out, galois, nl, 1, s))) return rc;
     if ((rc = launch_automorphism(c, in + poly, d, galois, nl, 1, s))) return rc;
     return keyswitch_core(c, d, gk, out, nl, out, nullptr, ks_ws, s);
+}
+
+extern "C" int rf_rotate(const rf_ctx *c, const uint64_t *in, uint32_t galois, const uint64_t *gk, uint64_t *out,
+                         uint32_t nl, void *ws, size_t ws_bytes, void *stream) {
+    int rc;
+    if ((rc = check_level(c, nl))) return rc;
+    if (!in || !gk || !out) return fail(RF_EINVAL, "rf_rotate: null argument");
+    if (overlaps(out, 2 * (size_t)nl * c->n, in, 2 * (size_t)nl * c->n))
+        return fail(RF_EINVAL, "rf_rotate: out overlaps in");
+    if ((galois & 1u) == 0 || galois >= 2u * c->n) return fail(RF_EINVAL, "rf_rotate: Galois element must be odd and < 2N");
+    if (c->scheme == RF_BFV && nl != c->L) return fail(RF_ELEVEL, "rf_rotate: BFV ciphertexts carry all L limbs");
+    if ((rc = check_ws(c, RF_OP_ROTATE, nl, ws, ws_bytes))) return rc;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (c->scheme != RF_BFV) return rotate_ntt(c, in, galois, gk, out, nl, (uint64_t *)ws, s);
+    // BFV rests in the coefficient domain.  NTT(sigma_g(a)) is a fixed
+    // permutation of NTT(a), so rotating the NTT of the input and transforming
+    // the result back applies sigma_g (and the key switch) to the coefficients.
+    const size_t poly = (size_t)nl * c->n;
+    uint64_t *x = (uint64_t *)ws;
+    if ((rc = launch_ntt(c, batch(in, x, poly, poly, nl, 2, 0, nullptr), true, s))) return rc;
+    if ((rc = rotate_ntt(c, x, galois, gk, out, nl, x + 2 * poly, s))) return rc;
+    return launch_ntt(c, batch(out, out, poly, poly, nl, 2, 0, nullptr), false, s);
 }
 
 extern "C" int rf_automorphism(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint32_t galois, uint32_t nl,

@@ -1,5 +1,6 @@
-"""GPU parity for BFV HMult+Relin (BEHZ tensor + relinearisation) against the
-oracle, bit for bit, and exact decryption of GPU results with oracle keys."""
+"""GPU parity for BFV HMult+Relin (BEHZ tensor + relinearisation) and HRotate
+(Galois automorphism + key switch of coefficient-domain ciphertexts) against
+the oracle, bit for bit, and exact decryption of GPU results with oracle keys."""
 import numpy as np
 import pytest
 
@@ -64,7 +65,33 @@ def test_bfv_exact_slots_through_gpu():
     assert np.array_equal(F.decrypt(p, s, host(m2)), z12 * z12 % p.t)
 
 
-def test_bfv_rejects_other_levels_and_rotation():
+@pytest.mark.parametrize("log_n", [12, 15])
+def test_bfv_rotate_parity(log_n):
+    p, ctx = context(log_n)
+    rng = np.random.default_rng(200 + log_n)
+    ct = np.stack([synthetic.uniform_residues(rng, p.q, p.n) for _ in range(2)])
+    qp = p.q + p.p
+    gk = np.stack([np.stack([synthetic.uniform_residues(rng, qp, p.n) for _ in range(2)])
+                   for _ in range(p.dnum())])
+    for g in (C.galois_element(synthetic.rotation_index(rng, p.n), p.n), 2 * p.n - 1):
+        print("bfv rotate log_n=%d g=%d" % (log_n, g), flush=True)
+        got = host(ctx.rotate(dev(ct), g, dev(gk)))
+        assert np.array_equal(got, F.rotate(ct, g, gk, p)), g
+
+
+def test_bfv_rotate_permutes_slots_through_gpu():
+    p, ctx = context(15)
+    st = synthetic.streams(synthetic.WORKLOADS["bfv_n15"]["seed"] + 7)
+    s = C.secret_key(p, st["sk"])
+    m = F.encode(synthetic.integer_slots(st["msgs"], p.n, p.t), p)
+    ct = dev(F.encrypt(p, s, m, st["ct_a"], st["ct_e"]))
+    for g in (5, 2 * p.n - 1):
+        gk = dev(F.galois_key(p, s, g, st["galois"]))
+        m_g = np.mod(C.automorphism_coeffs(np.asarray(m, dtype=np.int64), g), p.t)
+        assert np.array_equal(F.decrypt(p, s, host(ctx.rotate(ct, g, gk))), F.decode(m_g, p)), g
+
+
+def test_bfv_rejects_other_levels():
     from paper_2503_22227_amd import RFError
     p, ctx = context(12)
     x = dev(np.zeros((2, p.L - 1, p.n), dtype=np.uint64))
@@ -72,4 +99,4 @@ def test_bfv_rejects_other_levels_and_rotation():
     with pytest.raises((RFError, ValueError)):
         ctx.hmult_relin(x, x, k)
     with pytest.raises(RFError):
-        ctx.rotate(dev(np.zeros((2, p.L, p.n), dtype=np.uint64)), 5, k)
+        ctx.rotate(x, 5, k)

@@ -6,7 +6,10 @@
 * steps 2-4 against big-integer arithmetic: on N=32 the BEHZ tensor equals
   floor(t (a' x b') / Q) mod Q, a' and b' those representatives and the
   products schoolbook over Z, up to an error in [-(L+1), 1] per coefficient;
-* end to end: exact slot products through two multiplications.
+* end to end: exact slot products through two multiplications;
+* rotation: the rotated ciphertext decrypts to the plaintext polynomial with
+  X -> X^g applied (mod X^N + 1, mod t), for rotation elements and the
+  conjugation.
 """
 import numpy as np
 import pytest
@@ -91,3 +94,17 @@ def test_e2e_exact_slots(log_n):
     assert np.array_equal(F.decrypt(p, s, c), z12)
     e = F.hmult_relin(c, c, rlk, p)
     assert np.array_equal(F.decrypt(p, s, e), z12 * z12 % p.t)
+
+
+@pytest.mark.parametrize("g", [5, 25, 3, 63])
+def test_rotation_decrypts_to_the_automorphism(g):
+    p = small_bfv()
+    assert g < 2 * p.n and g % 2 == 1
+    rng = np.random.default_rng(40 + g)
+    s = C.secret_key(p, rng)
+    m = rng.integers(0, p.t, p.n)
+    ct = F.encrypt(p, s, m, rng, rng)
+    rot = F.rotate(ct, g, F.galois_key(p, s, g, rng), p)
+    m_g = np.mod(C.automorphism_coeffs(np.asarray(m, dtype=np.int64), g), p.t)
+    assert np.array_equal(F.decrypt(p, s, rot), F.decode(m_g, p))
+    assert not np.array_equal(F.decrypt(p, s, rot), F.decrypt(p, s, ct))
