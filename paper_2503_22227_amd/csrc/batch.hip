@@ -160,8 +160,8 @@ __device__ __forceinline__ void moddown_cols_pass(uint64_t *lds, const NttJob &J
 // FIRST = the pass that reads b.in (forward: columns; inverse: rows); the
 // second pass works in place on b.out.  TAIL (the forward row pass of
 // NTT(conv)) writes the ModDown result instead.  PRO: the first pass computes
-// its input: 1 = d2 from a, b (INTT of d2), 2 = the ModDown conversion (NTT of
-// conv).  Units [unit0, unit0 + total) of the step; jobs = the items of the
+// its input: 1 = d2 from a, b (INTT of d2), 2 / 3 = the ModDown conversion
+// (NTT of conv) from 4 / up to 8 special primes.  Units [unit0, unit0 + total) of the step; jobs = the items of the
 // ring degree, whose unit_begin values are absolute.
 template <int A, int B, bool FWD, bool FIRST, bool TAIL, int PRO>
 __device__ __forceinline__ void ntt_batched_unit(uint64_t *lds, const NttJob &J, uint32_t u) {
@@ -183,11 +183,11 @@ __device__ __forceinline__ void ntt_batched_unit(uint64_t *lds, const NttJob &J,
         const size_t poly1 = ((size_t)J.nl + li) << LOGN;
         const TensorPro pro{J.ct_a + poly1, J.ct_b + poly1, pc.q, pc.mu1, pc.mu0};
         ntt_rows_unit_pe<A, B, false>(lds, pro, tw, pc, tile, StoreEpi{out});
-    } else if constexpr (PRO == 2) {
-        // first pass of NTT(conv): ModDown conversion of target li of polynomial poly
-        // (specialised for 4 special primes, the generic variant otherwise)
-        if (J.K == 4) moddown_cols_pass<A, B, 4>(lds, J, poly, li, out, tw, pc, tile);
-        else moddown_cols_pass<A, B, 8>(lds, J, poly, li, out, tw, pc, tile);
+    } else if constexpr (PRO == 2 || PRO == 3) {
+        // first pass of NTT(conv): ModDown conversion of target li of polynomial
+        // poly (2: 4 special primes; 3: any K <= 8).  One variant per kernel: both
+        // behind a runtime switch cost the register allocation of the larger.
+        moddown_cols_pass<A, B, PRO == 2 ? 4 : 8>(lds, J, poly, li, out, tw, pc, tile);
     } else if constexpr (TAIL) {
         // limb li of polynomial poly of conv [2][nl][N]: ModDown tail into out
         const size_t lo = ((size_t)poly * (J.nl + J.K) + li) << LOGN;
@@ -207,8 +207,8 @@ __device__ __forceinline__ void ntt_batched_unit(uint64_t *lds, const NttJob &J,
 // FIRST = the pass that reads b.in (forward: columns; inverse: rows); the
 // second pass works in place on b.out.  TAIL (the forward row pass of
 // NTT(conv)) writes the ModDown result instead.  PRO: the first pass computes
-// its input: 1 = d2 from a, b (INTT of d2), 2 = the ModDown conversion (NTT of
-// conv).  Units [unit0, unit0 + total) of the step; jobs = the items of the
+// its input: 1 = d2 from a, b (INTT of d2), 2 / 3 = the ModDown conversion
+// (NTT of conv) from 4 / up to 8 special primes.  Units [unit0, unit0 + total) of the step; jobs = the items of the
 // ring degree, whose unit_begin values are absolute.  LOOP: workgroups walk
 // per_wg consecutive units; otherwise each takes one unit (per_wg == 1).
 template <int A, int B, bool FWD, bool FIRST, bool TAIL, int PRO, bool LOOP>
@@ -245,6 +245,7 @@ struct rf_batch {
     // first unit / unit count of every step inside the group
     struct Group {
         uint32_t log_n, job0, job1;
+        bool k4;  // every item has 4 special primes (the specialised ModDown prologue)
         uint32_t unit0[kStages], units[kStages];
     };
     std::vector<Group> groups;
@@ -351,7 +352,13 @@ int enqueue(rf_batch *p, hipStream_t s, bool profile) {
         case kNttExt1: RF_BLK(A, B, true, false, false, 0); break;                                               \
         case kInttP0: RF_BLK(A, B, false, true, false, 0); break;                                                \
         case kInttP1: RF_BLK(A, B, false, false, false, 0); break;                                               \
-        case kNttConv0: RF_BLK(A, B, true, true, false, 2); break;                                               \
+        case kNttConv0:                                                                                          \
+            if (G.k4) {                                                                                          \
+                RF_BLK(A, B, true, true, false, 2);                                                              \
+            } else {                                                                                             \
+                RF_BLK(A, B, true, true, false, 3);                                                              \
+            }                                                                                                    \
+            break;                                                                                               \
         case kNttConv1: RF_BLK(A, B, true, false, true, 0); break;                                               \
     }
                 switch (G.log_n) {
@@ -417,9 +424,11 @@ extern "C" int rf_batch_create(const rf_batch_item *items, uint32_t n, void *ws,
             rf_batch::Group G{};
             G.log_n = c->log_n;
             G.job0 = i;
+            G.k4 = true;
             for (int st = 0; st < kStages; ++st) G.unit0[st] = acc[st];
             groups.push_back(G);
         }
+        if (c->K != 4) groups.back().k4 = false;
         const uint32_t nl = it.n_limbs;
         const size_t N = c->n;
         const ModupLevel &lv = c->modup_levels[nl];
