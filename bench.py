@@ -625,7 +625,20 @@ def cpu_baseline(w, min_seconds: float = 10.0, max_pairs: int = 12):
     dt = time.perf_counter() - t0
     return {"value": round(2 * pairs / dt, 4), "unit": "ops/s", "cores": 1, "kind": "oracle",
             "sample": "%d HMult+Relin + %d HRotate at N=2^16, 24 limbs, dnum=3 (%.1f s, single thread)"
-                      % (pairs, pairs, dt)}
+                      % (pairs, pairs, dt),
+            "host_cpu": _cpu_model(), "host_logical_cpus": os.cpu_count()}
+
+
+def _cpu_model() -> str:
+    """The timing host's CPU model (Linux /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 if __name__ == "__main__":
