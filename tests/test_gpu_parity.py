@@ -265,3 +265,19 @@ def test_error_codes():
     code = _lib.lib.rf_hmult_relin(ctx._h, a.data_ptr(), a.data_ptr(), rlk.data_ptr(), out.data_ptr(), 3,
                                    small.data_ptr(), 128, None)
     assert code == _lib.RF_ELEVEL
+    # outputs overlapping inputs, Galois elements out of range, empty or
+    # out-of-range limb windows: rejected on the host before any launch
+    ws = ctx.workspace(_lib.RF_OP_HMULT_RELIN, 2)
+    code = _lib.lib.rf_hmult_relin(ctx._h, a.data_ptr(), out.data_ptr(), rlk.data_ptr(), a.data_ptr(), 2,
+                                   ws.data_ptr(), ws.numel() * 8, None)
+    assert code == _lib.RF_EINVAL
+    code = _lib.lib.rf_rotate(ctx._h, a.data_ptr(), 5, rlk.data_ptr(), a.data_ptr(), 2, ws.data_ptr(),
+                              ws.numel() * 8, None)
+    assert code == _lib.RF_EINVAL
+    code = _lib.lib.rf_rotate(ctx._h, a.data_ptr(), 2 * p.n + 1, rlk.data_ptr(), out.data_ptr(), 2, ws.data_ptr(),
+                              ws.numel() * 8, None)
+    assert code == _lib.RF_EINVAL
+    for first, nl in ((0, 0), (p.L + p.k - 1, 2)):
+        assert _lib.lib.rf_ntt(ctx._h, a.data_ptr(), first, nl, 1, None) == _lib.RF_ELEVEL
+        assert _lib.lib.rf_intt(ctx._h, a.data_ptr(), first, nl, 1, None) == _lib.RF_ELEVEL
+    assert _lib.lib.rf_ntt(ctx._h, None, 0, 1, 1, None) == _lib.RF_EINVAL
