@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed-N batch section")
     ap.add_argument("--no-pdq", action="store_true", help="skip the private-query serving section")
     ap.add_argument("--pdq-queries", type=int, default=60, help="queries per arrival-rate point")
-    ap.add_argument("--latency-reps", type=int, default=50, help="individually timed reps per op and cache state")
+    ap.add_argument("--latency-reps", type=int, default=50, help="individually timed reps per op and cache state (0: skip)")
     ap.add_argument("--no-bfv-bgv", action="store_true", help="skip the BFV/BGV section")
     ap.add_argument("--ntt-microbench", action="store_true",
                     help="only time forward and inverse NTTs of 60 limbs at N=2^16 (kernel profiling)")
@@ -259,10 +259,12 @@ def main():
     t_hm = timed(lambda: ctx.hmult_relin(a, b, rlk, out=m_out), reps)
     t_ro = timed(lambda: ctx.rotate(a, g, gk, out=ro_out), reps)
     t_rs = timed(lambda: ctx.rescale(m_out, out=r_out), reps)
-    latency = latency_section(stream, {"hmult_relin": lambda: ctx.hmult_relin(a, b, rlk, out=m_out),
-                                       "hrotate": lambda: ctx.rotate(a, g, gk, out=ro_out),
-                                       "rescale": lambda: ctx.rescale(m_out, out=r_out)}, args.latency_reps)
-    _progress("per-op latency distributions done")
+    latency = None
+    if args.latency_reps > 0:
+        latency = latency_section(stream, {"hmult_relin": lambda: ctx.hmult_relin(a, b, rlk, out=m_out),
+                                           "hrotate": lambda: ctx.rotate(a, g, gk, out=ro_out),
+                                           "rescale": lambda: ctx.rescale(m_out, out=r_out)}, args.latency_reps)
+        _progress("per-op latency distributions done")
 
     # per-kernel durations from HIP events on the launch stream
     _lib.profile_read()
