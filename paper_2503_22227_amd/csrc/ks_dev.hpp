@@ -145,9 +145,9 @@ __device__ __forceinline__ void inner_product_unit(const uint64_t *__restrict__ 
             s0.mac(x0, y0);
             s1.mac(x0, y1);
             s1.mac(x1, y0);
-            own = barrett128(s2.value(), pc.mu1, pc.mu0, pc.q);
-            ad0 = barrett128(s0.value(), pc.mu1, pc.mu0, pc.q);
-            ad1 = barrett128(s1.value(), pc.mu1, pc.mu0, pc.q);
+            own = reduce128(s2.value(), pc.q, pc.r64, pc.r64_p, pc.one_p);
+            ad0 = reduce128(s0.value(), pc.q, pc.r64, pc.r64_p, pc.one_p);
+            ad1 = reduce128(s1.value(), pc.q, pc.r64, pc.r64_p, pc.one_p);
         } else {
             const size_t src = lo + galois_src((uint32_t)n, fold.galois, log_n);
             own = fold.a[poly + src];
@@ -171,8 +171,11 @@ __device__ __forceinline__ void inner_product_unit(const uint64_t *__restrict__ 
         mac(acc1, src, kj[key_poly]);
     }
     const size_t out_poly = (size_t)(nl + K) << log_n;
-    uint64_t r0 = barrett128(acc0, pc.mu1, pc.mu0, pc.q);
-    uint64_t r1 = barrett128(acc1, pc.mu1, pc.mu0, pc.q);
+    // [0, 4q): the Shoup product by P^-1 takes any 64-bit input, the other
+    // outputs are made canonical below
+    uint64_t r0 = reduce128_lazy(acc0, pc.q, pc.r64, pc.r64_p, pc.one_p);
+    uint64_t r1 = reduce128_lazy(acc1, pc.q, pc.r64, pc.r64_p, pc.one_p);
+    const uint64_t q2 = 2 * pc.q;
     if (fold.pinv && m < nl) {
         const uint64_t pinv = fold.pinv[2 * m], pinv_p = fold.pinv[2 * m + 1];
         r0 = shoup(r0, pinv, pinv_p, pc.q);
@@ -187,6 +190,9 @@ __device__ __forceinline__ void inner_product_unit(const uint64_t *__restrict__ 
             if (fold.add0) r0 = addmod(r0, fold.add0[lo + n], pc.q);
             if (fold.add1) r1 = addmod(r1, fold.add1[lo + n], pc.q);
         }
+    } else {
+        r0 = csub(csub(r0, q2), pc.q);
+        r1 = csub(csub(r1, q2), pc.q);
     }
     ip[((size_t)m << log_n) + n] = r0;
     ip[out_poly + ((size_t)m << log_n) + n] = r1;

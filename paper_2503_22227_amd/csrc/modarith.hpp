@@ -179,6 +179,13 @@ __device__ __forceinline__ uint64_t reduce128_lazy(u128 x, uint64_t q, uint64_t 
     return a + b;
 }
 
+// x mod q in [0, q) for any 128-bit x by reduce128_lazy and two conditional
+// subtractions (cheaper than barrett128: two Shoup products instead of three
+// high products).
+__device__ __forceinline__ uint64_t reduce128(u128 x, uint64_t q, uint64_t r64, uint64_t r64_p, uint64_t one_p) {
+    return csub(csub(reduce128_lazy(x, q, r64, r64_p, one_p), 2 * q), q);
+}
+
 // 64-bit x mod q (x < 2^64) with the same constants.
 __device__ __forceinline__ uint64_t barrett64(uint64_t x, uint64_t mu1, uint64_t mu0, uint64_t q) {
     uint64_t c0 = mulhi64(x, mu0);
