@@ -181,7 +181,7 @@ __device__ __forceinline__ void ntt_batched_unit(uint64_t *lds, const NttJob &J,
     if constexpr (PRO == 1) {
         // first pass of INTT(d2): d2 = a1 b1 of limb li
         const size_t poly1 = ((size_t)J.nl + li) << LOGN;
-        const TensorPro pro{J.ct_a + poly1, J.ct_b + poly1, pc.q, pc.mu1, pc.mu0};
+        const TensorPro pro{J.ct_a + poly1, J.ct_b + poly1, pc.q, pc.r64, pc.r64_p, pc.one_p};
         ntt_rows_unit_pe<A, B, false>(lds, pro, tw, pc, tile, StoreEpi{out});
     } else if constexpr (PRO == 2 || PRO == 3) {
         // first pass of NTT(conv): ModDown conversion of target li of polynomial

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
     const uint32_t i = blockIdx.y;
     const PrimeConst pc = pcs[i];
     const size_t li = (size_t)i << LOGN, poly = (size_t)nl << LOGN;
-    const TensorPro pro{a + poly + li, b + poly + li, pc.q, pc.mu1, pc.mu0};
+    const TensorPro pro{a + poly + li, b + poly + li, pc.q, pc.r64, pc.r64_p, pc.one_p};
     ntt_rows_unit_pe<A, B, false>(lds, pro, tw_all + li, pc, blockIdx.x, StoreEpi{dc + li});
 }
 

@@ -456,14 +456,15 @@ __device__ __forceinline__ void ntt_rows_unit(uint64_t *lds, const uint64_t *in,
 }
 
 // HMult: d2 = a1 b1 mod q as the prologue of the INTT of d2 (the inner product
-// computes d0, d1 and its own d2 residues from a and b itself).
+// computes d0, d1 and its own d2 residues from a and b itself), lazy in
+// [0, 2q), the range the inverse butterflies accept.
 struct TensorPro {
     const uint64_t *a1, *b1;  // limb i of a1, b1
-    uint64_t q, mu1, mu0;
+    uint64_t q, r64, r64_p, one_p;
     __device__ __forceinline__ uint64_t operator()(size_t idx) const {
         MacAcc s2;
         s2.mac(a1[idx], b1[idx]);
-        return barrett128(s2.value(), mu1, mu0, q);
+        return csub(reduce128_lazy(s2.value(), q, r64, r64_p, one_p), 2 * q);
     }
 };
 
