@@ -73,9 +73,11 @@ NttBatch batch(const uint64_t *in, uint64_t *out, uint64_t in_stride, uint64_t o
 // fused (two-pass ring degrees only): d is not materialised; the workspace's
 // d_coeff region already holds INTT(d) (launch_intt_first) and the inner
 // product takes d's residues and the addends from fused's sources.
+// d_coeff_in (nullable): d in the coefficient domain, given by the caller
+// (BFV's fast floor produces it), which replaces the INTT of d.
 int keyswitch_core(const rf_ctx *c, const uint64_t *d, const uint64_t *evk, uint64_t *out, uint32_t nl,
                    const uint64_t *add0, const uint64_t *add1, uint64_t *ws, hipStream_t s,
-                   const IpFold *fused = nullptr) {
+                   const IpFold *fused = nullptr, const uint64_t *d_coeff_in = nullptr) {
     const KsLayout l = ks_layout(c, nl);
     const size_t N = c->n;
     const ModupLevel &lv = c->modup_levels[nl];
@@ -84,11 +86,11 @@ int keyswitch_core(const rf_ctx *c, const uint64_t *d, const uint64_t *evk, uint
     // ModUp: INTT of d, base conversion of each digit, NTT of the new limbs.
     // Two-pass ring degrees: the INTT folds in the conversion's input factor
     // (pc_modup; launch_intt_first does the same for the fused callers).
-    const bool scaled = c->log_n > 12;
-    if (!fused && (rc = launch_ntt(c, batch(d, d_coeff, 0, 0, nl, 1, 0, nullptr), false, s,
-                                   scaled ? pc_modup(c, nl) : nullptr)))
+    const bool scaled = c->log_n > 12 && !d_coeff_in;
+    if (!fused && !d_coeff_in &&
+        (rc = launch_ntt(c, batch(d, d_coeff, 0, 0, nl, 1, 0, nullptr), false, s, scaled ? pc_modup(c, nl) : nullptr)))
         return rc;
-    if ((rc = launch_modup_bconv(c, d_coeff, ext, nl, s, scaled))) return rc;
+    if ((rc = launch_modup_bconv(c, d_coeff_in ? d_coeff_in : d_coeff, ext, nl, s, scaled))) return rc;
     if ((rc = launch_ntt(c, batch(ext, ext, 0, 0, lv.ext_limbs, 1, 0, c->d_pmaps + lv.pmap_off), true, s))) return rc;
     // ModDown: INTT of the P-limbs, base conversion to Q_l, NTT, subtract and scale by P^-1
     const uint64_t ip_stride = (uint64_t)(nl + c->K) * N;
@@ -195,8 +197,11 @@ static int bfv_hmult_relin(const rf_ctx *c, const uint64_t *a, const uint64_t *b
     if ((rc = launch_tensor_map(c, ext, ext + 2 * wstride, tens, tens + 2 * wstride, W, c->d_pmap_qb, s))) return rc;
     if ((rc = launch_ntt(c, batch(tens, tens, wstride, wstride, W, 3, 0, c->d_pmap_qb), false, s))) return rc;
     if ((rc = launch_behz_floor_sk(c, tens, out, d2, s))) return rc;
-    if ((rc = launch_ntt(c, batch(d2, d2, 0, 0, c->L, 1, 0, nullptr), true, s))) return rc;
-    if ((rc = keyswitch_core(c, d2, rlk, ks, c->L, nullptr, nullptr, ks_ws, s))) return rc;
+    // the key switch takes d2 in both domains: the NTT (into the free tensor
+    // region) for its inner product, the coefficients for its ModUp
+    uint64_t *d2n = tens;
+    if ((rc = launch_ntt(c, batch(d2, d2n, 0, 0, c->L, 1, 0, nullptr), true, s))) return rc;
+    if ((rc = keyswitch_core(c, d2n, rlk, ks, c->L, nullptr, nullptr, ks_ws, s, nullptr, d2))) return rc;
     if ((rc = launch_ntt(c, batch(ks, ks, L * N, L * N, c->L, 2, 0, nullptr), false, s))) return rc;
     return launch_ewise(c, 0, out, ks, 0, out, c->L, 2, s);
 }
