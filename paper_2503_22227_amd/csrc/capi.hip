@@ -196,7 +196,8 @@ static int bfv_hmult_relin(const rf_ctx *c, const uint64_t *a, const uint64_t *b
     if ((rc = launch_ntt(c, batch(ext, ext, wstride, wstride, W, 4, 0, c->d_pmap_qb), true, s))) return rc;
     if ((rc = launch_tensor_map(c, ext, ext + 2 * wstride, tens, tens + 2 * wstride, W, c->d_pmap_qb, s))) return rc;
     if ((rc = launch_ntt(c, batch(tens, tens, wstride, wstride, W, 3, 0, c->d_pmap_qb), false, s))) return rc;
-    if ((rc = launch_behz_floor_sk(c, tens, out, d2, s))) return rc;
+    // the fast floor's B_sk residues go through the extension region, free after the tensor
+    if ((rc = launch_behz_floor_sk(c, tens, ext, out, d2, s))) return rc;
     // the key switch takes d2 in both domains: the NTT (into the free tensor
     // region) for its inner product, the coefficients for its ModUp
     uint64_t *d2n = tens;

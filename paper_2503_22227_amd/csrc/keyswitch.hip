@@ -34,11 +34,18 @@ __global__ __launch_bounds__(kEw) void behz_extend_kernel(const uint64_t *a, con
     behz_extend_unit(a, b, ext, pcs, tab, o, kb, log_n, blockIdx.x, blockIdx.y);
 }
 
-__global__ __launch_bounds__(kEw) void behz_floor_sk_kernel(const uint64_t *tens, uint64_t *out01, uint64_t *out2,
-                                                            const PrimeConst *__restrict__ pcs,
-                                                            const uint64_t *__restrict__ tab, BehzLayout o,
-                                                            uint32_t kb, uint32_t log_n) {
-    behz_floor_sk_unit(tens, out01, out2, pcs, tab, o, kb, log_n, blockIdx.x, blockIdx.y);
+__global__ __launch_bounds__(kEw) void behz_floor_kernel(const uint64_t *tens, uint64_t *f,
+                                                         const PrimeConst *__restrict__ pcs,
+                                                         const uint64_t *__restrict__ tab, BehzLayout o, uint32_t kb,
+                                                         uint32_t log_n) {
+    behz_floor_unit(tens, f, pcs, tab, o, kb, log_n, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(kEw) void behz_sk_kernel(const uint64_t *f, uint64_t *out01, uint64_t *out2,
+                                                      const PrimeConst *__restrict__ pcs,
+                                                      const uint64_t *__restrict__ tab, BehzLayout o, uint32_t kb,
+                                                      uint32_t log_n) {
+    behz_sk_unit(f, out01, out2, pcs, tab, o, kb, log_n, blockIdx.x, blockIdx.y);
 }
 
 template <bool SCALED>
@@ -132,10 +139,17 @@ int launch_behz_extend(const rf_ctx *c, const uint64_t *a, const uint64_t *b, ui
     return check_launch("behz_extend");
 }
 
-int launch_behz_floor_sk(const rf_ctx *c, const uint64_t *tens, uint64_t *out01, uint64_t *out2, hipStream_t s) {
-    ProfScope prof("behz_floor_sk", s);
-    hipLaunchKernelGGL(behz_floor_sk_kernel, ew_grid(c, 3), dim3(kEw), 0, s, tens, out01, out2, c->d_pc, c->d_behz,
-                       c->behz, c->L + c->K, c->log_n);
+int launch_behz_floor_sk(const rf_ctx *c, const uint64_t *tens, uint64_t *f, uint64_t *out01, uint64_t *out2,
+                         hipStream_t s) {
+    const uint32_t kb = c->L + c->K;
+    {
+        ProfScope prof("behz_floor", s);
+        hipLaunchKernelGGL(behz_floor_kernel, ew_grid(c, 3 * behz_groups(c->nb + 1)), dim3(kEw), 0, s, tens, f,
+                           c->d_pc, c->d_behz, c->behz, kb, c->log_n);
+    }
+    ProfScope prof("behz_sk", s);
+    hipLaunchKernelGGL(behz_sk_kernel, ew_grid(c, 3 * behz_groups(c->L)), dim3(kEw), 0, s, f, out01, out2, c->d_pc,
+                       c->d_behz, c->behz, kb, c->log_n);
     return check_launch("behz_floor_sk");
 }
 

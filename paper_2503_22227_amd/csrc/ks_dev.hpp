@@ -401,18 +401,26 @@ __device__ __forceinline__ void behz_extend_unit(const uint64_t *a, const uint64
     }
 }
 
-// BEHZ steps 3-4 for one polynomial d on q u B_sk (coefficient domain, gy selects
-// d0, d1, d2 of tens = [3][L + nb + 1][N]): fast floor of t d / Q into B_sk, then
-// the Shenoy-Kumaresan conversion B_sk -> q.  d0, d1 go to out01 = [2][L][N],
-// d2 to out2 = [L][N].
-__device__ __forceinline__ void behz_floor_sk_unit(const uint64_t *tens, uint64_t *out01, uint64_t *out2,
-                                                   const PrimeConst *__restrict__ pcs,
-                                                   const uint64_t *__restrict__ tab, BehzLayout o, uint32_t kb,
-                                                   uint32_t log_n, uint32_t gx, uint32_t gy) {
+// BEHZ fast floor and Shenoy-Kumaresan conversion, split over groups of
+// kBehzGroup output limbs so that a launch has several threads per
+// coefficient (one thread per coefficient and every limb left 1.5 waves per
+// SIMD, each running thousands of dependent instructions); the per-coefficient
+// inputs shared by a group are recomputed by each.
+constexpr int kBehzGroup = 4;
+
+__host__ __device__ inline uint32_t behz_groups(uint32_t limbs) { return (limbs + kBehzGroup - 1) / kBehzGroup; }
+
+// Fast floor into B_sk of polynomial gy / behz_groups(nb + 1), outputs
+// m = kBehzGroup (gy % behz_groups(nb + 1)) + k: f_m = (t d_m - conv_m) Q^-1
+// mod bsk_m, into f [3][nb+1][N].
+__device__ __forceinline__ void behz_floor_unit(const uint64_t *tens, uint64_t *f, const PrimeConst *__restrict__ pcs,
+                                                const uint64_t *__restrict__ tab, BehzLayout o, uint32_t kb,
+                                                uint32_t log_n, uint32_t gx, uint32_t gy) {
     const uint32_t L = o.L, nb = o.nb, W = L + nb + 1;
+    const uint32_t ng = behz_groups(nb + 1);
+    const uint32_t poly = gy / ng, m0 = (gy - poly * ng) * kBehzGroup;
     const size_t n = (size_t)gx * kEw + threadIdx.x;
-    const uint64_t *d = tens + (((size_t)gy * W) << log_n) + n;
-    uint64_t *out = (gy < 2 ? out01 + (((size_t)gy * L) << log_n) : out2) + n;
+    const uint64_t *d = tens + (((size_t)poly * W) << log_n) + n;
     uint64_t z[kMaxBfvLimbs];
 #pragma unroll
     for (int i = 0; i < kMaxBfvLimbs; ++i) {
@@ -421,44 +429,59 @@ __device__ __forceinline__ void behz_floor_sk_unit(const uint64_t *tens, uint64_
             z[i] = shoup(d[(size_t)i << log_n], tab[o.floor_factor + 2 * i], tab[o.floor_factor + 2 * i + 1],
                          pcs[i].q);
     }
-    // fast floor into B_sk: f_m = (t d_m - conv_m) Q^-1 mod bsk_m
-    uint64_t f[kMaxBfvLimbs + 1];
 #pragma unroll
-    for (int m = 0; m <= kMaxBfvLimbs; ++m) {
-        f[m] = 0;
-        if (m <= (int)nb) {
+    for (int k = 0; k < kBehzGroup; ++k) {
+        const uint32_t m = m0 + k;
+        if (m <= nb) {
             const PrimeConst pc = pcs[kb + m];
             const u128 acc =
                 dot_wide<kMaxBfvLimbs>(z, [&](int i) { return tab[o.cross_q_bsk + i * (nb + 1) + m]; }, L);
             const uint64_t conv = barrett128(acc, pc.mu1, pc.mu0, pc.q);
             const uint64_t td = shoup(d[(size_t)(L + m) << log_n], tab[o.t_bsk + 2 * m], tab[o.t_bsk + 2 * m + 1],
                                       pc.q);
-            f[m] = shoup(submod(td, conv, pc.q), tab[o.qinv_bsk + 2 * m], tab[o.qinv_bsk + 2 * m + 1], pc.q);
+            f[(((size_t)poly * (nb + 1) + m) << log_n) + n] =
+                shoup(submod(td, conv, pc.q), tab[o.qinv_bsk + 2 * m], tab[o.qinv_bsk + 2 * m + 1], pc.q);
         }
     }
-    // Shenoy-Kumaresan: w_j = f_j (M/b_j)^-1 mod b_j, alpha from the m_sk residue
+}
+
+// Shenoy-Kumaresan conversion B_sk -> q of polynomial gy / behz_groups(L),
+// outputs i = kBehzGroup (gy % behz_groups(L)) + k: w_j = f_j (M/b_j)^-1 mod
+// b_j, alpha from the m_sk residue (centred), out_i = sum_j w_j [M/b_j]_{q_i}
+// - alpha M mod q_i; polynomials 0, 1 to out01 [2][L][N], 2 to out2 [L][N].
+__device__ __forceinline__ void behz_sk_unit(const uint64_t *f, uint64_t *out01, uint64_t *out2,
+                                             const PrimeConst *__restrict__ pcs, const uint64_t *__restrict__ tab,
+                                             BehzLayout o, uint32_t kb, uint32_t log_n, uint32_t gx, uint32_t gy) {
+    const uint32_t L = o.L, nb = o.nb;
+    const uint32_t ng = behz_groups(L);
+    const uint32_t poly = gy / ng, i0 = (gy - poly * ng) * kBehzGroup;
+    const size_t n = (size_t)gx * kEw + threadIdx.x;
+    const uint64_t *fp = f + (((size_t)poly * (nb + 1)) << log_n) + n;
     uint64_t w[kMaxBfvLimbs];
 #pragma unroll
     for (int j = 0; j < kMaxBfvLimbs; ++j) {
         w[j] = 0;
-        if (j < (int)nb) w[j] = shoup(f[j], tab[o.sk_factor + 2 * j], tab[o.sk_factor + 2 * j + 1], pcs[kb + j].q);
+        if (j < (int)nb)
+            w[j] = shoup(fp[(size_t)j << log_n], tab[o.sk_factor + 2 * j], tab[o.sk_factor + 2 * j + 1], pcs[kb + j].q);
     }
     const u128 acc_msk = dot_wide<kMaxBfvLimbs>(w, [&](int j) { return tab[o.cross_b_msk + j]; }, nb);
     const PrimeConst pm = pcs[kb + nb];
-    uint64_t fmsk = 0;
-#pragma unroll
-    for (int m = 0; m <= kMaxBfvLimbs; ++m)
-        if (m == (int)nb) fmsk = f[m];
+    const uint64_t fmsk = fp[(size_t)nb << log_n];
     const uint64_t cmsk = barrett128(acc_msk, pm.mu1, pm.mu0, pm.q);
     const uint64_t alpha = shoup(submod(cmsk, fmsk, pm.q), tab[o.minv_msk], tab[o.minv_msk + 1], pm.q);
     const bool neg = alpha > (pm.q >> 1);
     const uint64_t amag = neg ? pm.q - alpha : alpha;
-    for (uint32_t i = 0; i < L; ++i) {
-        const PrimeConst pc = pcs[i];
-        const u128 acc = dot_wide<kMaxBfvLimbs>(w, [&](int j) { return tab[o.cross_b_q + j * L + i]; }, nb);
-        const uint64_t r = barrett128(acc, pc.mu1, pc.mu0, pc.q);
-        const uint64_t am = mulmod(barrett64(amag, pc.mu1, pc.mu0, pc.q), tab[o.m_q + i], pc.mu1, pc.mu0, pc.q);
-        out[(size_t)i << log_n] = neg ? addmod(r, am, pc.q) : submod(r, am, pc.q);
+    uint64_t *out = (poly < 2 ? out01 + (((size_t)poly * L) << log_n) : out2) + n;
+#pragma unroll
+    for (int k = 0; k < kBehzGroup; ++k) {
+        const uint32_t i = i0 + k;
+        if (i < L) {
+            const PrimeConst pc = pcs[i];
+            const u128 acc = dot_wide<kMaxBfvLimbs>(w, [&](int j) { return tab[o.cross_b_q + j * L + i]; }, nb);
+            const uint64_t r = barrett128(acc, pc.mu1, pc.mu0, pc.q);
+            const uint64_t am = mulmod(barrett64(amag, pc.mu1, pc.mu0, pc.q), tab[o.m_q + i], pc.mu1, pc.mu0, pc.q);
+            out[(size_t)i << log_n] = neg ? addmod(r, am, pc.q) : submod(r, am, pc.q);
+        }
     }
 }
 

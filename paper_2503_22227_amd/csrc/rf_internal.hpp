@@ -219,7 +219,10 @@ int launch_rescale_tail(const rf_ctx *c, const uint64_t *in, const uint64_t *lif
 int launch_ewise(const rf_ctx *c, int op, const uint64_t *a, const uint64_t *b, int64_t k, uint64_t *out,
                  uint32_t nl, uint32_t n_polys, hipStream_t s);
 int launch_behz_extend(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *ext, hipStream_t s);
-int launch_behz_floor_sk(const rf_ctx *c, const uint64_t *tens, uint64_t *out01, uint64_t *out2, hipStream_t s);
+// BEHZ fast floor (into f [3][nb+1][N], scratch) and Shenoy-Kumaresan
+// conversion of tens = [3][L+nb+1][N]: d0, d1 to out01 [2][L][N], d2 to out2 [L][N].
+int launch_behz_floor_sk(const rf_ctx *c, const uint64_t *tens, uint64_t *f, uint64_t *out01, uint64_t *out2,
+                         hipStream_t s);
 int launch_tensor_map(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *d01, uint64_t *d2,
                       uint32_t nl, const uint8_t *pmap, hipStream_t s);
 int launch_automorphism(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint32_t galois,
