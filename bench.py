@@ -162,6 +162,25 @@ def latency_section(stream, ops, reps: int):
     return out
 
 
+def _copy_bandwidth(stream, nbytes: int = 256 << 20, reps: int = 5) -> float:
+    """GB/s (bytes read + written) of a plain device-to-device copy of ``nbytes``,
+    the best of ``reps`` event-timed copies on the launch stream."""
+    import torch
+
+    src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        dst.copy_(src)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    return 2 * nbytes / best / 1e9
+
+
 def _progress(msg: str) -> None:
     """One line per finished section on stderr (stdout carries only the result line)."""
     print("[bench] " + msg, file=sys.stderr, flush=True)
@@ -306,9 +325,13 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_frac, 4)}
+    copy_gbs = _copy_bandwidth(stream)
     roof.update({"traffic": traffic, "kernel": dominant, "avg_us": round(kd["avg_us"], 3),
                  "alu_frac": round(alu_frac, 4), "hbm_frac": round(hbm_frac, 4),
-                 "algorithmic_bytes": round(by), "work_per_launch": work})
+                 "algorithmic_bytes": round(by), "work_per_launch": work,
+                 # what a plain device copy reaches on this GPU, measured here: the
+                 # practical ceiling a streaming kernel is compared with
+                 "copy_gbs": round(copy_gbs, 1), "hbm_frac_of_copy": round(hbm / copy_gbs, 4)})
 
     _progress("timed steps and kernel roofline done")
     batch = None
