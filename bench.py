@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--workload", default="ckks_n16_l24")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (HBM counter calibration)")
+    ap.add_argument("--section", choices=("batch", "bfv-bgv"),
+                    help="only run this section with --steps repetitions and print its JSON (kernel profiling)")
     return ap.parse_args()
 
 
@@ -197,6 +199,10 @@ def main():
         return
     if args.ntt_microbench:
         ntt_microbench(args.steps)
+        return
+    if args.section:
+        fn = batch_section if args.section == "batch" else bfv_bgv_section
+        print(json.dumps({"section": args.section, "reps": args.steps, "result": fn(args.steps)}), flush=True)
         return
 
     import numpy as np
