@@ -74,3 +74,15 @@ def test_modup_and_pass_bytes():
     # ModUp column pass: 60 limbs read and written once
     limbs, by = bench._ntt_launch_model("ntt_fwd_cols", 24, 4, 8, N16)
     assert limbs == 60 and by == 2 * 60 * LIMB
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the multi-GPU layout is described, not built: the bench says so and exits 2
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                         stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=120)
+    assert res.returncode == 2
+    assert "single MI355X" in res.stdout and "--gpus 2" in res.stdout
