@@ -4,6 +4,6 @@ behind the C ABI of include/rnsfhe.h.  This package holds the ctypes binding
 (``fhe``), the prime-chain derivation (``params``) and the build script."""
 from . import params  # noqa: F401
 from ._lib import RFError, lib  # noqa: F401  (raises ImportError when the library is not built)
-from .fhe import BatchPlan, Context, galois_element  # noqa: F401
+from .fhe import BatchPlan, Context  # noqa: F401
 
-__all__ = ["BatchPlan", "Context", "galois_element", "RFError", "params", "lib"]
+__all__ = ["BatchPlan", "Context", "RFError", "params", "lib"]

@@ -11,11 +11,13 @@ import os
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("RF_LIBRARY") or os.path.join(_PKG, "librnsfhe.so")
 
-RF_OK, RF_EINVAL, RF_ELEVEL, RF_EDOMAIN, RF_EWORKSPACE, RF_EHIP, RF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+RF_OK, RF_EINVAL, RF_ELEVEL, RF_EWORKSPACE, RF_EHIP, RF_EUNSUPPORTED = 0, -1, -2, -4, -5, -6
 RF_CKKS, RF_BFV, RF_BGV = 0, 1, 2
 RF_OP_HMULT_RELIN, RF_OP_ROTATE, RF_OP_RESCALE, RF_OP_KEYSWITCH, RF_OP_MODSWITCH = 1, 2, 3, 4, 5
+RF_OP_ENCODE, RF_OP_DECODE = 6, 7
 
 _u64p = ctypes.POINTER(ctypes.c_uint64)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
 _vp = ctypes.c_void_p
 _u32 = ctypes.c_uint32
 _sz = ctypes.c_size_t
@@ -68,6 +70,14 @@ _SIGS = {
     "rf_modswitch": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _sz, _vp]),
     "rf_tensor": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32, _vp]),
     "rf_automorphism": (ctypes.c_int, [_vp, _vp, _vp, _u32, _u32, _u32, _vp]),
+    "rf_galois_element": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int, _u32p]),
+    "rf_key_ntt": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "rf_keygen_switch": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp, _vp]),
+    "rf_encrypt_sk": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _u32, _vp]),
+    "rf_decrypt": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32, _vp]),
+    "rf_crt_centered": (ctypes.c_int, [_vp, _vp, _vp, _u32, ctypes.c_double, _vp]),
+    "rf_encode_ckks": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _vp, _vp, _sz, _vp]),
+    "rf_decode_ckks": (ctypes.c_int, [_vp, _vp, _vp, _vp, _sz, _vp]),
     "rf_add": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32, _u32, _vp]),
     "rf_sub": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32, _u32, _vp]),
     "rf_mul_scalar": (ctypes.c_int, [_vp, _vp, ctypes.c_int64, _vp, _u32, _u32, _vp]),

@@ -1,26 +1,32 @@
 // Batched HMult+Relin over many ciphertexts of different ring degrees and
-// levels: every step of the chain is ONE launch of a persistent kernel that
-// walks the work units of all items.  The chain is the single-operation one:
-// INTT of d2 = a1 b1 (formed in the first pass), ModUp conversion, NTT, inner
-// product (which forms d0, d1 and the own-digit d2 residues itself and leaves
-// its Q-limbs as ip P^-1 + d_c), INTT of the P-limbs (with the conversion's
-// input factor in its last stage), NTT of the ModDown conversion (computed in
-// the first pass, the tail out = ip' - NTT(conv) P^-1 in the last).  The
-// tensor, ModDown-conversion and tail steps keep their stage numbers with no
-// work units.
+// levels.  The chain is the single-operation one: INTT of d2 = a1 b1 (formed
+// in the first pass), ModUp conversion, NTT, inner product (which forms d0, d1
+// and the own-digit d2 residues itself and leaves its Q-limbs as
+// ip P^-1 + d_c), INTT of the P-limbs (with the conversion's input factor in
+// its last stage), NTT of the ModDown conversion (computed in the first pass,
+// the tail out = ip' - NTT(conv) P^-1 in the last).  The tensor,
+// ModDown-conversion and tail steps keep their stage numbers with no work
+// units.
+//
+// Launches: each element-wise step (ModUp conversion, inner product) is ONE
+// launch over the work units of every item; each NTT pass is one launch per
+// ring degree present (one transform shape per kernel keeps the unrolled
+// rounds free of register spills).  By default a workgroup takes one work
+// unit; rf_batch_set_grid gives a launch a fixed number of workgroups, each
+// walking a contiguous range of units (a persistent form the autotuner can
+// pick).
 //
 // Work units: an NTT pass unit is one 4096-residue tile of one limb
 // (N / 4096 tiles per limb); an element-wise unit is 256 coefficients of one
 // limb, digit or polynomial.  The units of a step are numbered item after
-// item (prefix sums in the job tables); workgroup w of a launch with G
-// workgroups takes the contiguous range [w * per, (w + 1) * per) of units,
-// finds its first item by binary search and then walks forward, so the
-// per-unit overhead is a compare.  Mixed ring degrees are dispatched per unit
-// to the matching template instantiation of the shared device code
-// (ntt_dev.hpp, ks_dev.hpp), so an item's results are bit-identical to the
-// single-operation path.  The launch sequence can be captured once in a
-// hipGraph and replayed; the job tables are device data, so the graph does not
-// depend on anything but the plan.
+// item (prefix sums in the job tables); a workgroup finds the item of its
+// first unit by binary search and then walks forward, so the per-unit
+// overhead is a compare.  Mixed ring degrees are dispatched per unit to the
+// matching template instantiation of the shared device code (ntt_dev.hpp,
+// ks_dev.hpp), so an item's results are bit-identical to the single-operation
+// path.  The launch sequence can be captured once in a hipGraph and replayed;
+// the job tables are device data, so the graph does not depend on anything but
+// the plan.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -139,6 +139,8 @@ extern "C" size_t rf_workspace_bytes(const rf_ctx *c, int op, uint32_t nl) {
         case RF_OP_ROTATE: return (ks_layout(c, nl).total + (size_t)(c->scheme == RF_BFV ? 3 : 1) * nl * N) * 8;
         case RF_OP_RESCALE: return nl < 2 ? 0 : (2 + 2 * (size_t)(nl - 1)) * N * 8;
         case RF_OP_MODSWITCH: return (nl < 2 || c->scheme != RF_BGV) ? 0 : (2 + 2 * (size_t)(nl - 1)) * N * 8;
+        // two buffers of N complex doubles (the FFT's ping-pong)
+        case RF_OP_ENCODE: case RF_OP_DECODE: return c->scheme == RF_CKKS ? 32 * N : 0;
         default: return 0;
     }
 }
@@ -283,6 +285,22 @@ extern "C" int rf_rotate(const rf_ctx *c, const uint64_t *in, uint32_t galois, c
     if ((rc = launch_ntt(c, batch(in, x, poly, poly, nl, 2, 0, nullptr), true, s))) return rc;
     if ((rc = rotate_ntt(c, x, galois, gk, out, nl, x + 2 * poly, s))) return rc;
     return launch_ntt(c, batch(out, out, poly, poly, nl, 2, 0, nullptr), false, s);
+}
+
+extern "C" int rf_galois_element(const rf_ctx *c, int64_t r, int conjugate, uint32_t *out) {
+    if (!c || !out) return fail(RF_EINVAL, "rf_galois_element: null argument");
+    // 5 has order N/2 in (Z/2NZ)^*: reduce r mod N/2 (a negative r rotates right)
+    const uint64_t two_n = 2ull * c->n, half = c->n / 2;
+    int64_t e = r % (int64_t)half;
+    if (e < 0) e += (int64_t)half;
+    uint64_t g = 1, b = 5;
+    for (uint64_t k = (uint64_t)e; k; k >>= 1) {
+        if (k & 1) g = g * b % two_n;
+        b = b * b % two_n;
+    }
+    if (conjugate) g = g * (two_n - 1) % two_n;
+    *out = (uint32_t)g;
+    return RF_OK;
 }
 
 extern "C" int rf_automorphism(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint32_t galois, uint32_t nl,

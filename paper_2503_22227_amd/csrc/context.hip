@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -118,6 +119,10 @@ static void free_tables(rf_ctx *c) {
     (void)hipFree(c->d_pmaps);
     (void)hipFree(c->d_behz);
     (void)hipFree(c->d_pmap_qb);
+    (void)hipFree(c->d_client);
+    (void)hipFree(c->d_garner);
+    (void)hipFree(c->d_zeta);
+    (void)hipFree(c->d_slot_idx);
 }
 
 extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
@@ -502,7 +507,66 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
         for (uint32_t m = 0; m <= nb; ++m) pmqb.push_back((uint8_t)(KB + m));
     }
 
+    // Client-side tables.  [P]_{p_g} for the P [i in D_j] s' term of key
+    // generation (0 on the special primes); floor(Q_L / t) mod p_g for BFV
+    // encryption, = -[Q_L]_t t^-1 mod q_g since q_g divides Q_L.
+    std::vector<uint64_t> cl((size_t)NP * 4, 0);
+    {
+        uint64_t qt = 0;
+        if (c->scheme == RF_BFV) {
+            qt = 1 % c->t;
+            for (uint32_t h = 0; h < c->L; ++h) qt = mulmod_h(qt, c->primes[h] % c->t, c->t);
+        }
+        for (uint32_t g = 0; g < NP; ++g) {
+            const uint64_t q = c->primes[g];
+            uint64_t pm = 1 % q;
+            for (uint32_t a = 0; a < c->K; ++a) pm = mulmod_h(pm, c->primes[c->L + a] % q, q);
+            if (g >= c->L && g < c->L + c->K) pm = 0;
+            cl[4 * g] = pm;
+            cl[4 * g + 1] = shoup_companion(pm, q);
+            if (c->scheme == RF_BFV && g < c->L) {
+                const uint64_t d = mulmod_h((q - qt % q) % q, inv_h(c->t % q, q), q);
+                cl[4 * g + 2] = d;
+                cl[4 * g + 3] = shoup_companion(d, q);
+            }
+        }
+    }
+    // q_i^-1 mod q_j (i < j): balanced mixed-radix digits of the CRT composition
+    std::vector<uint64_t> gar((size_t)c->L * c->L * 2, 0);
+    for (uint32_t i = 0; i < c->L; ++i)
+        for (uint32_t j = i + 1; j < c->L; ++j) {
+            const uint64_t qj = c->primes[j];
+            const uint64_t v = inv_h(c->primes[i] % qj, qj);
+            gar[((size_t)i * c->L + j) * 2] = v;
+            gar[((size_t)i * c->L + j) * 2 + 1] = shoup_companion(v, qj);
+        }
+    // CKKS: zeta^k = exp(i pi k / N) for k < 2N and the slot positions of the
+    // canonical embedding: slot j is the evaluation at zeta^(5^j)
+    std::vector<double> zeta;
+    std::vector<uint32_t> slot_idx;
+    if (c->scheme == RF_CKKS) {
+        zeta.resize(4 * (size_t)N);
+        const long double pi = 3.141592653589793238462643383279502884L;
+        for (uint32_t k = 0; k < 2 * N; ++k) {
+            const long double ang = pi * (long double)k / (long double)N;
+            zeta[2 * k] = (double)cosl(ang);
+            zeta[2 * k + 1] = (double)sinl(ang);
+        }
+        slot_idx.resize(N / 2);
+        uint64_t x = 1;
+        for (uint32_t j = 0; j < N / 2; ++j) {
+            slot_idx[j] = (uint32_t)((x - 1) / 2);
+            x = x * 5 % (2 * (uint64_t)N);
+        }
+    }
+
     int rc = RF_OK;
+    if ((rc = upload(&c->d_client, cl)) || (rc = upload(&c->d_garner, gar)) ||
+        (!zeta.empty() && ((rc = upload(&c->d_zeta, zeta)) || (rc = upload(&c->d_slot_idx, slot_idx))))) {
+        free_tables(c);
+        delete c;
+        return rc;
+    }
     if ((!bz.empty() && ((rc = upload(&c->d_behz, bz)) || (rc = upload(&c->d_pmap_qb, pmqb)))) ||
         (rc = upload(&c->d_pc, pc)) || (rc = upload(&c->d_pc_md, pc_md)) || (rc = upload(&c->d_pc_mu, pc_mu)) ||
         (!twrf.empty() && ((rc = upload(&c->d_tw_fwd_rows, twrf)) || (rc = upload(&c->d_tw_inv_rows, twri)))) || (rc = upload(&c->d_tw_fwd, twf)) || (rc = upload(&c->d_tw_inv, twi)) ||

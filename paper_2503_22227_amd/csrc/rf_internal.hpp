@@ -105,6 +105,11 @@ struct rf_ctx {
     uint8_t *d_pmap_qb = nullptr;          // prime indices of q u B_sk
     rf::BehzLayout behz{};
     size_t modup_stride = 0;               // uint64 entries per (digit, size) block
+    // client side (key generation, encryption, decryption, encode / decode)
+    uint64_t *d_client = nullptr;          // [L+K][4]: [P]_{p_g}, companion, [floor(Q_L / t)]_{p_g} (BFV), companion
+    uint64_t *d_garner = nullptr;          // [L][L][2]: (q_i^-1 mod q_j, companion) for i < j
+    double *d_zeta = nullptr;              // CKKS: [2N][2] (cos, sin)(pi k / N)
+    uint32_t *d_slot_idx = nullptr;        // CKKS: [N/2] (5^j mod 2N - 1) / 2
 };
 
 namespace rf {

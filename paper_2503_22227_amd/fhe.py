@@ -28,6 +28,16 @@ def _ptr(t: torch.Tensor) -> int:
     return t.data_ptr()
 
 
+def _fptr(t: torch.Tensor) -> int:
+    if not t.is_cuda:
+        raise ValueError("tensor must be on a HIP device")
+    if t.dtype not in (torch.float64, torch.complex128):
+        raise ValueError("tensor must hold doubles")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
 def _stream() -> int:
     return torch.cuda.current_stream().cuda_stream
 
@@ -184,6 +194,70 @@ class Context:
               "rf_mul_plain")
         return out
 
+    def galois_element(self, rotation: int, conjugate: bool = False) -> int:
+        """The Galois element rotating slots left by ``rotation`` (5^r mod 2N), times 2N - 1
+        when ``conjugate``; computed by the library."""
+        g = ctypes.c_uint32()
+        check(lib.rf_galois_element(self._h, int(rotation), 1 if conjugate else 0, ctypes.byref(g)),
+              "rf_galois_element")
+        return int(g.value)
+
+    # ---------------------------------------------------------------- client side
+    def key_ntt(self, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """NTT-domain form over every prime of the chain ([L + k, N]) of an int64 [N] polynomial."""
+        out = self.empty(self.L + self.k, self.n) if out is None else out
+        check(lib.rf_key_ntt(self._h, _ptr(x), _ptr(out), _stream()), "rf_key_ntt")
+        return out
+
+    def keygen_switch(self, s_ntt: torch.Tensor, galois: int, a: torch.Tensor, e: torch.Tensor,
+                      out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Switching key [dnum, 2, L + k, N] from s^2 (galois 0) or s(X^g) to s, with the masks
+        a [dnum, L + k, N] and errors e [dnum, N] drawn by the caller."""
+        out = self.empty(self.dnum, 2, self.L + self.k, self.n) if out is None else out
+        check(lib.rf_keygen_switch(self._h, _ptr(s_ntt), int(galois), _ptr(a), _ptr(e), _ptr(out), _stream()),
+              "rf_keygen_switch")
+        return out
+
+    def encrypt(self, m: torch.Tensor, e: torch.Tensor, a: torch.Tensor, s_ntt: torch.Tensor,
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Secret-key encryption of the int64 [N] message coefficients m with error e and mask
+        a [limbs, N]; returns [2, limbs, N]."""
+        nl = a.shape[0]
+        out = self.empty(2, nl, self.n) if out is None else out
+        check(lib.rf_encrypt_sk(self._h, _ptr(m), _ptr(e), _ptr(a), _ptr(s_ntt), _ptr(out), nl, _stream()),
+              "rf_encrypt_sk")
+        return out
+
+    def decrypt(self, ct: torch.Tensor, s_ntt: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Coefficient-domain residues [limbs, N] of the phase c0 + c1 s."""
+        nl = ct.shape[1]
+        out = self.empty(nl, self.n) if out is None else out
+        check(lib.rf_decrypt(self._h, _ptr(ct), _ptr(s_ntt), _ptr(out), nl, _stream()), "rf_decrypt")
+        return out
+
+    def crt_centered(self, x: torch.Tensor, scale: float = 1.0, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """float64 [N]: the centred integer of the residues x [limbs, N] divided by scale."""
+        out = torch.empty(self.n, dtype=torch.float64, device=self.device) if out is None else out
+        check(lib.rf_crt_centered(self._h, _ptr(x), _fptr(out), x.shape[0], float(scale), _stream()),
+              "rf_crt_centered")
+        return out
+
+    def encode(self, z: torch.Tensor, scale: float, out: Optional[torch.Tensor] = None, slot: int = 0) -> torch.Tensor:
+        """CKKS encode of complex128 [N/2] slots: int64 [N] coefficients."""
+        out = self.empty(self.n) if out is None else out
+        ws = self.workspace(_lib.RF_OP_ENCODE, 1, slot)
+        check(lib.rf_encode_ckks(self._h, _fptr(z), float(scale), _ptr(out), _ptr(ws), ws.numel() * 8, _stream()),
+              "rf_encode_ckks")
+        return out
+
+    def decode(self, x: torch.Tensor, out: Optional[torch.Tensor] = None, slot: int = 0) -> torch.Tensor:
+        """CKKS decode of float64 [N] coefficients (already divided by the scale): complex128 [N/2]."""
+        out = torch.empty(self.n // 2, dtype=torch.complex128, device=self.device) if out is None else out
+        ws = self.workspace(_lib.RF_OP_DECODE, 1, slot)
+        check(lib.rf_decode_ckks(self._h, _fptr(x), _fptr(out), _ptr(ws), ws.numel() * 8, _stream()),
+              "rf_decode_ckks")
+        return out
+
     def automorphism(self, x: torch.Tensor, galois: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         """sigma_g of a [polys, limbs, N] NTT-domain tensor."""
         npolys, nl = x.shape[0], x.shape[1]
@@ -191,11 +265,6 @@ class Context:
         check(lib.rf_automorphism(self._h, _ptr(x), _ptr(out), galois, nl, npolys, _stream()),
               "rf_automorphism")
         return out
-
-
-def galois_element(r: int, n: int) -> int:
-    """5^r mod 2N: the automorphism that rotates CKKS slots left by r."""
-    return pow(5, r, 2 * n)
 
 
 BATCH_STAGES = ("tensor", "intt_d2_rows", "intt_d2_cols", "modup_bconv", "ntt_ext_cols", "ntt_ext_rows",

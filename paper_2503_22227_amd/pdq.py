@@ -230,7 +230,7 @@ class GpuExecutor:
     def __init__(self, ctx, keys: dict):
         self.ctx = ctx
         self.keys = keys
-        self.gal = {r: pow(5, r, 2 * ctx.n) for r in keys if r != "rlk"}
+        self.gal = {r: ctx.galois_element(r) for r in keys if r != "rlk"}
 
     def run(self, ops, regs: dict, slot: int = 0) -> dict:
         for op in ops:

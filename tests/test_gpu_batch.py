@@ -65,9 +65,12 @@ def test_batched_equals_single_and_oracle(batch):
     plan.run(graph=False)
     for i, (_, _, _, _, out) in enumerate(batch["items"]):
         assert np.array_equal(host(out), ref[i]), i
-    # oracle on sampled items: the smallest and one full-size item
-    for i in (len(batch["items"]) - 4, len(batch["items"]) - 5):
+    # oracle on the fixed items (every ring degree; N = 2^15 with 4 special primes
+    # runs the K = 4 ModDown prologue) and the first random ones
+    n = len(batch["items"])
+    for i in list(range(n - 5, n)) + [0, 1, 2]:
         ln, nl = batch["shapes"][i]
+        print("oracle item %d: log_n=%d limbs=%d" % (i, ln, nl), flush=True)
         p = batch["params"][ln]
         a, b = batch["host_in"][i]
         want = C.hmult_relin(C.Ciphertext(a, 1.0), C.Ciphertext(b, 1.0), batch["keys"][ln], p)
@@ -101,3 +104,41 @@ def test_batch_rejects_bad_items(batch):
     ctx, a, b, rlk, out = batch["items"][0]
     with pytest.raises(Exception):
         BatchPlan([(ctx, a, b, rlk, a)])  # out aliases a
+
+
+def test_benched_batch_equals_single():
+    """The 256-item mixed batch the benchmark times (same seeds and shapes): every item of
+    the graph replay, with the default and with persistent grids, bit-identical to one
+    rf_hmult_relin call per item (compared on the device)."""
+    from paper_2503_22227_amd import BatchPlan, Context
+    from paper_2503_22227_amd.params import chain_for
+    w = synthetic.WORKLOADS["ckks_batch"]
+    ch = chain_for(w)
+    st = synthetic.streams(w["seed"])
+    shapes = synthetic.batch_shapes(st["batch_shape"], w["items"], w["log_n_choices"], w["limbs_range"])
+    print("benched batch: %d items" % len(shapes), flush=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(w["seed"])
+    qp = ch["q"] + ch["p"]
+    ctxs, keys = {}, {}
+    for ln in sorted({x[0] for x in shapes}):
+        ctxs[ln] = Context(ch["q"], ch["p"], ln, w["alpha"], log_nmax=w["log_nmax"])
+        keys[ln] = torch.stack([torch.stack([synthetic.device_uniform_residues(qp, 1 << ln, gen, "cuda")
+                                             for _ in range(2)]) for _ in range(ctxs[ln].dnum)])
+    items = []
+    for ln, nl in shapes:
+        a = torch.stack([synthetic.device_uniform_residues(ch["q"][:nl], 1 << ln, gen, "cuda") for _ in range(2)])
+        b = torch.stack([synthetic.device_uniform_residues(ch["q"][:nl], 1 << ln, gen, "cuda") for _ in range(2)])
+        items.append((ctxs[ln], a, b, keys[ln], torch.zeros_like(a)))
+    ref = [ctx.hmult_relin(a, b, k) for ctx, a, b, k, _ in items]
+    plan = BatchPlan(items)
+    for grid in (0, 1024):
+        for stage in range(13):
+            plan.set_grid(stage, grid)
+        for it in items:
+            it[4].zero_()
+        plan.run(graph=True)
+        torch.cuda.synchronize()
+        bad = [i for i, it in enumerate(items) if not torch.equal(it[4], ref[i])]
+        assert not bad, (grid, bad[:10])
+    plan.close()

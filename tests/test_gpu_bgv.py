@@ -67,13 +67,14 @@ def test_bgv_modswitch_parity(nl):
     assert np.array_equal(host(d.view(-1)[: 2 * (nl - 1) * p.n].reshape(2, nl - 1, p.n)), want)
 
 
-def test_bgv_rotate_parity():
+@pytest.mark.parametrize("conj,nl", [(False, 14), (True, 14), (True, 6)])
+def test_bgv_rotate_parity(conj, nl):
+    """Column rotation (g = 5) and the row swap (g = 2N - 1)."""
     p, ctx = context(15)
-    rng = np.random.default_rng(77)
-    nl = 14
+    rng = np.random.default_rng(77 + nl)
     ct = rand_ct(p, nl, rng)
     gk = rand_key(p, rng)
-    g = C.galois_element(5, p.n)
+    g = 2 * p.n - 1 if conj else C.galois_element(5, p.n)
     got = host(ctx.rotate(dev(ct), g, dev(gk)))
     want = B.rotate(B.Ciphertext(ct), g, gk, p)
     assert np.array_equal(got, want.data)

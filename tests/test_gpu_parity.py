@@ -134,7 +134,8 @@ def test_hmult_relin_parity(name, alpha, nl):
 
 
 @pytest.mark.parametrize("name,alpha,nl", [("ckks_n12", None, 2), ("ckks_n16_l24", None, 24),
-                                           ("ckks_n16_l24", None, 10)])
+                                           ("ckks_n16_l24", None, 10), ("ckks_n16_l24_a4", None, 24),
+                                           ("ckks_n16_l24_a4", None, 10)])
 def test_rotate_parity(name, alpha, nl):
     p, ctx = context(name, alpha)
     show("rotate %s nl=%d" % (name, nl))
@@ -179,6 +180,26 @@ def test_rescale_parity(name, nl):
     torch.cuda.synchronize()
     inplace = d.view(-1)[: 2 * (nl - 1) * p.n].reshape(2, nl - 1, p.n)
     assert np.array_equal(host(inplace), want)
+
+
+@pytest.mark.parametrize("name,nl", [("ckks_n12", 2), ("ckks_n16_l24", 24), ("ckks_n16_l24", 5)])
+def test_elementwise_parity(name, nl):
+    """rf_add, rf_sub, rf_mul_scalar, rf_add_scalar, rf_mul_plain against the oracle."""
+    p, ctx = context(name)
+    rng = np.random.default_rng(400 + nl)
+    a, b = rand_ct(p, nl, rng), rand_ct(p, nl, rng)
+    pt = synthetic.uniform_residues(rng, p.q[:nl], p.n)
+    A, B = C.Ciphertext(a, 1.0), C.Ciphertext(b, 1.0)
+    assert np.array_equal(host(ctx.mul_plain(dev(a), dev(pt))), C.ct_mul_plain(A, pt, p).data)
+    assert np.array_equal(host(ctx.add(dev(a), dev(b))), C.ct_add(A, B, p).data)
+    assert np.array_equal(host(ctx.sub(dev(a), dev(b))), C.ct_sub(A, B, p).data)
+    for k in (3, -7, (1 << 62) + 5, -(1 << 61)):
+        assert np.array_equal(host(ctx.mul_scalar(dev(a), k)), C.ct_mul_int(A, k, p).data), k
+        assert np.array_equal(host(ctx.add_scalar(dev(a), k)), C.ct_add_int(A, k, p).data), k
+    # out aliasing an input
+    d = dev(a)
+    ctx.mul_plain(d, dev(pt), out=d)
+    assert np.array_equal(host(d), C.ct_mul_plain(A, pt, p).data)
 
 
 def test_modswitch_parity():

@@ -1,6 +1,11 @@
 """Private-table queries on the GPU: the op list run by the library is bit-identical
 to the oracle's run, and every query's result is the same alone and in a mix of
-concurrent queries served by the continuous-batching server."""
+concurrent queries served by the continuous-batching server.
+
+N = 2^12 runs every operation on the single-pass kernels; N = 2^14 (alpha = 4,
+4 special primes, the query chain) runs the fused two-pass kernels of the
+benchmarked N = 2^16 workload; the alone-versus-mixed check is also made at
+N = 2^16 itself (GPU against GPU, on seeded uniform residues)."""
 import numpy as np
 import pytest
 
@@ -21,10 +26,15 @@ def host(t):
     return t.cpu().numpy().view(np.uint64)
 
 
-@pytest.fixture(scope="module")
-def setup():
+_SETUP = {}
+
+
+def make_setup(log_n, rows):
     from paper_2503_22227_amd import Context, pdq
-    q = client_query(12, 60)
+    if log_n in _SETUP:
+        return _SETUP[log_n]
+    print("pdq keys at log_n=%d" % log_n, flush=True)
+    q = client_query(log_n, rows)
     p, s = q["p"], q["s"]
     ctx = Context(p.q, p.p, p.log_n, p.alpha, log_nmax=p.log_nmax)
     rlk = C.relin_key(p, s, q["st"]["rlk"])
@@ -32,21 +42,31 @@ def setup():
     gk = OQ.rotation_keys(p, s, amounts, q["st"]["galois"])
     keys = {"rlk": dev(rlk)}
     keys.update({r: dev(k) for r, k in gk.items()})
-    return dict(q=q, p=p, s=s, ctx=ctx, rlk=rlk, gk=gk, opx=pdq.GpuExecutor(ctx, keys))
+    _SETUP[log_n] = dict(q=q, p=p, s=s, ctx=ctx, rlk=rlk, gk=gk, opx=pdq.GpuExecutor(ctx, keys), rows=rows)
+    return _SETUP[log_n]
+
+
+@pytest.fixture(scope="module")
+def setup():
+    return make_setup(12, 60)
 
 
 def gpu_inputs(inputs):
     return {k: dev(v.data) for k, v in inputs.items()}
 
 
-def test_pdq_gpu_equals_oracle(setup):
+@pytest.mark.parametrize("log_n,rows", [(12, 60), (14, 40)])
+def test_pdq_gpu_equals_oracle(log_n, rows):
     from paper_2503_22227_amd import pdq
+    setup = make_setup(log_n, rows)
     q, p = setup["q"], setup["p"]
-    ops, outs, regs = pdq.plan_query(p.q, p.L, q["D"], 60, q["a"], q["b"])
-    print("pdq op list of %d ops" % len(ops), flush=True)
+    ops, outs, regs = pdq.plan_query(p.q, p.L, q["D"], rows, q["a"], q["b"])
+    print("pdq op list of %d ops at log_n=%d (alpha=%d, k=%d)" % (len(ops), log_n, p.alpha, p.k), flush=True)
     got = setup["opx"].run(ops, gpu_inputs(q["inputs"]))
     want = OQ.Executor(p, setup["rlk"], setup["gk"]).run(ops, dict(q["inputs"]))
-    for r in outs:
+    # every register the op list wrote (the executors keep them all), outputs included
+    assert set(got) == set(want)
+    for r in sorted(got):
         assert np.array_equal(host(got[r]), want[r].data), r
     ref = OQ.reference(q["vals"], q["lo"], q["hi"], q["a"], q["b"])
     dec = [C.decode(C.decrypt(p, setup["s"], C.Ciphertext(host(got[r]), 1.0)), regs[r][1], p.n)[0].real
@@ -83,3 +103,55 @@ def test_server_alone_equals_mixed(setup):
         got = C.decode(C.decrypt(p, q["s"], C.Ciphertext(rm.result[outs[0]].numpy().view(np.uint64), 1.0)),
                        regs[outs[0]][1], p.n)[0].real
         assert abs(got - ref[0]) < 0.05
+
+
+def test_server_alone_equals_mixed_n16():
+    """The benchmarked serving shape (N = 2^16, 24 limbs, alpha = 4, 4 special primes):
+    queries of different sizes served alone (one slot) and concurrently (four slots,
+    each on its own stream and workspace) give bit-identical results."""
+    import synthetic
+    from paper_2503_22227_amd import Context, pdq
+    from paper_2503_22227_amd.params import chain_for
+    from paper_2503_22227_amd.serve import GpuQueryExecutor, Request, Server
+    w = synthetic.WORKLOADS["pdq"]
+    ch = chain_for(w)
+    n = 1 << w["log_n"]
+    L = len(ch["q"])
+    ctx = Context(ch["q"], ch["p"], w["log_n"], w["alpha"], log_nmax=w["log_nmax"])
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(w["seed"] + 1)
+    qp = ch["q"] + ch["p"]
+
+    def key():
+        return torch.stack([torch.stack([synthetic.device_uniform_residues(qp, n, gen, "cuda") for _ in range(2)])
+                            for _ in range(ctx.dnum)])
+
+    keys = {"rlk": key()}
+    for i in range(9):
+        keys[1 << i] = key()
+    opx = pdq.GpuExecutor(ctx, keys)
+    plans, inputs = [], []
+    for i, rows in enumerate((10, 33, 64, 100, 128)):
+        a, b = i % 4, (i + 1) % 4
+        plans.append(pdq.plan_query(ch["q"], L, 2.0 ** w["log_scale"], rows, a, b))
+        inputs.append({k: torch.stack([synthetic.device_uniform_residues(ch["q"], n, gen, "cuda")
+                                       for _ in range(2)]) for k in ("T", "LO", "HI")})
+    torch.cuda.synchronize()
+
+    def requests():
+        return [Request(rid=i, arrival=0.0, ops=ops, inputs={k: v.clone() for k, v in inputs[i].items()},
+                        outputs=outs, footprint=1) for i, (ops, outs, regs) in enumerate(plans)]
+
+    print("n16 serving: %d queries alone" % len(plans), flush=True)
+    alone = requests()
+    torch.cuda.synchronize()
+    st1 = Server(GpuQueryExecutor(opx, 1), budget_bytes=10, slots=1).run(alone)
+    print("n16 serving: mixed", flush=True)
+    mixed = requests()
+    torch.cuda.synchronize()
+    st2 = Server(GpuQueryExecutor(opx, 4), budget_bytes=10, slots=4, ops_per_chunk=8).run(mixed)
+    assert st1.completed == st2.completed == len(plans)
+    assert st1.peak_inflight == 1 and st2.peak_inflight > 1
+    for (ops, outs, regs), ra, rm in zip(plans, alone, mixed):
+        for r in outs:
+            assert torch.equal(ra.result[r], rm.result[r]), (ra.rid, r)

@@ -74,6 +74,36 @@ def test_tensor_schoolbook():
         assert [int(x) for x in coeff(d2, moduli, p)[i]] == sb(ac[1], bc[1], q)
 
 
+def test_mul_plain_schoolbook():
+    """ct_mul_plain: each polynomial of the ciphertext times the plaintext, checked in the
+    coefficient domain against the schoolbook negacyclic product (on a truncated level,
+    so the plaintext's extra limbs must be ignored); ct_mul_int and ct_add_int against
+    their integer definitions."""
+    p = small_ckks(log_n=5)
+    st = synthetic.streams(2)
+    nl = 3
+    moduli = p.q[:nl]
+    ct = C.Ciphertext(np.stack([synthetic.uniform_residues(st["ct_a"], moduli, p.n) for _ in range(2)]), 1.0)
+    pt = synthetic.uniform_residues(st["ct_e"], p.q, p.n)
+    out = C.ct_mul_plain(ct, pt, p)
+    assert out.data.shape == ct.data.shape
+    for c in range(2):
+        for i, q in enumerate(moduli):
+            want = T.negacyclic_schoolbook(coeff(ct.data[c], moduli, p)[i], coeff(pt[:nl], moduli, p)[i], q)
+            assert [int(x) for x in coeff(out.data[c], moduli, p)[i]] == want, (c, i)
+    k = -(1 << 61) - 3
+    mi = C.ct_mul_int(ct, k, p)
+    ai = C.ct_add_int(ct, k, p)
+    for c in range(2):
+        for i, q in enumerate(moduli):
+            assert [int(x) for x in mi.data[c, i]] == [int(x) * k % q for x in ct.data[c, i]]
+            # adding the constant polynomial k: k on the constant coefficient only
+            want = [int(x) for x in coeff(ct.data[c], moduli, p)[i]]
+            if c == 0:
+                want[0] = (want[0] + k) % q
+            assert [int(x) for x in coeff(ai.data[c], moduli, p)[i]] == want
+
+
 @pytest.mark.parametrize("alpha,nlimbs", [(2, 5), (2, 4), (3, 5), (1, 3), (5, 5)])
 def test_modup_invariant(alpha, nlimbs):
     p = small_ckks(log_n=5, alpha=alpha)
