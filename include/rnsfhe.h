@@ -142,6 +142,18 @@ int rf_hmult_relin(const rf_ctx *ctx, const uint64_t *a, const uint64_t *b, cons
                    uint64_t *out, uint32_t n_limbs, void *workspace, size_t workspace_bytes,
                    void *stream);
 
+/* HMult+Relin for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same operation and results as rf_hmult_relin, with the workspace taken from a
+ * static device array of 160 MiB that the library holds on every device it runs
+ * on until the process ends (enough for N = 2^16 with 24 Q-primes and 4 special
+ * primes at alpha = 8 or alpha = 4).  RF_EUNSUPPORTED when the operation needs
+ * more scratch than that, RF_ELEVEL / RF_EINVAL as rf_hmult_relin.  Every call on
+ * one device shares the array: calls that overlap on one device (other streams,
+ * other threads) race, so the caller serialises them. */
+int rf_hmult_relin_noalloc(const rf_ctx *ctx, const uint64_t *a, const uint64_t *b, const uint64_t *rlk,
+                           uint64_t *out, uint32_t n_limbs, void *stream);
+
 /* HRotate (the rotate and complex_conjugate rows of Table "CKKS operators",
  * rotate_rows / rotate_columns of the BFV and BGV tables):
  * out = (sigma_g(c0) + KS_0(sigma_g(c1)), KS_1(sigma_g(c1))) with

@@ -64,6 +64,7 @@ _SIGS = {
     "rf_ntt": (ctypes.c_int, [_vp, _vp, _u32, _u32, _u32, _vp]),
     "rf_intt": (ctypes.c_int, [_vp, _vp, _u32, _u32, _u32, _vp]),
     "rf_hmult_relin": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _u32, _vp, _sz, _vp]),
+    "rf_hmult_relin_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _u32, _vp]),
     "rf_rotate": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _u32, _vp, _sz, _vp]),
     "rf_keyswitch": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32, ctypes.c_int, _vp, _sz, _vp]),
     "rf_rescale": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _sz, _vp]),
