@@ -17,8 +17,7 @@ struct LimbView {
 // are launched back to back, 16 workgroups apart at N = 2^16, which places them
 // on the same XCD (workgroups are dealt to the 8 XCDs in turn), so the second
 // reads the twiddles from that XCD's L2.
-__device__ __forceinline__ LimbView limb_view(const NttBatch &b, int log_n) {
-    const uint32_t limb = blockIdx.y;
+__device__ __forceinline__ LimbView limb_view(const NttBatch &b, int log_n, uint32_t limb) {
     const uint32_t li = limb / b.n_polys, poly = limb - li * b.n_polys;
     LimbView v;
     v.g = b.pmap ? (uint32_t)b.pmap[li] : b.prime_base + li;
@@ -31,18 +30,20 @@ template <int A, int B, bool FWD>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesCols))) void ntt_cols_kernel(NttBatch b, const TwPair *__restrict__ tw_all,
                                                             const PrimeConst *__restrict__ pcs) {
     __shared__ uint64_t lds[(1 << A) * (kTile / (1 << A) + 1)];
-    const LimbView v = limb_view(b, A + B);
+    const uint32_t tile = blockIdx.x;
+    const LimbView v = limb_view(b, A + B, blockIdx.y);
     const PrimeConst pc = pcs[v.g];
-    ntt_cols_unit<A, B, FWD>(lds, v.in, v.out, tw_all + ((size_t)v.g << (A + B)), pc, blockIdx.x);
+    ntt_cols_unit<A, B, FWD>(lds, v.in, v.out, tw_all + ((size_t)v.g << (A + B)), pc, tile);
 }
 
 template <int A, int B, bool FWD>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesRows))) void ntt_rows_kernel(NttBatch b, const TwPair *__restrict__ tw_all,
                                                             const PrimeConst *__restrict__ pcs) {
     __shared__ uint64_t lds[(1 << B) * (kTile / (1 << B) + 1)];
-    const LimbView v = limb_view(b, A + B);
+    const uint32_t tile = blockIdx.x;
+    const LimbView v = limb_view(b, A + B, blockIdx.y);
     const PrimeConst pc = pcs[v.g];
-    ntt_rows_unit<A, B, FWD>(lds, v.in, v.out, tw_all + ((size_t)v.g << (A + B)), pc, blockIdx.x);
+    ntt_rows_unit<A, B, FWD>(lds, v.in, v.out, tw_all + ((size_t)v.g << (A + B)), pc, tile);
 }
 
 // First forward pass of NTT(conv) with the ModDown base conversion as its
@@ -53,6 +54,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KP == 
     const uint64_t *__restrict__ cross, const uint64_t *__restrict__ negp, uint32_t nl, uint32_t L, uint32_t K) {
     __shared__ uint64_t lds[(1 << A) * (kTile / (1 << A) + 1)];
     constexpr int LOGN = A + B;
+    const uint32_t tile = blockIdx.x;
     const uint32_t c = blockIdx.y & 1, i = blockIdx.y >> 1;  // polynomials interleaved
     const PrimeConst pc = pcs[i];
     ModdownPro<KP> pro;
@@ -69,8 +71,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KP == 
     pro.r64 = pc.r64;
     pro.r64_p = pc.r64_p;
     pro.one_p = pc.one_p;
-    ntt_cols_unit_pro<A, B, true, true>(lds, conv + (((size_t)c * nl + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
-                                  blockIdx.x, pro);
+    ntt_cols_unit_pro<A, B, true, B == 8>(lds, conv + (((size_t)c * nl + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
+                                  tile, pro);
 }
 
 // First forward pass of NTT(lift) with the rescale lift as its prologue: limb
@@ -82,6 +84,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
     __shared__ uint64_t lds[(1 << A) * (kTile / (1 << A) + 1)];
     constexpr int LOGN = A + B;
     const uint32_t l = nl - 1;
+    const uint32_t tile = blockIdx.x;
     const uint32_t c = blockIdx.y & 1, i = blockIdx.y >> 1;  // polynomials interleaved
     const PrimeConst pl = pcs[l];
     const PrimeConst pc = pcs[i];
@@ -96,24 +99,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
     pro.corr = tab[((size_t)l * L + i) * 3 + 2];
     pro.tmod = pc.tmod;
     pro.tmod_p = pc.tmod_p;
-    ntt_cols_unit_pro<A, B, true, true>(lds, lift + (((size_t)c * l + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
-                                  blockIdx.x, pro);
+    ntt_cols_unit_pro<A, B, true, B == 8>(lds, lift + (((size_t)c * l + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
+                                  tile, pro);
 }
 
 // Last forward pass of NTT(conv) with the ModDown tail: limb (c, i) of conv
 // [2][nl][N] -> out[c][i] = (ip[c][i] - NTT(conv)[c][i]) P^-1 (+ add_c[i]).
 template <int A, int B>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesFused))) void ntt_rows_moddown_kernel(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(B == 8 ? kNttWavesFused : kNttWavesCols))) void ntt_rows_moddown_kernel(
     const uint64_t *conv, const TwPair *__restrict__ tw_all, const PrimeConst *__restrict__ pcs, const uint64_t *ip,
     uint64_t *out, const uint64_t *__restrict__ pinv, uint32_t nl, uint32_t K) {
     __shared__ uint64_t lds[(1 << B) * (kTile / (1 << B) + 1)];
     constexpr int LOGN = A + B;
+    const uint32_t tile = blockIdx.x;
     const uint32_t c = blockIdx.y & 1, i = blockIdx.y >> 1;  // polynomials interleaved
     const PrimeConst pc = pcs[i];
     const ModdownFoldEpi epi{ip + (((size_t)c * (nl + K) + i) << LOGN), out + (((size_t)c * nl + i) << LOGN),
                              pinv[2 * i], pinv[2 * i + 1], pc.q};
-    ntt_rows_unit_epi<A, B, true, true>(lds, conv + (((size_t)c * nl + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
-                                  blockIdx.x, epi);
+    ntt_rows_unit_epi<A, B, true, B == 8>(lds, conv + (((size_t)c * nl + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
+                                  tile, epi);
 }
 
 // First inverse pass of INTT(d2) with d2 = a1 b1 as its prologue: limb i of a, b
@@ -124,11 +128,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
     const PrimeConst *__restrict__ pcs, uint32_t nl) {
     __shared__ uint64_t lds[(1 << B) * (kTile / (1 << B) + 1)];
     constexpr int LOGN = A + B;
-    const uint32_t i = blockIdx.y;
+    const uint32_t tile = blockIdx.x, i = blockIdx.y;
     const PrimeConst pc = pcs[i];
     const size_t li = (size_t)i << LOGN, poly = (size_t)nl << LOGN;
     const TensorPro pro{a + poly + li, b + poly + li, pc.q, pc.r64, pc.r64_p, pc.one_p};
-    ntt_rows_unit_pe<A, B, false>(lds, pro, tw_all + li, pc, blockIdx.x, StoreEpi{dc + li});
+    ntt_rows_unit_pe<A, B, false>(lds, pro, tw_all + li, pc, tile, StoreEpi{dc + li});
 }
 
 // First inverse pass of INTT(sigma_g(a1)) with the automorphism as its
@@ -139,28 +143,29 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
     const PrimeConst *__restrict__ pcs) {
     __shared__ uint64_t lds[(1 << B) * (kTile / (1 << B) + 1)];
     constexpr int LOGN = A + B;
-    const uint32_t i = blockIdx.y;
+    const uint32_t tile = blockIdx.x, i = blockIdx.y;
     const PrimeConst pc = pcs[i];
     const size_t li = (size_t)i << LOGN;
     const GatherPro pro{a1 + li, galois, (uint32_t)LOGN};
-    ntt_rows_unit_pe<A, B, false>(lds, pro, tw_all + li, pc, blockIdx.x, StoreEpi{dc + li});
+    ntt_rows_unit_pe<A, B, false>(lds, pro, tw_all + li, pc, tile, StoreEpi{dc + li});
 }
 
 // Last forward pass of NTT(lift) with the rescale tail: limb (c, i) of lift
 // [2][l][N] -> out[c][i] = (in[c][i] - NTT(lift)[c][i]) q_l^-1, l = nl - 1.
 template <int A, int B>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWavesFused))) void ntt_rows_rescale_kernel(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(B == 8 ? kNttWavesFused : kNttWavesCols))) void ntt_rows_rescale_kernel(
     const uint64_t *lift, const TwPair *__restrict__ tw_all, const PrimeConst *__restrict__ pcs, const uint64_t *in,
     uint64_t *out, const uint64_t *__restrict__ tab, uint32_t nl, uint32_t L) {
     __shared__ uint64_t lds[(1 << B) * (kTile / (1 << B) + 1)];
     constexpr int LOGN = A + B;
     const uint32_t l = nl - 1;
+    const uint32_t tile = blockIdx.x;
     const uint32_t c = blockIdx.y & 1, i = blockIdx.y >> 1;  // polynomials interleaved
     const PrimeConst pc = pcs[i];
     const uint64_t *t = tab + ((size_t)l * L + i) * 3;
     RescaleTailEpi epi{in + (((size_t)c * nl + i) << LOGN), out + (((size_t)c * l + i) << LOGN), t[0], t[1], pc.q};
-    ntt_rows_unit_epi<A, B, true, true>(lds, lift + (((size_t)c * l + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
-                                  blockIdx.x, epi);
+    ntt_rows_unit_epi<A, B, true, B == 8>(lds, lift + (((size_t)c * l + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
+                                  tile, epi);
 }
 
 // Whole limb in one workgroup (N = 2^LOGN <= 4096).
@@ -170,7 +175,7 @@ __global__ __launch_bounds__(kThreads) void ntt_single_kernel(NttBatch b, const 
     constexpr int S = 1 << LOGN;
     constexpr int NT = S / kElems;
     __shared__ uint64_t lds[S];
-    const LimbView v = limb_view(b, LOGN);
+    const LimbView v = limb_view(b, LOGN, blockIdx.y);
     const PrimeConst pc = pcs[v.g];
     const TwPair *tw = tw_all + ((size_t)v.g << LOGN);
     if (threadIdx.x < NT) {
@@ -190,10 +195,65 @@ __global__ __launch_bounds__(kThreads) void ntt_single_kernel(NttBatch b, const 
     }
 }
 
+// A pass of a launch with few limbs (ntt_cols_small / ntt_rows_small): one
+// workgroup per TILE residues of a limb, E residues per thread.
+template <int A, int B, bool FWD, bool COLS, int TILE, int E>
+__global__ __launch_bounds__(TILE / E) void ntt_small_kernel(NttBatch b, const TwPair *__restrict__ tw_all,
+                                                             const PrimeConst *__restrict__ pcs) {
+    constexpr int S = COLS ? (1 << A) : (1 << B);
+    __shared__ uint64_t lds[S * (TILE / S + 1)];
+    const LimbView v = limb_view(b, A + B, blockIdx.y);
+    const PrimeConst pc = pcs[v.g];
+    const TwPair *tw = tw_all + ((size_t)v.g << (A + B));
+    if constexpr (COLS) ntt_cols_small<A, B, FWD, TILE, E>(lds, v.in, v.out, tw, pc, blockIdx.x);
+    else ntt_rows_small<A, B, FWD, TILE, E>(lds, v.in, v.out, tw, pc, blockIdx.x);
+}
+
+// Residues per thread of the few-limb passes (4 measured faster than 8: the
+// 8-limb inverse passes at N = 2^16 took 10.3 / 10.9 us against 10.8 / 12.7 us).
+constexpr int kSmallE = 4;
+// A launch is "small" when its kTile tiles number fewer than the CUs.
+constexpr uint32_t kSmallBelowTiles = 256;
+
+template <int A, int B, int TILE>
+static void launch_two_pass_small(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s,
+                                  const PrimeConst *pcs) {
+    const uint32_t limbs = b.per_poly * b.n_polys;
+    const dim3 grid((1u << (A + B)) / TILE, limbs), block(TILE / kSmallE);
+    NttBatch b2 = b;
+    b2.in = b.out;
+    b2.in_poly_stride = b.out_poly_stride;
+    if (forward) {
+        {
+            ProfScope p("ntt_fwd_cols_small", s);
+            hipLaunchKernelGGL((ntt_small_kernel<A, B, true, true, TILE, kSmallE>), grid, block, 0, s, b, c->d_tw_fwd,
+                               pcs);
+        }
+        ProfScope p("ntt_fwd_rows_small", s);
+        hipLaunchKernelGGL((ntt_small_kernel<A, B, true, false, TILE, kSmallE>), grid, block, 0, s, b2, c->d_tw_fwd,
+                           pcs);
+    } else {
+        {
+            ProfScope p("ntt_inv_rows_small", s);
+            hipLaunchKernelGGL((ntt_small_kernel<A, B, false, false, TILE, kSmallE>), grid, block, 0, s, b,
+                               c->d_tw_inv, pcs);
+        }
+        ProfScope p("ntt_inv_cols_small", s);
+        hipLaunchKernelGGL((ntt_small_kernel<A, B, false, true, TILE, kSmallE>), grid, block, 0, s, b2, c->d_tw_inv,
+                           pcs);
+    }
+}
+
 template <int A, int B>
 static void launch_two_pass(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s,
                             const PrimeConst *pcs) {
     const uint32_t limbs = b.per_poly * b.n_polys;
+    const uint32_t tiles = limbs << (A + B - 12);
+    if (tiles < kSmallBelowTiles) {
+        if (tiles * 2 >= kSmallBelowTiles) launch_two_pass_small<A, B, 2048>(c, b, forward, s, pcs);
+        else launch_two_pass_small<A, B, 1024>(c, b, forward, s, pcs);
+        return;
+    }
     const dim3 block(kThreads);
     const dim3 grid_cols((1u << B) / (kTile >> A), limbs);
     const dim3 grid_rows((1u << A) / (kTile >> B), limbs);

@@ -122,20 +122,22 @@ __device__ __forceinline__ uint32_t row_or_natural(uint32_t tw_base, int s, int 
     }
 }
 
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
+
 // One round of C butterfly stages of a size-2^S_LOG sub-transform held in LDS
 // (element p of sub-transform u at lds[p * ldu + u]).  Thread t of the
-// sub-transform owns kElems residues: kElems / 2^C groups of 2^C residues spaced by
-// the round's smallest distance 2^DL.
+// sub-transform owns E residues (kElems unless stated): E / 2^C groups of 2^C
+// residues spaced by the round's smallest distance 2^DL.
 //
 // IN_REGS / OUT_REGS: the round takes its residues from regs / leaves them in
 // regs (group gi, element e at regs[gi * 2^C + e]) instead of LDS.
 template <int S_LOG, int ST0, int C, bool FWD, bool SCALE_LAST, int ROW_A, bool IN_REGS = false,
-          bool OUT_REGS = false, bool LZ = false>
+          bool OUT_REGS = false, bool LZ = false, int E = kElems>
 __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, uint32_t tw_base,
                                           const TwPair *__restrict__ tw, const PrimeConst &pc,
                                           uint64_t *regs = nullptr) {
     constexpr int G = 1 << C;
-    constexpr int NG = kElems / G;
+    constexpr int NG = E / G;
     constexpr int DL = FWD ? (S_LOG - ST0 - C) : ST0;
     const uint64_t q = pc.q, q2 = 2 * q, nq = 0 - q;
 #pragma unroll
@@ -192,27 +194,84 @@ __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, 
     }
 }
 
-// Rounds of a size-2^S_LOG sub-transform from stage ST0 on: radix-kElems rounds,
-// the last one shorter when kElemsLog does not divide S_LOG.
-template <int S_LOG, int ST0, bool FWD, bool SCALE_LAST, int ROW_A, bool LZ = false>
+// Rounds of a size-2^S_LOG sub-transform from stage ST0 on: radix-E rounds,
+// the last one shorter when log2(E) does not divide S_LOG.
+template <int S_LOG, int ST0, bool FWD, bool SCALE_LAST, int ROW_A, bool LZ = false, int E = kElems>
 __device__ __forceinline__ void ntt_rounds_from(uint64_t *lds, int ldu, int u, int t, uint32_t tw_base,
                                                 const TwPair *__restrict__ tw, const PrimeConst &pc) {
-    constexpr int C = (S_LOG - ST0) < kElemsLog ? (S_LOG - ST0) : kElemsLog;
+    constexpr int CL = ilog2(E);
+    constexpr int C = (S_LOG - ST0) < CL ? (S_LOG - ST0) : CL;
     constexpr bool LAST = ST0 + C == S_LOG;
-    ntt_round<S_LOG, ST0, C, FWD, SCALE_LAST && LAST, ROW_A, false, false, LZ>(lds, ldu, u, t, tw_base, tw, pc);
+    ntt_round<S_LOG, ST0, C, FWD, SCALE_LAST && LAST, ROW_A, false, false, LZ, E>(lds, ldu, u, t, tw_base, tw, pc);
     __syncthreads();
     if constexpr (!LAST)
-        ntt_rounds_from<S_LOG, ST0 + C, FWD, SCALE_LAST, ROW_A, LZ>(lds, ldu, u, t, tw_base, tw, pc);
+        ntt_rounds_from<S_LOG, ST0 + C, FWD, SCALE_LAST, ROW_A, LZ, E>(lds, ldu, u, t, tw_base, tw, pc);
 }
 
 // ROW_A: 0 for the natural twiddle table; A for a row pass reading the row table
-// (which needs exactly two rounds: S_LOG in (kElemsLog, 2 kElemsLog]).
-template <int S_LOG, bool FWD, bool SCALE_LAST, int ROW_A = 0, bool LZ = false>
+// (which needs exactly two rounds of kElems residues: S_LOG in (kElemsLog, 2 kElemsLog]).
+template <int S_LOG, bool FWD, bool SCALE_LAST, int ROW_A = 0, bool LZ = false, int E = kElems>
 __device__ __forceinline__ void ntt_rounds(uint64_t *lds, int ldu, int u, int t, uint32_t tw_base,
                                            const TwPair *__restrict__ tw, const PrimeConst &pc) {
     static_assert(S_LOG >= 5 && S_LOG <= 12, "sub-transform size");
-    static_assert(ROW_A == 0 || (S_LOG > kElemsLog && S_LOG <= 2 * kElemsLog), "row table: two rounds");
-    ntt_rounds_from<S_LOG, 0, FWD, SCALE_LAST, ROW_A, LZ>(lds, ldu, u, t, tw_base, tw, pc);
+    static_assert(ROW_A == 0 || (E == kElems && S_LOG > kElemsLog && S_LOG <= 2 * kElemsLog),
+                  "row table: two rounds of kElems residues");
+    ntt_rounds_from<S_LOG, 0, FWD, SCALE_LAST, ROW_A, LZ, E>(lds, ldu, u, t, tw_base, tw, pc);
+}
+
+// Passes of launches with few limbs (the INTT of the special-prime limbs before
+// ModDown, the INTT of the dropped limb before a rescale): a tile of TILE
+// residues (fewer than kTile) and E residues per thread (fewer than kElems), so
+// such a launch has enough workgroups for every CU and a shorter chain of
+// dependent butterflies per thread; twiddles from the natural table.  Columns:
+// U = TILE / 2^A columns of 2^A rows; rows: U rows of 2^B.  Values in the same
+// ranges as the kTile passes (forward columns lazy below 4q, forward rows in
+// [0, q); inverse rows lazy below 2q, inverse columns in [0, q)).  Ends with a
+// barrier.
+template <int A, int B, bool FWD, int TILE, int E>
+__device__ __forceinline__ void ntt_cols_small(uint64_t *lds, const uint64_t *in, uint64_t *out,
+                                               const TwPair *__restrict__ tw, const PrimeConst &pc, int tile) {
+    constexpr int U = TILE >> A, LDU = U + 1, NT = TILE / E;
+    static_assert(U >= 1 && NT >= 64, "small column tile");
+    const int col0 = tile * U;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int idx = threadIdx.x + r * NT;
+        lds[(idx / U) * LDU + idx % U] = in[((size_t)(idx / U) << B) + col0 + idx % U];
+    }
+    __syncthreads();
+    ntt_rounds<A, FWD, !FWD, 0, false, E>(lds, LDU, threadIdx.x % U, threadIdx.x / U, 1u, tw, pc);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int idx = threadIdx.x + r * NT;
+        const uint64_t x = lds[(idx / U) * LDU + idx % U];
+        out[((size_t)(idx / U) << B) + col0 + idx % U] = FWD ? x : csub(x, pc.q);
+    }
+    __syncthreads();
+}
+
+template <int A, int B, bool FWD, int TILE, int E>
+__device__ __forceinline__ void ntt_rows_small(uint64_t *lds, const uint64_t *in, uint64_t *out,
+                                               const TwPair *__restrict__ tw, const PrimeConst &pc, int tile) {
+    constexpr int S = 1 << B, U = TILE >> B, LDU = U + 1, NT = TILE / E;
+    static_assert(U >= 1 && NT >= 64, "small row tile");
+    const int row0 = tile * U;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int idx = threadIdx.x + r * NT;
+        lds[(idx & (S - 1)) * LDU + (idx >> B)] = in[((size_t)(row0 + (idx >> B)) << B) + (idx & (S - 1))];
+    }
+    __syncthreads();
+    const int u = threadIdx.x % U;
+    ntt_rounds<B, FWD, false, 0, false, E>(lds, LDU, u, threadIdx.x / U, (1u << A) + row0 + u, tw, pc);
+    const uint64_t q2 = 2 * pc.q;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int idx = threadIdx.x + r * NT;
+        const uint64_t x = lds[(idx & (S - 1)) * LDU + (idx >> B)];
+        out[((size_t)(row0 + (idx >> B)) << B) + (idx & (S - 1))] = FWD ? csub(csub(x, q2), pc.q) : x;
+    }
+    __syncthreads();
 }
 
 // Column pass: sub-transforms are columns (2^A rows, stride 2^B), tile
