@@ -42,7 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed-N batch section")
     ap.add_argument("--no-pdq", action="store_true", help="skip the private-query serving section")
-    ap.add_argument("--pdq-queries", type=int, default=60, help="queries per arrival-rate point")
+    ap.add_argument("--pdq-queries", type=int, default=1000, help="queries per arrival-rate point")
+    ap.add_argument("--pdq-warmup", type=int, default=200, help="queries served before the measured points")
     ap.add_argument("--latency-reps", type=int, default=50, help="individually timed reps per op and cache state (0: skip)")
     ap.add_argument("--no-bfv-bgv", action="store_true", help="skip the BFV/BGV section")
     ap.add_argument("--ntt-microbench", action="store_true",
@@ -205,15 +206,23 @@ def main():
         print(json.dumps({"section": args.section, "reps": args.steps, "result": fn(args.steps)}), flush=True)
         return
 
+    import synthetic
+
+    w = synthetic.WORKLOADS[args.workload]
+    cpu = None
+    if not args.no_cpu_baseline:
+        # first, before this process touches the GPU: the all-cores leg runs in
+        # child processes
+        cpu = cpu_baseline(w)
+        _progress("CPU oracle baseline done")
+
     import numpy as np
     import torch
 
-    import synthetic
-    from paper_2503_22227_amd import Context, galois_element
+    from paper_2503_22227_amd import Context
     from paper_2503_22227_amd import _lib
     from paper_2503_22227_amd.params import chain_for
 
-    w = synthetic.WORKLOADS[args.workload]
     ch = chain_for(w)
     n = 1 << w["log_n"]
     ctx = Context(ch["q"], ch["p"], w["log_n"], w["alpha"], log_nmax=w["log_nmax"])
@@ -232,7 +241,7 @@ def main():
     gk = dev(np.stack([np.stack([synthetic.uniform_residues(st["galois"], qp, n) for _ in range(2)])
                        for _ in range(dnum)]))
     r = synthetic.rotation_index(st["rot"], n)
-    g = galois_element(r, n)
+    g = ctx.galois_element(r)
     m_out = ctx.empty(2, L, n)
     r_out = ctx.empty(2, L - 1, n)
     ro_out = ctx.empty(2, L, n)
@@ -303,6 +312,23 @@ def main():
     kernels = {k: {"launches_per_step": c / prof_steps, "avg_us": ms / c * 1e3,
                    "us_per_step": ms / prof_steps * 1e3} for k, (c, ms) in prof.items()}
     dominant = max(kernels, key=lambda k: kernels[k]["us_per_step"])
+    # the same step with the Infinity Cache and the L2s flushed before every
+    # operation (a 1 GiB buffer rewritten on the launch stream): each kernel's
+    # inputs that the operation did not produce itself (keys, ciphertexts) come
+    # from HBM
+    flush = torch.empty(1 << 27, dtype=torch.int64, device="cuda")
+    cold_steps = min(args.steps, 10)
+    _lib.profile_read()
+    for _ in range(cold_steps):
+        for fn in (lambda: ctx.hmult_relin(a, b, rlk, out=m_out), lambda: ctx.rescale(m_out, out=r_out),
+                   lambda: ctx.rotate(a, g, gk, out=ro_out)):
+            flush.fill_(1)
+            _lib.profile_enable(True)
+            fn()
+            _lib.profile_enable(False)
+    torch.cuda.synchronize()
+    cold = {k: ms / c * 1e3 for k, (c, ms) in _lib.profile_read().items()}
+    del flush
 
     # roofline of the dominant kernel: its integer-ALU and HBM fractions, and
     # the larger of the two is the bound it is closest to
@@ -332,6 +358,10 @@ def main():
         roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_frac, 4)}
     copy_gbs = _copy_bandwidth(stream)
+    cold_us = cold.get(dominant)
+    roof.update({"cold_avg_us": round(cold_us, 3) if cold_us else None,
+                 "cold_hbm_frac": round(by / (cold_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) if cold_us else None})
+    roof.update({"passes": _pass_fractions(kernels, cold, L, K, alpha, n, w["log_n"])})
     roof.update({"traffic": traffic, "kernel": dominant, "avg_us": round(kd["avg_us"], 3),
                  "alu_frac": round(alu_frac, 4), "hbm_frac": round(hbm_frac, 4),
                  "algorithmic_bytes": round(by), "work_per_launch": work,
@@ -340,9 +370,11 @@ def main():
                  "copy_gbs": round(copy_gbs, 1), "hbm_frac_of_copy": round(hbm / copy_gbs, 4)})
 
     _progress("timed steps and kernel roofline done")
+    del m_out, r_out, ro_out
+    shapes = other_shapes_section(max(args.steps, 20))
+    _progress("alpha=4 and N=2^12 shapes done")
     batch = None
     if not args.no_batch:
-        del m_out, r_out, ro_out
         batch = batch_section(max(3, min(args.steps, 10)))
         _progress("batched section done")
 
@@ -353,13 +385,8 @@ def main():
 
     serving = None
     if not args.no_pdq:
-        serving = pdq_section(args.pdq_queries)
+        serving = pdq_section(args.pdq_queries, args.pdq_warmup)
         _progress("serving section done")
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w)
-        _progress("CPU oracle baseline done")
 
     line = {
         "metric": "CKKS HMult+Relin/HRotate per sec @N=2^16 L=24",
@@ -383,6 +410,7 @@ def main():
                 "hmult_relin_us": round(t_hm / reps * 1e6, 2), "hrotate_us": round(t_ro / reps * 1e6, 2),
                 "rescale_us": round(t_rs / reps * 1e6, 2)},
         "latency": latency,
+        "shapes": shapes,
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in sorted(kernels.items())},
         "roofline": roof,
         "batch": batch,
@@ -391,6 +419,33 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def _pass_fractions(kernels, cold, L, K, alpha, n, log_n):
+    """HBM (and, for NTT passes, integer-ALU) fraction of every kernel of the step,
+    warm and cold, from its byte and butterfly model."""
+    out = {}
+    for k, v in sorted(kernels.items()):
+        if k.startswith("ntt"):
+            limbs, by = _ntt_launch_model(k, L, K, alpha, n)
+            bfly = limbs * (n // 2) * (log_n // 2) if limbs == limbs else 0
+        else:
+            op = "rotate" if k == "automorphism" else "hmult"
+            by = algorithmic_bytes(k, L, K, alpha, n, op)
+            if k == "inner_product":
+                by = (by + algorithmic_bytes(k, L, K, alpha, n, "rotate")) / 2
+            bfly = 0
+        if by != by:  # no byte model for this kernel
+            continue
+        row = {"avg_us": round(v["avg_us"], 2), "mb": round(by / 1e6, 1),
+               "hbm_frac": round(by / (v["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 3)}
+        if bfly:
+            row["alu_frac"] = round(bfly * BFLY_OPS / (v["avg_us"] * 1e-6) / VALU_SLOTS_PER_S, 3)
+        if k in cold:
+            row["cold_us"] = round(cold[k], 2)
+            row["cold_hbm_frac"] = round(by / (cold[k] * 1e-6) / 1e9 / HBM_PEAK_GBS, 3)
+        out[k] = row
+    return out
 
 
 # Algorithmic integer work of one Harvey butterfly with a Shoup product on
@@ -443,18 +498,77 @@ def _ntt_launch_model(name: str, L: int, K: int, alpha: int, n: int):
     launches = {
         "ntt_inv_rows_tensor": [(L, 2 * L + L, L)],                   # a1, b1 in; row pass of d2 = a1 b1 out
         "ntt_inv_rows_gather": [(L, L + L, L)],                       # c1 gathered in; row pass out
-        "ntt_inv_rows": [(2 * K, 4 * K, K)] * 2 + [(2, 4, 1)],        # P-limbs (x2 ops), rescale's last limb
-        "ntt_inv_cols": [(L, 2 * L, 0)] * 2 + [(2 * K, 4 * K, 0)] * 2 + [(2, 4, 0)],
+        # few-limb launches (fewer tiles than CUs) run the small-tile passes:
+        # the P-limbs of both key switches and rescale's last limb
+        "ntt_inv_rows_small": [(2 * K, 4 * K, K)] * 2 + [(2, 4, 1)],
+        "ntt_inv_cols_small": [(2 * K, 4 * K, 0)] * 2 + [(2, 4, 0)],
+        "ntt_inv_cols": [(L, 2 * L, 0)] * 2,                          # d2 / sigma(c1)
         "ntt_fwd_cols": [(ext, 2 * ext, 0)] * 2,                      # ModUp NTT
         "ntt_fwd_rows": [(ext, 2 * ext, L + K)] * 2,
         "ntt_fwd_cols_moddown": [(2 * L, 2 * K + 2 * L, 0)] * 2,      # P-limbs in, conv out
         "ntt_fwd_rows_moddown": [(2 * L, 6 * L, L)] * 2,              # conv, folded ip in; out
         "ntt_fwd_cols_lift": [(2 * (L - 1), 2 + 2 * (L - 1), 0)],     # last limb in, lift out
         "ntt_fwd_rows_rescale": [(2 * (L - 1), 2 * (L - 1) * 3, L - 1)],
-    }[name]
+    }.get(name)
+    if launches is None:
+        return float("nan"), float("nan")
     limbs = sum(x[0] for x in launches) / len(launches)
     by = sum(x[1] * limb + x[2] * tw for x in launches) / len(launches)
     return limbs, by
+
+
+def other_shapes_section(reps: int):
+    """The other single-ciphertext shapes: N = 2^16, 24 limbs with alpha = 4 (dnum = 6,
+    the shape whose special modulus covers a digit, so results decrypt), and the small
+    N = 2^12 chain (60 + 40-bit primes, one special prime, alpha = 1) whose
+    HMult+Relin -> rescale is launch-bound.  Per-op times from back-to-back loops."""
+    import torch
+
+    import synthetic
+    from paper_2503_22227_amd import Context
+    from paper_2503_22227_amd.params import chain_for
+
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3  # us
+
+    out = {}
+    for name, label in (("ckks_n16_l24_a4", "n16_l24_alpha4"), ("ckks_n12", "n12_l2_alpha1")):
+        w = synthetic.WORKLOADS[name]
+        ch = chain_for(w)
+        n = 1 << w["log_n"]
+        ctx = Context(ch["q"], ch["p"], w["log_n"], w["alpha"], log_nmax=w["log_nmax"])
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(w["seed"])
+        qp = ch["q"] + ch["p"]
+        L = len(ch["q"])
+        a = torch.stack([synthetic.device_uniform_residues(ch["q"], n, gen, "cuda") for _ in range(2)])
+        b = torch.stack([synthetic.device_uniform_residues(ch["q"], n, gen, "cuda") for _ in range(2)])
+        key = lambda: torch.stack([torch.stack([synthetic.device_uniform_residues(qp, n, gen, "cuda")  # noqa: E731
+                                                for _ in range(2)]) for _ in range(ctx.dnum)])
+        rlk, gk = key(), key()
+        g = ctx.galois_element(int(synthetic.rotation_index(synthetic.streams(w["seed"])["rot"], n)))
+        mo, ro, rs = torch.empty_like(a), torch.empty_like(a), ctx.empty(2, L - 1, n)
+        hm = timed(lambda: ctx.hmult_relin(a, b, rlk, out=mo))
+        rt = timed(lambda: ctx.rotate(a, g, gk, out=ro))
+        sc = timed(lambda: ctx.rescale(mo, out=rs))
+        chain = timed(lambda: (ctx.hmult_relin(a, b, rlk, out=mo), ctx.rescale(mo, out=rs)))
+        out[label] = {"log_n": w["log_n"], "limbs": L, "special_primes": len(ch["p"]), "alpha": w["alpha"],
+                      "dnum": ctx.dnum, "hmult_relin_us": round(hm, 2), "hrotate_us": round(rt, 2),
+                      "rescale_us": round(sc, 2), "hmult_relin_rescale_us": round(chain, 2),
+                      "hmult_relin_per_s": round(1e6 / hm, 1), "hrotate_per_s": round(1e6 / rt, 1)}
+        del a, b, rlk, gk, mo, ro, rs
+        ctx.close()
+    return out
 
 
 def batch_section(reps: int):
@@ -560,15 +674,21 @@ def bfv_bgv_section(reps: int):
     return out
 
 
-def pdq_section(n_queries: int):
-    """Private-table range-sum queries at CKKS N=2^16, 24 limbs, alpha=4, scale 2^45 served
-    by the continuous-batching server: saturation rate from a burst, then Poisson
-    arrivals at 0.25 / 0.5 / 0.75 / 0.9 of it; p50/p99 latency (arrival to result on host)."""
+def pdq_section(n_queries: int, n_warmup: int):
+    """Private-table range-sum and search-and-average queries at CKKS N=2^16, 24 limbs,
+    alpha=4, scale 2^45 served by the continuous-batching server, with keys, tables
+    and the multiply-inverse client step made by the client-side kernels:
+    saturation rate from a burst, then Poisson
+    arrivals at 0.25 / 0.5 / 0.75 / 0.9 of it (4 slots, 6 GiB budget); one point where
+    the budget, not the slot count, bounds admission (8 slots); one uncapped run
+    (8 slots, no budget).  Latency = arrival to result on the host; p50 / p99 over
+    ``n_queries`` queries per point after ``n_warmup`` served first."""
     import numpy as np
     import torch
 
     import synthetic
     from paper_2503_22227_amd import Context, pdq
+    from paper_2503_22227_amd import _lib
     from paper_2503_22227_amd.params import chain_for
     from paper_2503_22227_amd.serve import GpuQueryExecutor, Request, Server
 
@@ -576,63 +696,97 @@ def pdq_section(n_queries: int):
     ch = chain_for(w)
     n = 1 << w["log_n"]
     L = len(ch["q"])
+    D = 2.0 ** w["log_scale"]
     ctx = Context(ch["q"], ch["p"], w["log_n"], w["alpha"], log_nmax=w["log_nmax"])
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(w["seed"])
-    qp = ch["q"] + ch["p"]
-
-    def key():
-        return torch.stack([torch.stack([synthetic.device_uniform_residues(qp, n, gen, "cuda") for _ in range(2)])
-                            for _ in range(ctx.dnum)])
-
-    keys = {"rlk": key()}
-    for i in range(12):
-        keys[1 << i] = key()
-    opx = pdq.GpuExecutor(ctx, keys)
     st = synthetic.streams(w["seed"])
     rng = st["arrivals"]
+    # the client side on the GPU: secret key, relinearisation and power-of-two
+    # rotation keys, encrypted tables and bounds
+    s_ntt = ctx.key_ntt(torch.from_numpy(synthetic.ternary(st["sk"], n)).cuda())
+    client = pdq.GpuClient(ctx, s_ntt, st["ct_a"], st["ct_e"])
+    keys = client.switch_keys([1 << i for i in range(12)], st["rlk"])
+    opx = pdq.GpuExecutor(ctx, keys, client)
     ct_bytes = 2 * L * n * 8
-    slots = 4
+    # the key-switching workspace every slot holds (HMult+Relin needs the most)
+    ws_bytes = max(ctx.workspace_bytes(_lib.RF_OP_HMULT_RELIN, L), ctx.workspace_bytes(_lib.RF_OP_ROTATE, L))
+    # queries read their encrypted table and bounds and never write them: one
+    # table per row padding (16 .. 1024 rows) and a pool of bounds are shared
+    tables = {}
+    for k in range(4, 11):
+        rows_t = int(rng.integers((1 << (k - 1)) + 1, (1 << k) + 1))
+        tables[1 << k] = client.encrypt_table(rng.integers(0, 1000, size=(rows_t, 4)), L, D)
+    bounds = []
+    for _ in range(8):
+        lo, hi = sorted(int(x) for x in rng.integers(0, 1000, 2))
+        bounds.append(client.encrypt_bounds(lo, hi, L, D))
+    plans = {}
 
-    def make(count, rate, t0=0.0):
-        reqs, t = [], t0
+    def make(count, rate):
+        reqs, t = [], 0.0
         for i in range(count):
             rows = int(round(np.exp(rng.uniform(np.log(10), np.log(1000)))))
             a, b = (int(x) for x in rng.choice(4, 2, replace=False))
-            ops, outs, regs = pdq.plan_query(ch["q"], L, 2.0 ** w["log_scale"], rows, a, b)
-            inputs = {k: torch.stack([synthetic.device_uniform_residues(ch["q"], n, gen, "cuda") for _ in range(2)])
-                      for k in ("T", "LO", "HI")}
-            fp = (pdq.peak_live(ops, outputs=outs) + 3) * ct_bytes
+            avg = rng.random() < 0.25  # a quarter are search-and-average queries
+            key = (rows, a, b, avg)
+            if key not in plans:
+                if avg:
+                    r = float(np.exp(rng.uniform(0.0, np.log(64.0))))
+                    ops, outs, regs = pdq.plan_average_query(ch["q"], L, D, rows, a, b, r)
+                else:
+                    ops, outs, regs = pdq.plan_query(ch["q"], L, D, rows, a, b)
+                plans[key] = (ops, outs, (pdq.peak_live(ops, outputs=outs) + 3 + int(avg)) * ct_bytes)
+            ops, outs, fp = plans[key]
             if rate:
                 t += rng.exponential(1.0 / rate)
-            reqs.append(Request(rid=i, arrival=t, ops=ops, inputs=inputs, outputs=outs, footprint=fp))
+            lo_ct, hi_ct = bounds[i % len(bounds)]
+            reqs.append(Request(rid=i, arrival=t, ops=ops,
+                                inputs={"T": tables[pdq.r_pad(rows)], "LO": lo_ct, "HI": hi_ct}, outputs=outs,
+                                footprint=fp))
+        torch.cuda.synchronize()  # keys, tables and bounds are written before any query starts
         return reqs
 
+    def serve(reqs, slots, budget):
+        # every slot keeps its own workspace: charged once per slot, not per query
+        avail = (1 << 62) if budget is None else budget - slots * ws_bytes
+        return Server(GpuQueryExecutor(opx, slots), avail, slots=slots).run(reqs)
+
+    def point(s2, **kw):
+        d = {"queries_per_s": round(s2.completed / s2.makespan, 2), "p50_ms": round(s2.percentile(50) * 1e3, 2),
+             "p99_ms": round(s2.percentile(99) * 1e3, 2), "samples": len(s2.latencies), "completed": s2.completed,
+             "failed": s2.failed, "peak_inflight": s2.peak_inflight, "peak_admitted_gib": round(s2.peak_bytes / 2 ** 30, 2)}
+        d.update(kw)
+        return d
+
     budget = 6 << 30
-    warm = make(slots, 0)
-    Server(GpuQueryExecutor(opx, slots), budget, slots=slots).run(warm)
+    serve(make(n_warmup, 0), 4, budget)
     burst = make(n_queries, 0)
-    stb = Server(GpuQueryExecutor(opx, slots), budget, slots=slots).run(burst)
+    stb = serve(burst, 4, budget)
     sat = stb.completed / stb.makespan
     points = []
     for f in (0.25, 0.5, 0.75, 0.9):
-        reqs = make(n_queries, f * sat)
-        s2 = Server(GpuQueryExecutor(opx, slots), budget, slots=slots).run(reqs)
-        points.append({"load": f, "arrival_rate_qps": round(f * sat, 2),
-                       "queries_per_s": round(s2.completed / s2.makespan, 2),
-                       "p50_ms": round(s2.percentile(50) * 1e3, 2), "p99_ms": round(s2.percentile(99) * 1e3, 2),
-                       "completed": s2.completed, "failed": s2.failed, "peak_inflight": s2.peak_inflight})
-    return {"workload": "range-sum queries, CKKS N=2^16 24 limbs alpha=4 scale 2^45, tables of 10..1000 rows x 4 "
-                        "columns (log-uniform), %d queries per point, %d stream slots, 6 GiB admission budget"
-                        % (n_queries, slots),
+        points.append(point(serve(make(n_queries, f * sat), 4, budget), load=f, arrival_rate_qps=round(f * sat, 2),
+                            slots=4, budget_gib=6))
+    mean_fp = float(np.mean([r.footprint for r in burst]))
+    tight = 8 * ws_bytes + int(2.5 * mean_fp)
+    points.append(point(serve(make(n_queries, 0.9 * sat), 8, tight), load=0.9, arrival_rate_qps=round(0.9 * sat, 2),
+                        slots=8, budget_gib=round(tight / 2 ** 30, 2), note="budget-bound admission"))
+    points.append(point(serve(make(n_queries, 0.9 * sat), 8, None), load=0.9, arrival_rate_qps=round(0.9 * sat, 2),
+                        slots=8, budget_gib=None, note="uncapped admission"))
+    return {"workload": "range-sum queries (a quarter search-and-average, with the client's multiply-inverse "
+                        "step on the GPU), CKKS N=2^16 24 limbs alpha=4 scale 2^45, tables of 10..1000 rows x 4 "
+                        "columns (log-uniform), keys and encrypted tables made by the GPU client, %d queries per "
+                        "point after %d warm-up, Poisson arrivals" % (n_queries, n_warmup),
             "ops_per_query_mean": round(float(np.mean([len(r.ops) for r in burst])), 1),
+            "query_footprint_mean_mib": round(mean_fp / 2 ** 20, 1),
+            "slot_workspace_mib": round(ws_bytes / 2 ** 20, 1),
             "saturation_qps": round(sat, 2), "burst_p50_ms": round(stb.percentile(50) * 1e3, 2),
             "burst_p99_ms": round(stb.percentile(99) * 1e3, 2), "points": points}
 
 
-def cpu_baseline(w, min_seconds: float = 10.0, max_pairs: int = 12):
-    """The oracle, as it stands, on a bounded sample: HMult+Relin / HRotate pairs at full
-    size, repeated until at least ``min_seconds`` of CPU work (at most ``max_pairs``)."""
+def _oracle_pairs(args):
+    """Worker: ``pairs`` HMult+Relin + HRotate pairs of the oracle at full size; returns
+    (pairs, seconds of the timed loop)."""
+    w, pairs, seed = args
     import numpy as np
 
     import synthetic
@@ -640,23 +794,65 @@ def cpu_baseline(w, min_seconds: float = 10.0, max_pairs: int = 12):
     from oracle import params as P
 
     p = P.make_params(w)
-    rng = np.random.default_rng(1)
+    rng = np.random.default_rng(seed)
     ct = lambda: np.stack([synthetic.uniform_residues(rng, p.q, p.n) for _ in range(2)])  # noqa: E731
     qp = p.q + p.p
     key = lambda: np.stack([np.stack([synthetic.uniform_residues(rng, qp, p.n) for _ in range(2)])  # noqa: E731
                             for _ in range(p.dnum())])
     a, b, rlk, gk = ct(), ct(), key(), key()
     g = C.galois_element(3, p.n)
-    pairs = 0
     t0 = time.perf_counter()
-    while pairs < max_pairs and (pairs == 0 or time.perf_counter() - t0 < min_seconds):
+    for _ in range(pairs):
         C.hmult_relin(C.Ciphertext(a, 1.0), C.Ciphertext(b, 1.0), rlk, p)
         C.rotate(C.Ciphertext(a, 1.0), g, gk, p)
-        pairs += 1
-    dt = time.perf_counter() - t0
-    return {"value": round(2 * pairs / dt, 4), "unit": "ops/s", "cores": 1, "kind": "oracle",
-            "sample": "%d HMult+Relin + %d HRotate at N=2^16, 24 limbs, dnum=3 (%.1f s, single thread)"
-                      % (pairs, pairs, dt),
+    return pairs, time.perf_counter() - t0
+
+
+def cpu_baseline(w, min_seconds: float = 10.0, max_pairs: int = 12):
+    """The oracle, as it stands, on a bounded sample of the same workload.
+    Single thread: HMult+Relin / HRotate pairs at full size until at least
+    ``min_seconds`` (at most ``max_pairs``).  All host cores: one process per
+    logical CPU (at most 16), each timing one pair on its own operands; the
+    rate is the pairs over the slowest process's loop.  Also the BFV and BGV
+    HMult+Relin of the N = 2^15, 14-limb chain, one each, single thread."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import synthetic
+    from oracle import bfv as OF
+    from oracle import bgv as OB
+    from oracle import params as P
+
+    pairs, dt = 0, 0.0
+    while pairs < max_pairs and (pairs == 0 or dt < min_seconds):
+        k, t = _oracle_pairs((w, 1, 1 + pairs))
+        pairs, dt = pairs + k, dt + t
+    procs = max(1, min(16, os.cpu_count() or 1))
+    with mp.get_context("spawn").Pool(procs) as pool:
+        res = pool.map(_oracle_pairs, [(w, 1, 100 + i) for i in range(procs)])
+    par_dt = max(t for _, t in res)
+    exact = {}
+    for name in ("bfv_n15", "bgv_n15"):
+        wx = synthetic.WORKLOADS[name]
+        p = P.make_params(wx)
+        rng = np.random.default_rng(2)
+        ct = np.stack([synthetic.uniform_residues(rng, p.q, p.n) for _ in range(2)])
+        qp = p.q + p.p
+        rlk = np.stack([np.stack([synthetic.uniform_residues(rng, qp, p.n) for _ in range(2)])
+                        for _ in range(p.dnum())])
+        t0 = time.perf_counter()
+        if name == "bfv_n15":
+            OF.hmult_relin(ct, ct, rlk, p)
+        else:
+            OB.hmult_relin(OB.Ciphertext(ct), OB.Ciphertext(ct), rlk, p)
+        exact[wx["scheme"]] = {"hmult_relin_s": round(time.perf_counter() - t0, 3)}
+    return {"value": round(2 * procs / par_dt, 4), "unit": "ops/s", "cores": procs, "kind": "oracle",
+            "sample": "%d processes, each 1 HMult+Relin + 1 HRotate at N=2^16, 24 limbs, dnum=3 (slowest %.1f s)"
+                      % (procs, par_dt),
+            "single_thread": {"value": round(2 * pairs / dt, 4), "cores": 1,
+                              "sample": "%d HMult+Relin + %d HRotate (%.1f s)" % (pairs, pairs, dt)},
+            "bfv_bgv_single_thread": exact,
             "host_cpu": _cpu_model(), "host_logical_cpus": os.cpu_count()}
 
 

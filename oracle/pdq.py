@@ -2,6 +2,11 @@
 lists with the oracle's CKKS operations, and the float64 evaluation of the
 same circuit.  Test infrastructure only.
 
+Search-and-average (section IV-C) adds the paper's two-party multiply-inverse
+of the count: the server masks it by a random r, the client (``Client``)
+decrypts, inverts and re-encrypts, the server unmasks by r and multiplies by
+the sum.
+
 The circuit (section IV of the paper: search-and-sum over an encrypted table;
 its comparison method is only cited, so the composite sign polynomial stands
 in): mask_r = ((F(x_a[r] - lo') + 1)/2) ((F(hi' - x_a[r]) + 1)/2) with
@@ -75,18 +80,49 @@ def exact_answer(values: np.ndarray, lo: int, hi: int, col_a: int, col_b: int):
     return float(values[sel, col_b].sum() / ROWS_SCALE), float(sel.sum())
 
 
+def reference_average(values: np.ndarray, lo: int, hi: int, col_a: int, col_b: int) -> float:
+    """float64 evaluation of the search-and-average circuit: sum / count of ``reference``."""
+    total, count = reference(values, lo, hi, col_a, col_b)
+    return total / count
+
+
+class Client:
+    """The data holder in the two-party multiply-inverse (section IV-C, Algorithm
+    "The Two-Party Multiply-Inverse Method"), on the oracle.  Given the server's
+    C1 = Enc(r x) it decrypts x1 = Dec(C1) (slot 0), computes x2 = 1 / x1 and
+    returns a fresh encryption of x2 in every slot: the constant polynomial
+    round(x2 scale), secret-key encrypted with masks from ``rng_a`` and errors
+    from ``rng_e``."""
+
+    def __init__(self, params, s, rng_a, rng_e):
+        self.p = params
+        self.s = s
+        self.rng_a = rng_a
+        self.rng_e = rng_e
+
+    def inverse(self, ct: C.Ciphertext, src_scale: float, limbs: int, scale: float) -> C.Ciphertext:
+        p = self.p
+        x1 = C.decode(C.decrypt(p, self.s, C.Ciphertext(ct.data, src_scale)), src_scale, p.n)[0].real
+        x2 = 1.0 / x1
+        m = np.zeros(p.n, dtype=object)
+        m[0] = int(round(x2 * scale))
+        return C.encrypt(p, self.s, m, limbs, scale, self.rng_a, self.rng_e)
+
+
 def rotation_keys(params, s, amounts, rng) -> dict:
     """{r: Galois key rotating slots left by r}."""
     return {r: C.galois_key(params, s, C.galois_element(r, params.n), rng) for r in amounts}
 
 
 class Executor:
-    """Runs an op list with the oracle (registers are oracle Ciphertexts)."""
+    """Runs an op list with the oracle (registers are oracle Ciphertexts);
+    ``client`` answers the multiply-inverse's client steps."""
 
-    def __init__(self, params, rlk, gkeys: dict):
+    def __init__(self, params, rlk, gkeys: dict, client=None):
         self.p = params
         self.rlk = rlk
         self.gkeys = gkeys
+        self.client = client
 
     def run(self, ops, regs: dict) -> dict:
         for op in ops:
@@ -114,5 +150,7 @@ class Executor:
         elif kind == "drop":
             src = regs[op[2]]
             regs[dst] = C.Ciphertext(src.data[:, :op[3]].copy(), src.scale)
+        elif kind == "client_inv":
+            regs[dst] = self.client.inverse(regs[op[2]], op[3], op[4], op[5])
         else:
             raise ValueError("unknown op %r" % (kind,))

@@ -24,6 +24,12 @@ executor here and by any other executor.  Ops:
     ("mul_int", dst, src, k)    multiply by the integer k
     ("add_int", dst, src, k)    add the integer k to every slot value * scale
     ("drop", dst, src, limbs)   keep the first `limbs` limbs
+    ("client_inv", dst, src, src_scale, limbs, scale)
+                                the two-party multiply-inverse's client step
+                                (section IV-C): the data holder decrypts src,
+                                inverts its slot 0 and sends back a fresh
+                                encryption of that constant at `limbs` limbs
+                                and `scale`
 """
 from __future__ import annotations
 
@@ -140,6 +146,13 @@ class Planner:
             bit += 1
         return cur
 
+    def client_inverse(self, a: str, limbs: int, scale: float) -> str:
+        """Fresh encryption of 1 / slot0(a) in every slot, made by the client."""
+        d = self._tmp()
+        self.ops.append(("client_inv", d, a, self.scale(a), limbs, scale))
+        self.regs[d] = (limbs, scale)
+        return d
+
     def odd_poly15(self, x: str, coef) -> str:
         """sum_k coef[k] x^(2k+1): y = x^2, q(y) by baby-step giant-step, result x q(y)."""
         y = self.mul(x, x)
@@ -198,6 +211,28 @@ def plan_query(q: List[int], limbs: int, scale: float, rows: int, col_a: int, co
     return pl.ops, (s, c), pl.regs
 
 
+def plan_average_query(q: List[int], limbs: int, scale: float, rows: int, col_a: int, col_b: int, r: float):
+    """Op list of one search-and-average query (section IV-C): the range-sum circuit,
+    then the two-party multiply-inverse of the count (the paper's Algorithm "The
+    Two-Party Multiply-Inverse Method"): the server masks the count by its random
+    r, the client decrypts r count, inverts it and encrypts 1 / (r count) afresh,
+    the server multiplies that by r (giving 1 / count) and by the sum.  Inputs T,
+    LO, HI; outputs (average, sum, count), the average in slot 0."""
+    pl = Planner(q)
+    T = pl.input("T", limbs, scale)
+    LO = pl.input("LO", limbs, scale)
+    HI = pl.input("HI", limbs, scale)
+    width = r_pad(rows)
+    xa = pl.rot(T, col_a * width)
+    xb = pl.rot(T, col_b * width)
+    mask = pl.mul(pl.sign01(pl.sub(xa, LO)), pl.sign01(pl.sub(HI, xa)))
+    s = pl.rotsum(pl.mul(mask, xb), width)
+    c = pl.rotsum(mask, width)
+    inv = pl.client_inverse(pl.mulc(c, r), limbs, scale)
+    avg = pl.mul(s, pl.mulc(inv, r))
+    return pl.ops, (avg, s, c), pl.regs
+
+
 def rotation_amounts(ops) -> List[int]:
     return sorted({op[3] for op in ops if op[0] == "rot"})
 
@@ -220,16 +255,107 @@ def peak_live(ops, inputs=("T", "LO", "HI"), outputs=()) -> int:
     return peak
 
 
+class GpuClient:
+    """The data holder's side of the multiply-inverse protocol on the GPU (the
+    client runs the same framework, section IV-A): its secret key in the NTT
+    domain and its own random streams for fresh encryptions (numpy Generators
+    drawn in the order of the oracle's encryption: masks from ``rng_a``, errors
+    from ``rng_e``)."""
+
+    def __init__(self, ctx, s_ntt, rng_a, rng_e):
+        self.ctx = ctx
+        self.s_ntt = s_ntt
+        self.rng_a = rng_a
+        self.rng_e = rng_e
+
+    def slot0(self, ct, scale: float) -> float:
+        """Real part of slot 0 of the decryption of ct (waits for the stream)."""
+        c = self.ctx
+        z = c.decode(c.crt_centered(c.decrypt(ct, self.s_ntt), scale))
+        return float(z[0].real.item())
+
+    def _encrypt(self, m, limbs: int):
+        import numpy as np
+        import torch
+
+        import synthetic
+        c = self.ctx
+        a = synthetic.uniform_residues(self.rng_a, c.q[:limbs], c.n)
+        e = synthetic.gaussian(self.rng_e, c.n)
+        return c.encrypt(m, torch.from_numpy(e).to(c.device), torch.from_numpy(a.view(np.int64)).to(c.device),
+                         self.s_ntt)
+
+    def encrypt_constant(self, v: float, limbs: int, scale: float):
+        """Fresh encryption of v in every slot: the constant polynomial round(v scale)
+        (0 for a value that is not finite or does not fit the coefficient)."""
+        import math
+
+        import torch
+        c = self.ctx
+        k = v * scale
+        m = torch.zeros(c.n, dtype=torch.int64, device=c.device)
+        m[0] = int(round(k)) if math.isfinite(k) and abs(k) < 2.0 ** 62 else 0
+        return self._encrypt(m, limbs)
+
+    def encrypt_slots(self, z, limbs: int, scale: float):
+        """Fresh encryption of the complex128 slot vector z (N/2 values): GPU encode, then encrypt."""
+        import torch
+        return self._encrypt(self.ctx.encode(torch.as_tensor(z).to(self.ctx.device), scale), limbs)
+
+    def encrypt_table(self, values, limbs: int, scale: float):
+        """The table [rows][4] of integers in [0, 1000): column c, row r at slot c R_pad + r
+        holding v / 2000, padding rows -0.5 (see the module docstring)."""
+        import numpy as np
+        rows = len(values)
+        w = r_pad(rows)
+        z = np.zeros(self.ctx.n // 2, dtype=np.complex128)
+        for c in range(4):
+            z[c * w:(c + 1) * w] = -0.5
+            z[c * w:c * w + rows] = np.asarray(values)[:, c] / 2000.0
+        return self.encrypt_slots(z, limbs, scale)
+
+    def encrypt_bounds(self, lo: int, hi: int, limbs: int, scale: float):
+        """(LO, HI): (lo - 1/2) / 2000 and (hi + 1/2) / 2000 in every slot."""
+        return (self.encrypt_constant((lo - 0.5) / 2000.0, limbs, scale),
+                self.encrypt_constant((hi + 0.5) / 2000.0, limbs, scale))
+
+    def switch_keys(self, amounts, rng):
+        """{"rlk": relinearisation key, r: Galois key of the rotation by r} made on the GPU
+        from the secret key, with masks and errors drawn from ``rng``."""
+        import numpy as np
+        import torch
+
+        import synthetic
+        c = self.ctx
+        qp = c.q + c.p
+
+        def one(g):
+            a = np.stack([synthetic.uniform_residues(rng, qp, c.n) for _ in range(c.dnum)])
+            e = np.stack([synthetic.gaussian(rng, c.n) for _ in range(c.dnum)])
+            return c.keygen_switch(self.s_ntt, g, torch.from_numpy(a.view(np.int64)).to(c.device),
+                                   torch.from_numpy(e).to(c.device))
+
+        keys = {"rlk": one(0)}
+        for r in amounts:
+            keys[r] = one(c.galois_element(r))
+        return keys
+
+    def inverse(self, ct, src_scale: float, limbs: int, scale: float):
+        return self.encrypt_constant(1.0 / self.slot0(ct, src_scale), limbs, scale)
+
+
 class GpuExecutor:
     """Runs op lists with the library on the current torch stream.
 
     keys: {"rlk": tensor, r: galois key tensor for rotation by r}.  ``slot``
     selects the workspace set, so op lists on different streams never share
-    scratch memory."""
+    scratch memory.  ``client``: the GpuClient (or any object with its
+    ``inverse``) that answers "client_inv" steps."""
 
-    def __init__(self, ctx, keys: dict):
+    def __init__(self, ctx, keys: dict, client=None):
         self.ctx = ctx
         self.keys = keys
+        self.client = client
         self.gal = {r: ctx.galois_element(r) for r in keys if r != "rlk"}
 
     def run(self, ops, regs: dict, slot: int = 0) -> dict:
@@ -257,6 +383,10 @@ class GpuExecutor:
         elif kind == "drop":
             src = regs[op[2]]
             regs[dst] = src[:, :op[3]].contiguous()
+        elif kind == "client_inv":
+            if self.client is None:
+                raise ValueError("a client_inv step needs a client")
+            regs[dst] = self.client.inverse(regs[op[2]], op[3], op[4], op[5])
         else:
             raise ValueError("unknown op %r" % (kind,))
 

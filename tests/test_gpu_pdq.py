@@ -155,3 +155,58 @@ def test_server_alone_equals_mixed_n16():
     for (ops, outs, regs), ra, rm in zip(plans, alone, mixed):
         for r in outs:
             assert torch.equal(ra.result[r], rm.result[r]), (ra.rid, r)
+
+
+class _Recorder:
+    """Oracle client that keeps every fresh ciphertext it sends, for replay."""
+
+    def __init__(self, inner):
+        self.inner = inner
+        self.sent = []
+
+    def inverse(self, *args):
+        ct = self.inner.inverse(*args)
+        self.sent.append(ct)
+        return ct
+
+
+class _Replay:
+    def __init__(self, sent):
+        self.sent = list(sent)
+
+    def inverse(self, *args):
+        return dev(self.sent.pop(0).data)
+
+
+def test_search_and_average_gpu_equals_oracle(setup):
+    """Search-and-average (the two-party multiply-inverse of the count): the server's
+    steps on the GPU are bit-identical to the oracle's, every register, given the
+    client's fresh ciphertext; then the whole protocol with the client on the GPU too
+    (decrypt, CRT, decode, invert, encrypt: the client-side kernels) decrypts to the
+    float64 evaluation of sum / count."""
+    import synthetic
+    from paper_2503_22227_amd import pdq
+    q, p = setup["q"], setup["p"]
+    ops, outs, regs = pdq.plan_average_query(p.q, p.L, q["D"], setup["rows"], q["a"], q["b"], 37.25)
+    print("search-and-average op list of %d ops" % len(ops), flush=True)
+    st = synthetic.streams(99)
+    rec = _Recorder(OQ.Client(p, setup["s"], st["ct_a"], st["ct_e"]))
+    want = OQ.Executor(p, setup["rlk"], setup["gk"], rec).run(ops, dict(q["inputs"]))
+    opx = pdq.GpuExecutor(setup["ctx"], setup["opx"].keys, _Replay(rec.sent))
+    got = opx.run(ops, gpu_inputs(q["inputs"]))
+    assert set(got) == set(want)
+    for r in sorted(got):
+        assert np.array_equal(host(got[r]), want[r].data), r
+    ref = OQ.reference_average(q["vals"], q["lo"], q["hi"], q["a"], q["b"])
+    ctx = setup["ctx"]
+    s_ntt = ctx.key_ntt(torch.from_numpy(np.asarray(setup["s"], dtype=np.int64)).cuda())
+    st = synthetic.streams(99)
+    client = pdq.GpuClient(ctx, s_ntt, st["ct_a"], st["ct_e"])
+    got = pdq.GpuExecutor(ctx, setup["opx"].keys, client).run(ops, gpu_inputs(q["inputs"]))
+    avg = client.slot0(got[outs[0]], regs[outs[0]][1])
+    assert abs(avg - ref) < 5e-3
+    # the GPU client reads the masked count as the oracle client does
+    inv = [op for op in ops if op[0] == "client_inv"][0]
+    x1_gpu = client.slot0(got[inv[2]], inv[3])
+    x1 = C.decode(C.decrypt(p, setup["s"], C.Ciphertext(host(got[inv[2]]), inv[3])), inv[3], p.n)[0].real
+    assert abs(x1_gpu - x1) <= 1e-9 * abs(x1)

@@ -131,3 +131,49 @@ def test_circuit_on_oracle_matches_float_evaluation():
     got_s = C.decode(C.decrypt(p, s, out[so]), regs[so][1], p.n)[0].real
     got_c = C.decode(C.decrypt(p, s, out[co]), regs[co][1], p.n)[0].real
     assert abs(got_s - ref[0]) < 0.05 and abs(got_c - ref[1]) < 0.05
+
+
+def _oracle_keys(q):
+    p, s = q["p"], q["s"]
+    return C.relin_key(p, s, q["st"]["rlk"]), OQ.rotation_keys(p, s, [1 << i for i in range(11)], q["st"]["galois"])
+
+
+@pytest.mark.parametrize("x", [1.0, 3.0, 117.0, 1000.0, 0.125])
+def test_multiply_inverse_protocol_on_oracle(x):
+    """The paper's two-party multiply-inverse on a fresh encryption of x in every slot:
+    the server masks by r, the client inverts slot 0 of the decryption and re-encrypts,
+    the server unmasks by r.  Pin: the result decrypts to 1/x within 2^-30 (the paper
+    reports 32 fractional bits; here the noise of the rescales after the masking
+    products bounds it)."""
+    w = synthetic.WORKLOADS["pdq"]
+    p = P.make_params(w).at_degree(12)
+    st = synthetic.streams(w["seed"])
+    s = C.secret_key(p, st["sk"])
+    rlk = C.relin_key(p, s, st["rlk"])
+    D = 2.0 ** w["log_scale"]
+    ct = C.encrypt(p, s, C.encode(np.full(p.n // 2, x, dtype=np.complex128), D, p.n), p.L, D, st["ct_a"], st["ct_e"])
+    r = 13.75
+    pl = pdq.Planner(p.q)
+    X = pl.input("X", p.L, D)
+    y = pl.mulc(pl.client_inverse(pl.mulc(X, r), p.L, D), r)
+    cl = OQ.Client(p, s, st["ct_a"], st["ct_e"])
+    res = OQ.Executor(p, rlk, {}, cl).run(pl.ops, {"X": ct})
+    got = C.decode(C.decrypt(p, s, res[y]), pl.scale(y), p.n)
+    assert [op[0] for op in pl.ops] == ["mul_int", "rescale", "client_inv", "mul_int", "rescale"]
+    assert np.abs(got - 1.0 / x).max() < 2.0 ** -30
+
+
+def test_search_and_average_on_oracle_matches_float_evaluation():
+    """Search-and-average: the whole op list (range-sum circuit, masking, client
+    inversion, unmasking, product with the sum) on the oracle decrypts to the float64
+    evaluation of the same circuit's sum / count."""
+    q = client_query(12, 60)
+    p, s = q["p"], q["s"]
+    rlk, gk = _oracle_keys(q)
+    ops, outs, regs = pdq.plan_average_query(p.q, p.L, q["D"], 60, q["a"], q["b"], 37.25)
+    assert sum(op[0] == "client_inv" for op in ops) == 1
+    st = synthetic.streams(99)
+    res = OQ.Executor(p, rlk, gk, OQ.Client(p, s, st["ct_a"], st["ct_e"])).run(ops, dict(q["inputs"]))
+    avg = C.decode(C.decrypt(p, s, res[outs[0]]), regs[outs[0]][1], p.n)[0].real
+    ref = OQ.reference_average(q["vals"], q["lo"], q["hi"], q["a"], q["b"])
+    assert abs(avg - ref) < 5e-3
