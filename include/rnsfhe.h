@@ -101,6 +101,38 @@ typedef struct rf_ctx rf_ctx;
 int rf_ctx_create(const rf_params *params, int device, rf_ctx **out);
 void rf_ctx_destroy(rf_ctx *ctx);
 
+/* Kernel variants of one level (the segmentation / grouping choices of
+ * III-A.3 "Kernel Fusion and Segmentation", made per ring degree and limb count
+ * instead of fixed).  Every variant computes the same residues: a setting
+ * changes speed only, never results.
+ *   ntt_small_below  an (I)NTT launch of a two-pass degree (N >= 2^13) with fewer
+ *                    4096-residue tiles than this runs the small-tile passes
+ *                    (more workgroups, a shorter butterfly chain per thread);
+ *                    0 = never.  Default 256 (the CU count).
+ *   ntt_small_tile   residues per small tile: 1024 or 2048, or 0 = 2048 when the
+ *                    launch has at least half of ntt_small_below tiles, else 1024
+ *                    (default 0).
+ *   ntt_small_radix  residues per thread of the small tiles, i.e. butterfly
+ *                    stages per LDS round: 4 (radix-4, default) or 8 (radix-8).
+ *                    The 4096-residue tiles always hold 16 (radix-16 rounds).
+ *   modup_chunk      ModUp base-conversion output limbs per thread (the limb
+ *                    grouping of the conversion): 4, 8 (default) or 16.
+ * The settings of every level start at the defaults. */
+typedef struct rf_tuning {
+    uint32_t ntt_small_below;
+    uint32_t ntt_small_tile;
+    uint32_t ntt_small_radix;
+    uint32_t modup_chunk;
+} rf_tuning;
+
+/* Use `t` for operations at level `n_limbs` (1 <= n_limbs <= L; 0 = every
+ * level).  The standalone rf_ntt / rf_intt use the level min(n_limbs, L) of
+ * their window.  RF_EINVAL for a value outside the lists above.  Host state
+ * only: call it while no other thread issues operations on the context. */
+int rf_ctx_set_tuning(rf_ctx *ctx, uint32_t n_limbs, const rf_tuning *t);
+/* The setting of level n_limbs (1 <= n_limbs <= L) into *out. */
+int rf_ctx_get_tuning(const rf_ctx *ctx, uint32_t n_limbs, rf_tuning *out);
+
 /* Operation ids for rf_workspace_bytes. */
 enum rf_op {
     RF_OP_HMULT_RELIN = 1,
@@ -334,6 +366,11 @@ void rf_batch_destroy(rf_batch *plan);
  * range of work units; 0 = one workgroup per work unit.  Invalidates a
  * captured graph. */
 int rf_batch_set_grid(rf_batch *plan, uint32_t stage, uint32_t workgroups);
+/* Limb grouping of the batched ModUp conversion: output limbs per thread,
+ * 4, 8 (default) or 16 (modup_chunk of rf_tuning).  Waits for the device to
+ * be idle, rebuilds and uploads the job tables and invalidates a captured
+ * graph; RF_EINVAL for another value. */
+int rf_batch_set_modup_chunk(rf_batch *plan, uint32_t chunk);
 /* Work units of launch `stage` (or a negative RF_E* code). */
 int rf_batch_stage_units(const rf_batch *plan, uint32_t stage);
 /* Enqueue the batch on `stream`. */

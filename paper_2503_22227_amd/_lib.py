@@ -51,6 +51,15 @@ class rf_batch_item(ctypes.Structure):
     ]
 
 
+class rf_tuning(ctypes.Structure):
+    _fields_ = [
+        ("ntt_small_below", _u32),
+        ("ntt_small_tile", _u32),
+        ("ntt_small_radix", _u32),
+        ("modup_chunk", _u32),
+    ]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError("librnsfhe.so is not built (run __graft_entry__.build() or "
                       "python paper_2503_22227_amd/build.py): %s" % LIB_PATH)
@@ -61,6 +70,8 @@ _SIGS = {
     "rf_ctx_create": (ctypes.c_int, [ctypes.POINTER(rf_params), ctypes.c_int, ctypes.POINTER(_vp)]),
     "rf_ctx_destroy": (None, [_vp]),
     "rf_workspace_bytes": (_sz, [_vp, ctypes.c_int, _u32]),
+    "rf_ctx_set_tuning": (ctypes.c_int, [_vp, _u32, ctypes.POINTER(rf_tuning)]),
+    "rf_ctx_get_tuning": (ctypes.c_int, [_vp, _u32, ctypes.POINTER(rf_tuning)]),
     "rf_ntt": (ctypes.c_int, [_vp, _vp, _u32, _u32, _u32, _vp]),
     "rf_intt": (ctypes.c_int, [_vp, _vp, _u32, _u32, _u32, _vp]),
     "rf_hmult_relin": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _u32, _vp, _sz, _vp]),
@@ -88,6 +99,7 @@ _SIGS = {
     "rf_batch_create": (ctypes.c_int, [ctypes.POINTER(rf_batch_item), _u32, _vp, _sz, ctypes.POINTER(_vp)]),
     "rf_batch_destroy": (None, [_vp]),
     "rf_batch_set_grid": (ctypes.c_int, [_vp, _u32, _u32]),
+    "rf_batch_set_modup_chunk": (ctypes.c_int, [_vp, _u32]),
     "rf_batch_stage_units": (ctypes.c_int, [_vp, _u32]),
     "rf_batch_hmult_relin": (ctypes.c_int, [_vp, _vp]),
     "rf_batch_graph_launch": (ctypes.c_int, [_vp, _vp]),

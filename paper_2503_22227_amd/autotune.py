@@ -1,13 +1,29 @@
-"""Autotuner of the batched key-switching launches.
+"""Autotuner of the kernel variants (the segmentation and grouping choices of
+the paper's kernel-fusion section, III-A.3, searched per shape instead of fixed;
+the stream-pool size ablation of V-C is the paper's own analogue of such a
+search).
 
-Knob: the number of persistent workgroups of each launch of a batch plan
-(one per work unit, or a fixed count that walks the units in contiguous
-ranges), chosen per class of launch: NTT passes, base conversions, and the
-element-wise steps (tensor, inner product, tail).  The search is coordinate
-descent over the classes, each candidate timed with HIP events on whole-batch
-graph replays; the best setting is cached per batch shape (the multiset of
-ring degree and limb count) in a JSON file (RF_AUTOTUNE_CACHE, default
-~/.cache/rnsfhe_autotune.json).
+Single operations, per (ring degree, limb count) of a context
+(``tune_level``): the knobs of ``rf_tuning``
+
+  * ntt_small_below: below how many 4096-residue tiles an (I)NTT launch runs
+    small tiles (0: never);
+  * ntt_small_tile: 1024- or 2048-residue small tiles (0: by launch size);
+  * ntt_small_radix: residues per thread of the small tiles, i.e. radix-4 or
+    radix-8 LDS rounds (the 4096-residue tiles always run radix-16 rounds);
+  * modup_chunk: ModUp output limbs per thread (the conversion's limb grouping).
+
+Batches (``tune``): the workgroup count of each class of batched launch (one
+per work unit, or a fixed persistent count walking contiguous ranges) and the
+batched ModUp limb grouping.
+
+Both searches are coordinate descent from the defaults: each candidate value of
+one knob is timed with HIP events, and a change is kept only if it is faster
+than the best so far by more than ``min_gain`` (a relative margin, so timing
+noise does not move the setting).  Results are cached per device (name and CU
+count) and shape in a JSON file (RF_AUTOTUNE_CACHE, default
+~/.cache/rnsfhe_autotune.json).  Every variant computes the same residues, so
+tuning changes speed only.
 """
 from __future__ import annotations
 
@@ -17,16 +33,32 @@ import os
 
 import torch
 
+# ---------------------------------------------------------------- batches
 CLASSES = {
     "ntt": (1, 2, 4, 5, 7, 8, 10, 11),
     "bconv": (3, 9),
     "elementwise": (0, 6, 12),
 }
 CANDIDATES = (0, 256, 512, 1024, 2048, 4096)
+MODUP_CHUNKS = (4, 8, 16)
+
+# ---------------------------------------------------------------- single operations
+LEVEL_CANDIDATES = {
+    "ntt_small_below": (0, 64, 128, 256, 512, 1024, 4096),
+    "ntt_small_tile": (0, 1024, 2048),
+    "ntt_small_radix": (4, 8),
+    "modup_chunk": (4, 8, 16),
+}
+DEFAULT_LEVEL = {"ntt_small_below": 256, "ntt_small_tile": 0, "ntt_small_radix": 4, "modup_chunk": 8}
 
 
 def cache_path() -> str:
     return os.environ.get("RF_AUTOTUNE_CACHE", os.path.expanduser("~/.cache/rnsfhe_autotune.json"))
+
+
+def device_key(device=None) -> str:
+    p = torch.cuda.get_device_properties(device if device is not None else torch.cuda.current_device())
+    return "%s|%dcu" % (p.name, p.multi_processor_count)
 
 
 def shape_key(shape) -> str:
@@ -35,61 +67,151 @@ def shape_key(shape) -> str:
     return hashlib.sha1(s.encode()).hexdigest()[:16]
 
 
-def _time(plan, reps: int) -> float:
+def _load_cache(path: str) -> dict:
+    if os.path.exists(path):
+        try:
+            with open(path) as f:
+                return json.load(f)
+        except (OSError, ValueError):
+            pass
+    return {}
+
+
+def _store_cache(path: str, cache: dict) -> None:
+    try:
+        os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def time_fn(fn, reps: int, repeats: int = 3) -> float:
+    """Best of ``repeats`` mean times (ms) of ``reps`` back-to-back calls of fn on
+    the current stream, after one untimed call."""
     stream = torch.cuda.current_stream()
-    plan.run(graph=True)
+    fn()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        plan.run(graph=True)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / reps
+    best = float("inf")
+    for _ in range(repeats):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / reps)
+    return best
+
+
+def _descend(knobs: dict, apply, measure, min_gain: float, log=None, rounds: int = 2):
+    """Coordinate descent over ``knobs`` ({name: candidates}) starting from the
+    setting ``apply`` was last given; returns (setting, best_ms, trials)."""
+    setting = dict(apply.current)
+    apply(setting)
+    best = measure()
+    trials = [(dict(setting), best)]
+    for _ in range(rounds):
+        moved = False
+        for name, cands in knobs.items():
+            for cand in cands:
+                if cand == setting[name]:
+                    continue
+                trial = dict(setting)
+                trial[name] = cand
+                apply(trial)
+                ms = measure()
+                trials.append((trial, ms))
+                if log:
+                    log("autotune %s=%s: %.4f ms" % (name, cand, ms))
+                if ms < best * (1.0 - min_gain):
+                    best, setting, moved = ms, trial, True
+        if not moved:
+            break
+    apply(setting)
+    return setting, best, trials
+
+
+class _LevelApply:
+    def __init__(self, ctx, nlimbs):
+        self.ctx, self.nlimbs = ctx, nlimbs
+        self.current = ctx.get_tuning(nlimbs)
+
+    def __call__(self, setting):
+        self.ctx.set_tuning(self.nlimbs, setting)
+        self.current = dict(setting)
+
+
+def level_key(ctx, nlimbs: int, tag: str) -> str:
+    h = hashlib.sha1(",".join(str(x) for x in ctx.q + ctx.p).encode()).hexdigest()[:12]
+    return "level:%s:%d:%d:%d:%s:%s" % (ctx.scheme, ctx.log_n, nlimbs, ctx.alpha, h, tag)
+
+
+def tune_level(ctx, nlimbs: int, workload, reps: int = 10, min_gain: float = 0.01, use_cache: bool = True,
+               tag: str = "step", log=None) -> dict:
+    """Best rf_tuning of level ``nlimbs`` of ``ctx`` for ``workload`` (a callable
+    running the operations to optimise once, e.g. HMult+Relin, HRotate and rescale
+    at that level); applied to the context before returning.  Returns
+    {"setting", "default", "default_ms", "tuned_ms", "trials", "cached"}."""
+    path = cache_path()
+    key = level_key(ctx, nlimbs, tag)
+    dkey = device_key(ctx.device)
+    cache = _load_cache(path) if use_cache else {}
+    hit = cache.get(dkey, {}).get(key)
+    if hit:
+        ctx.set_tuning(nlimbs, hit["setting"])
+        return dict(hit, cached=True)
+    ap = _LevelApply(ctx, nlimbs)
+    ap(DEFAULT_LEVEL)
+    setting, best, trials = _descend(LEVEL_CANDIDATES, ap, lambda: time_fn(workload, reps), min_gain, log)
+    default_ms = trials[0][1]
+    res = {"setting": setting, "default": dict(DEFAULT_LEVEL), "default_ms": default_ms, "tuned_ms": best,
+           "trials": len(trials)}
+    if use_cache:
+        cache = _load_cache(path)
+        cache.setdefault(dkey, {})[key] = res
+        _store_cache(path, cache)
+    return dict(res, cached=False)
+
+
+class _BatchApply:
+    def __init__(self, plan):
+        self.plan = plan
+        self.current = {cls: 0 for cls in CLASSES}
+        self.current["modup_chunk"] = 8
+
+    def __call__(self, setting):
+        for cls, stages in CLASSES.items():
+            for st in stages:
+                self.plan.set_grid(st, int(setting.get(cls, 0)))
+        self.plan.set_modup_chunk(int(setting.get("modup_chunk", 8)))
+        self.current = dict(setting)
 
 
 def apply(plan, setting: dict) -> None:
-    for cls, stages in CLASSES.items():
-        for st in stages:
-            plan.set_grid(st, int(setting.get(cls, 0)))
+    _BatchApply(plan)(setting)
 
 
-def tune(plan, shape, reps: int = 3, use_cache: bool = True, log=None) -> dict:
-    """Best {class: workgroups} for the plan; applied to the plan before returning."""
-    key = shape_key(shape)
+def tune(plan, shape, reps: int = 3, use_cache: bool = True, min_gain: float = 0.01, log=None) -> dict:
+    """Best {class: workgroups, "modup_chunk": limbs} for a batch plan; applied to
+    the plan before returning."""
+    key = "batch:" + shape_key(shape)
     path = cache_path()
-    cache = {}
-    if use_cache and os.path.exists(path):
-        try:
-            cache = json.load(open(path))
-        except (OSError, ValueError):
-            cache = {}
-    if use_cache and key in cache:
-        apply(plan, cache[key]["setting"])
-        return cache[key]["setting"]
-    setting = {cls: 0 for cls in CLASSES}
-    apply(plan, setting)
-    best = _time(plan, reps)
-    trials = [(dict(setting), best)]
-    for cls in CLASSES:
-        for cand in CANDIDATES:
-            if cand == setting[cls]:
-                continue
-            trial = dict(setting)
-            trial[cls] = cand
-            apply(plan, trial)
-            ms = _time(plan, reps)
-            trials.append((trial, ms))
-            if log:
-                log("autotune %s=%d: %.3f ms" % (cls, cand, ms))
-            if ms < best:
-                best, setting = ms, trial
-    apply(plan, setting)
+    dkey = device_key()
+    cache = _load_cache(path) if use_cache else {}
+    hit = cache.get(dkey, {}).get(key)
+    if hit:
+        apply(plan, hit["setting"])
+        return hit["setting"]
+    knobs = {cls: CANDIDATES for cls in CLASSES}
+    knobs["modup_chunk"] = MODUP_CHUNKS
+    ap = _BatchApply(plan)
+    setting, best, trials = _descend(knobs, ap, lambda: time_fn(lambda: plan.run(graph=True), reps, repeats=2),
+                                     min_gain, log, rounds=1)
     if use_cache:
-        cache[key] = {"setting": setting, "ms": best, "trials": len(trials)}
-        try:
-            os.makedirs(os.path.dirname(path), exist_ok=True)
-            json.dump(cache, open(path, "w"), indent=1)
-        except OSError:
-            pass
+        cache = _load_cache(path)
+        cache.setdefault(dkey, {})[key] = {"setting": setting, "ms": best, "trials": len(trials)}
+        _store_cache(path, cache)
     return setting

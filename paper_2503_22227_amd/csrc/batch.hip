@@ -103,7 +103,8 @@ __device__ __forceinline__ uint32_t find_job(const J *jobs, uint32_t njobs, uint
     return lo;
 }
 
-template <int STAGE>
+// CH: ModUp conversion output limbs per thread (kModupConv only).
+template <int STAGE, int CH = kModupChunk>
 __global__ __launch_bounds__(kEw) void ks_batched_kernel(const KsJob *__restrict__ jobs, uint32_t njobs,
                                                          uint32_t total, uint32_t per_wg) {
     const uint32_t u0 = blockIdx.x * per_wg;
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(kEw) void ks_batched_kernel(const KsJob *__restrict
         if constexpr (STAGE == kTensor) {
             tensor_unit(J.a, J.b, J.out, J.d2, J.pcs, J.log_n, J.nl, nullptr, gx, gy);
         } else if constexpr (STAGE == kModupConv) {
-            modup_bconv_unit<true>(J.d_coeff, J.ext, J.pcs, J.modup_tab, J.modup_stride, J.log_n, J.nl, J.L, J.K, J.alpha,
+            modup_bconv_unit<true, CH>(J.d_coeff, J.ext, J.pcs, J.modup_tab, J.modup_stride, J.log_n, J.nl, J.L, J.K, J.alpha,
                              gx, gy);
         } else if constexpr (STAGE == kInnerProduct) {
             IpFold f;
@@ -259,6 +260,9 @@ struct rf_batch {
     NttJob *d_ntt[4] = {nullptr, nullptr, nullptr, nullptr};  // INTT d2, NTT ext, INTT P, NTT conv
     uint32_t total[kStages] = {0};
     uint32_t grid[kStages] = {0};  // workgroups per launch; 0 = one per unit
+    uint32_t modup_chunk = kModupChunk;  // ModUp output limbs per thread
+    std::vector<rf_batch_item> items;    // the item list, to rebuild the tables
+    uint64_t *ws = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t capture_stream = nullptr;
@@ -287,13 +291,13 @@ int validate(const rf_batch_item *items, uint32_t n) {
     return RF_OK;
 }
 
-uint32_t stage_units(const rf_ctx *c, uint32_t nl, int stage) {
+uint32_t stage_units(const rf_ctx *c, uint32_t nl, int stage, uint32_t chunk) {
     const uint32_t chunks = c->n / kEw, tiles = c->n / kTile;
     const uint32_t dn = (nl + c->alpha - 1) / c->alpha;
     switch (stage) {
         case kTensor: return 0;  // formed by the INTT of d2 and the inner product
         case kInttD0: case kInttD1: return nl * tiles;
-        case kModupConv: return dn * modup_chunks(nl, c->K) * chunks;
+        case kModupConv: return dn * modup_chunks(nl, c->K, chunk) * chunks;
         case kNttExt0: case kNttExt1: return c->modup_levels[nl].ext_limbs * tiles;
         case kInnerProduct: return (nl + c->K) * chunks;
         case kInttP0: case kInttP1: return 2 * c->K * tiles;
@@ -323,7 +327,14 @@ int enqueue(rf_batch *p, hipStream_t s, bool profile) {
             const uint32_t nj = p->n_items;
             switch (st) {
                 case kTensor: hipLaunchKernelGGL(ks_batched_kernel<kTensor>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
-                case kModupConv: hipLaunchKernelGGL(ks_batched_kernel<kModupConv>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
+                case kModupConv:
+                    if (p->modup_chunk == 4)
+                        hipLaunchKernelGGL((ks_batched_kernel<kModupConv, 4>), blocks, kEw, 0, s, p->d_jobs, nj, total, per);
+                    else if (p->modup_chunk == 16)
+                        hipLaunchKernelGGL((ks_batched_kernel<kModupConv, 16>), blocks, kEw, 0, s, p->d_jobs, nj, total, per);
+                    else
+                        hipLaunchKernelGGL((ks_batched_kernel<kModupConv, 8>), blocks, kEw, 0, s, p->d_jobs, nj, total, per);
+                    break;
                 case kInnerProduct: hipLaunchKernelGGL(ks_batched_kernel<kInnerProduct>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
                 case kModdownConv: hipLaunchKernelGGL(ks_batched_kernel<kModdownConv>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
                 case kTail: hipLaunchKernelGGL(ks_batched_kernel<kTail>, blocks, kEw, 0, s, p->d_jobs, nj, total, per); break;
@@ -390,29 +401,15 @@ void drop_graph(rf_batch *p) {
     p->graph = nullptr;
 }
 
-}  // namespace
-
-extern "C" size_t rf_batch_workspace_bytes(const rf_batch_item *items, uint32_t n) {
-    if (validate(items, n)) return 0;
-    size_t limbs = 0;
-    for (uint32_t i = 0; i < n; ++i) limbs += item_ws_limbs(items[i].ctx, items[i].n_limbs) * items[i].ctx->n;
-    return limbs * 8;
-}
-
-extern "C" int rf_batch_create(const rf_batch_item *items, uint32_t n, void *ws, size_t ws_bytes, rf_batch **out) {
-    int rc;
-    if (!out) return fail(RF_EINVAL, "rf_batch_create: null out");
-    *out = nullptr;
-    if ((rc = validate(items, n))) return rc;
-    const size_t need = rf_batch_workspace_bytes(items, n);
-    if (!ws || ws_bytes < need)
-        return fail(RF_EWORKSPACE, "rf_batch_create: workspace of " + std::to_string(ws_bytes) + " bytes, need " +
-                                       std::to_string(need));
-    std::vector<KsJob> jobs(n);
-    std::vector<NttJob> ntt[4];
-    for (auto &v : ntt) v.resize(n);
+// Job tables of a plan from its items, workspace and ModUp chunk: the
+// element-wise jobs, the four NTT job lists and the ring-degree groups.
+void build_tables(rf_batch *p, std::vector<KsJob> &jobs, std::vector<NttJob> (&ntt)[4]) {
+    const rf_batch_item *items = p->items.data();
+    const uint32_t n = (uint32_t)p->items.size();
+    jobs.assign(n, KsJob{});
+    for (auto &v : ntt) v.assign(n, NttJob{});
     uint32_t acc[kStages] = {0};
-    uint64_t *w = (uint64_t *)ws;
+    uint64_t *w = p->ws;
     // items in order of ring degree (the NTT steps run one launch per degree)
     std::vector<uint32_t> order(n);
     for (uint32_t i = 0; i < n; ++i) order[i] = i;
@@ -461,7 +458,7 @@ extern "C" int rf_batch_create(const rf_batch_item *items, uint32_t n, void *ws,
         J.alpha = c->alpha;
         for (int st = 0; st < kStages; ++st) {
             J.unit_begin[st] = acc[st];
-            acc[st] += stage_units(c, nl, st);
+            acc[st] += stage_units(c, nl, st, p->modup_chunk);
         }
         const uint64_t ipstride = (uint64_t)(nl + c->K) * N;
         NttBatch bd{J.d2, J.d_coeff, 0, 0, nl, 1, 0, nullptr};
@@ -493,23 +490,60 @@ extern "C" int rf_batch_create(const rf_batch_item *items, uint32_t n, void *ws,
     }
     groups.back().job1 = n;
     for (int st = 0; st < kStages; ++st) groups.back().units[st] = acc[st] - groups.back().unit0[st];
-    rf_batch *p = new rf_batch();
-    p->device = items[0].ctx->device;
-    p->n_items = n;
     p->groups = groups;
     for (int st = 0; st < kStages; ++st) p->total[st] = acc[st];
+}
+
+// Rebuild and upload the job tables (the device buffers exist already).
+int upload_tables(rf_batch *p) {
+    std::vector<KsJob> jobs;
+    std::vector<NttJob> ntt[4];
+    build_tables(p, jobs, ntt);
+    const uint32_t n = p->n_items;
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(p->device);
-    bool ok = hipMalloc((void **)&p->d_jobs, sizeof(KsJob) * n) == hipSuccess &&
+    // a launch of the plan still in flight reads the old tables
+    bool ok = hipDeviceSynchronize() == hipSuccess &&
               hipMemcpy(p->d_jobs, jobs.data(), sizeof(KsJob) * n, hipMemcpyHostToDevice) == hipSuccess;
     for (int k = 0; k < 4 && ok; ++k)
-        ok = hipMalloc((void **)&p->d_ntt[k], sizeof(NttJob) * n) == hipSuccess &&
-             hipMemcpy(p->d_ntt[k], ntt[k].data(), sizeof(NttJob) * n, hipMemcpyHostToDevice) == hipSuccess;
+        ok = hipMemcpy(p->d_ntt[k], ntt[k].data(), sizeof(NttJob) * n, hipMemcpyHostToDevice) == hipSuccess;
     (void)hipSetDevice(prev);
-    if (!ok) {
+    return ok ? RF_OK : fail(RF_EHIP, "batch plan: upload of the job tables");
+}
+
+}  // namespace
+
+extern "C" size_t rf_batch_workspace_bytes(const rf_batch_item *items, uint32_t n) {
+    if (validate(items, n)) return 0;
+    size_t limbs = 0;
+    for (uint32_t i = 0; i < n; ++i) limbs += item_ws_limbs(items[i].ctx, items[i].n_limbs) * items[i].ctx->n;
+    return limbs * 8;
+}
+
+extern "C" int rf_batch_create(const rf_batch_item *items, uint32_t n, void *ws, size_t ws_bytes, rf_batch **out) {
+    int rc;
+    if (!out) return fail(RF_EINVAL, "rf_batch_create: null out");
+    *out = nullptr;
+    if ((rc = validate(items, n))) return rc;
+    const size_t need = rf_batch_workspace_bytes(items, n);
+    if (!ws || ws_bytes < need)
+        return fail(RF_EWORKSPACE, "rf_batch_create: workspace of " + std::to_string(ws_bytes) + " bytes, need " +
+                                       std::to_string(need));
+    rf_batch *p = new rf_batch();
+    p->device = items[0].ctx->device;
+    p->n_items = n;
+    p->items.assign(items, items + n);
+    p->ws = (uint64_t *)ws;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(p->device);
+    bool ok = hipMalloc((void **)&p->d_jobs, sizeof(KsJob) * n) == hipSuccess;
+    for (int k = 0; k < 4 && ok; ++k) ok = hipMalloc((void **)&p->d_ntt[k], sizeof(NttJob) * n) == hipSuccess;
+    (void)hipSetDevice(prev);
+    if (!ok || upload_tables(p) != RF_OK) {
         rf_batch_destroy(p);
-        return fail(RF_EHIP, "rf_batch_create: upload of the job tables");
+        return fail(RF_EHIP, "rf_batch_create: allocation or upload of the job tables");
     }
     *out = p;
     return RF_OK;
@@ -535,6 +569,15 @@ extern "C" int rf_batch_set_grid(rf_batch *p, uint32_t stage, uint32_t workgroup
         drop_graph(p);
     }
     return RF_OK;
+}
+
+extern "C" int rf_batch_set_modup_chunk(rf_batch *p, uint32_t chunk) {
+    if (!p) return fail(RF_EINVAL, "rf_batch_set_modup_chunk: null plan");
+    if (chunk != 4 && chunk != 8 && chunk != 16) return fail(RF_EINVAL, "rf_batch_set_modup_chunk: 4, 8 or 16");
+    if (p->modup_chunk == chunk) return RF_OK;
+    p->modup_chunk = chunk;
+    drop_graph(p);
+    return upload_tables(p);
 }
 
 extern "C" int rf_batch_stage_units(const rf_batch *p, uint32_t stage) {

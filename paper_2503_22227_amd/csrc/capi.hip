@@ -86,12 +86,15 @@ int keyswitch_core(const rf_ctx *c, const uint64_t *d, const uint64_t *evk, uint
     // ModUp: INTT of d, base conversion of each digit, NTT of the new limbs.
     // Two-pass ring degrees: the INTT folds in the conversion's input factor
     // (pc_modup; launch_intt_first does the same for the fused callers).
+    const rf_tuning &tn = level_tuning(c, nl);
     const bool scaled = c->log_n > 12 && !d_coeff_in;
     if (!fused && !d_coeff_in &&
-        (rc = launch_ntt(c, batch(d, d_coeff, 0, 0, nl, 1, 0, nullptr), false, s, scaled ? pc_modup(c, nl) : nullptr)))
+        (rc = launch_ntt(c, batch(d, d_coeff, 0, 0, nl, 1, 0, nullptr), false, s, scaled ? pc_modup(c, nl) : nullptr,
+                         &tn)))
         return rc;
-    if ((rc = launch_modup_bconv(c, d_coeff_in ? d_coeff_in : d_coeff, ext, nl, s, scaled))) return rc;
-    if ((rc = launch_ntt(c, batch(ext, ext, 0, 0, lv.ext_limbs, 1, 0, c->d_pmaps + lv.pmap_off), true, s))) return rc;
+    if ((rc = launch_modup_bconv(c, d_coeff_in ? d_coeff_in : d_coeff, ext, nl, s, scaled, tn.modup_chunk))) return rc;
+    if ((rc = launch_ntt(c, batch(ext, ext, 0, 0, lv.ext_limbs, 1, 0, c->d_pmaps + lv.pmap_off), true, s, nullptr, &tn)))
+        return rc;
     // ModDown: INTT of the P-limbs, base conversion to Q_l, NTT, subtract and scale by P^-1
     const uint64_t ip_stride = (uint64_t)(nl + c->K) * N;
     const NttBatch pl = batch(ip + (size_t)nl * N, ip + (size_t)nl * N, ip_stride, ip_stride, c->K, 2, c->L, nullptr);
@@ -107,14 +110,15 @@ int keyswitch_core(const rf_ctx *c, const uint64_t *d, const uint64_t *evk, uint
             f.add1 = add1;
         }
         if ((rc = launch_inner_product(c, d, ext, evk, ip, nl, s, &f))) return rc;
-        if ((rc = launch_ntt(c, pl, false, s, c->d_pc_md))) return rc;
+        if ((rc = launch_ntt(c, pl, false, s, c->d_pc_md, &tn))) return rc;
         return launch_ntt_fwd_moddown(c, conv, ip, out, nl, s);
     }
     // inner product with the key over Q_l u P
     if ((rc = launch_inner_product(c, d, ext, evk, ip, nl, s))) return rc;
-    if ((rc = launch_ntt(c, pl, false, s))) return rc;
+    if ((rc = launch_ntt(c, pl, false, s, nullptr, &tn))) return rc;
     if ((rc = launch_moddown_bconv(c, ip, conv, nl, s))) return rc;
-    if ((rc = launch_ntt(c, batch(conv, conv, (uint64_t)nl * N, (uint64_t)nl * N, nl, 2, 0, nullptr), true, s)))
+    if ((rc = launch_ntt(c, batch(conv, conv, (uint64_t)nl * N, (uint64_t)nl * N, nl, 2, 0, nullptr), true, s, nullptr,
+                         &tn)))
         return rc;
     return launch_moddown_tail(c, ip, conv, add0, add1, out, nl, s);
 }
@@ -150,7 +154,8 @@ extern "C" int rf_ntt(const rf_ctx *c, uint64_t *data, uint32_t first, uint32_t 
     if (nl == 0 || np == 0 || first + nl > c->L + c->K) return fail(RF_ELEVEL, "rf_ntt: limb range");
     DeviceGuard g(c->device);
     const uint64_t stride = (uint64_t)nl * c->n;
-    return launch_ntt(c, batch(data, data, stride, stride, nl, np, first, nullptr), true, (hipStream_t)stream);
+    return launch_ntt(c, batch(data, data, stride, stride, nl, np, first, nullptr), true, (hipStream_t)stream, nullptr,
+                      &level_tuning(c, nl));
 }
 
 extern "C" int rf_intt(const rf_ctx *c, uint64_t *data, uint32_t first, uint32_t nl, uint32_t np, void *stream) {
@@ -158,7 +163,8 @@ extern "C" int rf_intt(const rf_ctx *c, uint64_t *data, uint32_t first, uint32_t
     if (nl == 0 || np == 0 || first + nl > c->L + c->K) return fail(RF_ELEVEL, "rf_intt: limb range");
     DeviceGuard g(c->device);
     const uint64_t stride = (uint64_t)nl * c->n;
-    return launch_ntt(c, batch(data, data, stride, stride, nl, np, first, nullptr), false, (hipStream_t)stream);
+    return launch_ntt(c, batch(data, data, stride, stride, nl, np, first, nullptr), false, (hipStream_t)stream, nullptr,
+                      &level_tuning(c, nl));
 }
 
 extern "C" int rf_tensor(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *d, uint32_t nl,
@@ -194,18 +200,19 @@ static int bfv_hmult_relin(const rf_ctx *c, const uint64_t *a, const uint64_t *b
     uint64_t *ks = d2 + L * N;                // [2][L][N]
     uint64_t *ks_ws = ks + 2 * L * N;
     const uint64_t wstride = (uint64_t)W * N;
+    const rf_tuning &tn = level_tuning(c, c->L);
     if ((rc = launch_behz_extend(c, a, b, ext, s))) return rc;
-    if ((rc = launch_ntt(c, batch(ext, ext, wstride, wstride, W, 4, 0, c->d_pmap_qb), true, s))) return rc;
+    if ((rc = launch_ntt(c, batch(ext, ext, wstride, wstride, W, 4, 0, c->d_pmap_qb), true, s, nullptr, &tn))) return rc;
     if ((rc = launch_tensor_map(c, ext, ext + 2 * wstride, tens, tens + 2 * wstride, W, c->d_pmap_qb, s))) return rc;
-    if ((rc = launch_ntt(c, batch(tens, tens, wstride, wstride, W, 3, 0, c->d_pmap_qb), false, s))) return rc;
+    if ((rc = launch_ntt(c, batch(tens, tens, wstride, wstride, W, 3, 0, c->d_pmap_qb), false, s, nullptr, &tn))) return rc;
     // the fast floor's B_sk residues go through the extension region, free after the tensor
     if ((rc = launch_behz_floor_sk(c, tens, ext, out, d2, s))) return rc;
     // the key switch takes d2 in both domains: the NTT (into the free tensor
     // region) for its inner product, the coefficients for its ModUp
     uint64_t *d2n = tens;
-    if ((rc = launch_ntt(c, batch(d2, d2n, 0, 0, c->L, 1, 0, nullptr), true, s))) return rc;
+    if ((rc = launch_ntt(c, batch(d2, d2n, 0, 0, c->L, 1, 0, nullptr), true, s, nullptr, &tn))) return rc;
     if ((rc = keyswitch_core(c, d2n, rlk, ks, c->L, nullptr, nullptr, ks_ws, s, nullptr, d2))) return rc;
-    if ((rc = launch_ntt(c, batch(ks, ks, L * N, L * N, c->L, 2, 0, nullptr), false, s))) return rc;
+    if ((rc = launch_ntt(c, batch(ks, ks, L * N, L * N, c->L, 2, 0, nullptr), false, s, nullptr, &tn))) return rc;
     return launch_ewise(c, 0, out, ks, 0, out, c->L, 2, s);
 }
 
@@ -282,9 +289,9 @@ extern "C" int rf_rotate(const rf_ctx *c, const uint64_t *in, uint32_t galois, c
     // the result back applies sigma_g (and the key switch) to the coefficients.
     const size_t poly = (size_t)nl * c->n;
     uint64_t *x = (uint64_t *)ws;
-    if ((rc = launch_ntt(c, batch(in, x, poly, poly, nl, 2, 0, nullptr), true, s))) return rc;
+    if ((rc = launch_ntt(c, batch(in, x, poly, poly, nl, 2, 0, nullptr), true, s, nullptr, &level_tuning(c, nl)))) return rc;
     if ((rc = rotate_ntt(c, x, galois, gk, out, nl, x + 2 * poly, s))) return rc;
-    return launch_ntt(c, batch(out, out, poly, poly, nl, 2, 0, nullptr), false, s);
+    return launch_ntt(c, batch(out, out, poly, poly, nl, 2, 0, nullptr), false, s, nullptr, &level_tuning(c, nl));
 }
 
 extern "C" int rf_galois_element(const rf_ctx *c, int64_t r, int conjugate, uint32_t *out) {
@@ -323,7 +330,9 @@ static int divide_last(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint3
     uint64_t *last = (uint64_t *)ws;         // [2][N]
     uint64_t *lift = last + 2 * N;           // [2][nl-1][N]
     const uint64_t in_stride = (uint64_t)nl * N;
-    if ((rc = launch_ntt(c, batch(in + (size_t)(nl - 1) * N, last, in_stride, N, 1, 2, nl - 1, nullptr), false, s)))
+    const rf_tuning &tn = level_tuning(c, nl);
+    if ((rc = launch_ntt(c, batch(in + (size_t)(nl - 1) * N, last, in_stride, N, 1, 2, nl - 1, nullptr), false, s,
+                         nullptr, &tn)))
         return rc;
     // out has a smaller polynomial stride than in: when they overlap, compute in
     // the workspace and copy the result over.
@@ -336,7 +345,7 @@ static int divide_last(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint3
     } else {
         if ((rc = launch_rescale_lift(c, last, lift, nl, keep_t, s))) return rc;
         if ((rc = launch_ntt(c, batch(lift, lift, (uint64_t)(nl - 1) * N, (uint64_t)(nl - 1) * N, nl - 1, 2, 0,
-                                      nullptr), true, s)))
+                                      nullptr), true, s, nullptr, &tn)))
             return rc;
         if (!overlap) return launch_rescale_tail(c, in, lift, out, nl, s);
         if ((rc = launch_rescale_tail(c, in, lift, lift, nl, s))) return rc;

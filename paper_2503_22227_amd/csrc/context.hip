@@ -390,6 +390,7 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
     // ModUp extension prime maps per level nl: for each digit, the basis Q_l u P minus the digit
     std::vector<uint8_t> pm;
     c->modup_levels.assign(c->L + 1, ModupLevel{0, 0, 0});
+    c->tuning.assign(c->L + 1, kDefaultTuning);
     for (uint32_t nl = 1; nl <= c->L; ++nl) {
         ModupLevel lv;
         lv.dnum = (nl + A - 1) / A;
@@ -578,6 +579,31 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
         return rc;
     }
     *out = c;
+    return RF_OK;
+}
+
+static bool tuning_valid(const rf_tuning &t) {
+    return (t.ntt_small_tile == 0 || t.ntt_small_tile == 1024 || t.ntt_small_tile == 2048) &&
+           (t.ntt_small_radix == 4 || t.ntt_small_radix == 8) &&
+           (t.modup_chunk == 4 || t.modup_chunk == 8 || t.modup_chunk == 16);
+}
+
+extern "C" int rf_ctx_set_tuning(rf_ctx *c, uint32_t nl, const rf_tuning *t) {
+    if (!c || !t) return rf::fail(RF_EINVAL, "rf_ctx_set_tuning: null argument");
+    if (nl > c->L) return rf::fail(RF_ELEVEL, "rf_ctx_set_tuning: level out of range");
+    if (!tuning_valid(*t)) return rf::fail(RF_EINVAL, "rf_ctx_set_tuning: unsupported variant");
+    if (nl == 0) {
+        for (uint32_t l = 1; l <= c->L; ++l) c->tuning[l] = *t;
+    } else {
+        c->tuning[nl] = *t;
+    }
+    return RF_OK;
+}
+
+extern "C" int rf_ctx_get_tuning(const rf_ctx *c, uint32_t nl, rf_tuning *out) {
+    if (!c || !out) return rf::fail(RF_EINVAL, "rf_ctx_get_tuning: null argument");
+    if (nl < 1 || nl > c->L) return rf::fail(RF_ELEVEL, "rf_ctx_get_tuning: level out of range");
+    *out = c->tuning[nl];
     return RF_OK;
 }
 

@@ -48,13 +48,13 @@ __global__ __launch_bounds__(kEw) void behz_sk_kernel(const uint64_t *f, uint64_
     behz_sk_unit(f, out01, out2, pcs, tab, o, kb, log_n, blockIdx.x, blockIdx.y);
 }
 
-template <bool SCALED>
+template <bool SCALED, int CH>
 __global__ __launch_bounds__(kEw) void modup_bconv_kernel(const uint64_t *__restrict__ x, uint64_t *__restrict__ ext,
                                                           const PrimeConst *__restrict__ pcs,
                                                           const uint64_t *__restrict__ tab, size_t tab_stride,
                                                           uint32_t log_n, uint32_t nl, uint32_t L, uint32_t K,
                                                           uint32_t alpha) {
-    modup_bconv_unit<SCALED>(x, ext, pcs, tab, tab_stride, log_n, nl, L, K, alpha, blockIdx.x, blockIdx.y);
+    modup_bconv_unit<SCALED, CH>(x, ext, pcs, tab, tab_stride, log_n, nl, L, K, alpha, blockIdx.x, blockIdx.y);
 }
 
 __global__ __launch_bounds__(kEw) void inner_product_kernel(const uint64_t *__restrict__ d,
@@ -153,16 +153,25 @@ int launch_behz_floor_sk(const rf_ctx *c, const uint64_t *tens, uint64_t *f, uin
     return check_launch("behz_floor_sk");
 }
 
-int launch_modup_bconv(const rf_ctx *c, const uint64_t *x, uint64_t *ext, uint32_t nl, hipStream_t s, bool scaled) {
+int launch_modup_bconv(const rf_ctx *c, const uint64_t *x, uint64_t *ext, uint32_t nl, hipStream_t s, bool scaled,
+                       uint32_t chunk) {
     const uint32_t dn = (nl + c->alpha - 1) / c->alpha;
+    if (chunk != 4 && chunk != 8 && chunk != 16) return fail(RF_EINVAL, "modup_bconv: chunk of 4, 8 or 16 limbs");
     ProfScope prof("modup_bconv", s);
-    const dim3 grid = ew_grid(c, dn * modup_chunks(nl, c->K));
-    if (scaled)
-        hipLaunchKernelGGL(modup_bconv_kernel<true>, grid, dim3(kEw), 0, s, x, ext, c->d_pc, c->d_modup,
-                           c->modup_stride, c->log_n, nl, c->L, c->K, c->alpha);
-    else
-        hipLaunchKernelGGL(modup_bconv_kernel<false>, grid, dim3(kEw), 0, s, x, ext, c->d_pc, c->d_modup,
-                           c->modup_stride, c->log_n, nl, c->L, c->K, c->alpha);
+    const dim3 grid = ew_grid(c, dn * modup_chunks(nl, c->K, chunk));
+#define RF_MU(SC, CH)                                                                                            \
+    hipLaunchKernelGGL((modup_bconv_kernel<SC, CH>), grid, dim3(kEw), 0, s, x, ext, c->d_pc, c->d_modup,          \
+                       c->modup_stride, c->log_n, nl, c->L, c->K, c->alpha)
+    if (scaled) {
+        if (chunk == 4) RF_MU(true, 4);
+        else if (chunk == 16) RF_MU(true, 16);
+        else RF_MU(true, 8);
+    } else {
+        if (chunk == 4) RF_MU(false, 4);
+        else if (chunk == 16) RF_MU(false, 16);
+        else RF_MU(false, 8);
+    }
+#undef RF_MU
     return check_launch("modup_bconv");
 }
 

@@ -36,16 +36,14 @@ __device__ __forceinline__ void tensor_unit(const uint64_t *__restrict__ a, cons
 // chunk, which is cheap next to the chunk's multiply-accumulates) and lets the
 // unrolled target loop prefetch its uniform constants.
 constexpr int kConvChunk = 8;
-// ModUp targets per workgroup row.  Measured at N = 2^16, 24 + 4 primes,
-// alpha = 8 (20 targets per digit): 8 targets 18.4 us, 10 targets 19.1 us,
-// 20 targets 24.8 us per launch (fewer, longer waves hide less latency).
-#ifndef RF_MODUP_CHUNK
-#define RF_MODUP_CHUNK 8
-#endif
-constexpr int kModupChunk = RF_MODUP_CHUNK;
+// ModUp targets per thread (the conversion's limb grouping; rf_tuning picks
+// 4, 8 or 16 per level).  Measured at N = 2^16, 24 + 4 primes, alpha = 8 (20
+// targets per digit): 8 targets 18.4 us, 10 targets 19.1 us, 20 targets 24.8 us
+// per launch (fewer, longer waves hide less latency).
+constexpr int kModupChunk = 8;
 
-__host__ __device__ inline uint32_t modup_chunks(uint32_t nl, uint32_t K) {
-    return (nl + K - 1 + kModupChunk - 1) / kModupChunk;
+__host__ __device__ inline uint32_t modup_chunks(uint32_t nl, uint32_t K, uint32_t chunk) {
+    return (nl + K - 1 + chunk - 1) / chunk;
 }
 __host__ __device__ inline uint32_t moddown_chunks(uint32_t nl) { return (nl + kConvChunk - 1) / kConvChunk; }
 
@@ -55,7 +53,7 @@ __host__ __device__ inline uint32_t moddown_chunks(uint32_t nl) { return (nl + k
 // with wide scalar loads ahead of use).  SCALED: x already holds
 // y_i = [x_i (Q_j/q_i)^-1]_{q_i} (an INTT with that factor folded into its last
 // stage), so the digit's input products are skipped.
-template <int S, bool SCALED>
+template <int S, bool SCALED, int CH>
 __device__ __forceinline__ void modup_conv_s(const uint64_t *__restrict__ x, uint64_t *__restrict__ dst,
                                              const PrimeConst *__restrict__ pcs, const uint64_t *__restrict__ blk,
                                              uint32_t alpha, uint32_t start, uint32_t ntarget, uint32_t t0,
@@ -70,7 +68,7 @@ __device__ __forceinline__ void modup_conv_s(const uint64_t *__restrict__ x, uin
     }
     const uint64_t *cross = blk + 2 * alpha;
 #pragma unroll
-    for (int k = 0; k < kModupChunk; ++k) {
+    for (int k = 0; k < CH; ++k) {
         const uint32_t tt = t0 + k;
         if (tt < ntarget) {
             const uint32_t g = tt < start ? tt : (tt < nl - S ? tt + S : L + (tt - (nl - S)));
@@ -87,33 +85,34 @@ __device__ __forceinline__ void modup_conv_s(const uint64_t *__restrict__ x, uin
 // ModUp base conversion at level nl: x = [nl][N] coefficient domain; ext =
 // digits back to back, digit j holding nl - s_j + K limbs ordered as the basis
 // Q_l u P without the digit's own primes, each residue in [0, 4q) (the forward
-// NTT that follows accepts that range).  gy = digit * modup_chunks + chunk.
-// SCALED: x holds the digits' input factors already (see modup_conv_s).
-template <bool SCALED>
+// NTT that follows accepts that range).  gy = digit * modup_chunks + chunk,
+// CH targets per chunk.  SCALED: x holds the digits' input factors already (see
+// modup_conv_s).
+template <bool SCALED, int CH>
 __device__ __forceinline__ void modup_bconv_unit(const uint64_t *__restrict__ x, uint64_t *__restrict__ ext,
                                                  const PrimeConst *__restrict__ pcs,
                                                  const uint64_t *__restrict__ tab, size_t tab_stride,
                                                  uint32_t log_n, uint32_t nl, uint32_t L, uint32_t K,
                                                  uint32_t alpha, uint32_t gx, uint32_t gy) {
-    const uint32_t nch = modup_chunks(nl, K);
+    const uint32_t nch = modup_chunks(nl, K, CH);
     const uint32_t j = gy / nch, ch = gy - j * nch;
     const uint32_t start = j * alpha;
     const uint32_t s = min(alpha, nl - start);
     const uint32_t ntarget = nl - s + K;
-    const uint32_t t0 = ch * kModupChunk;
+    const uint32_t t0 = ch * CH;
     if (t0 >= ntarget) return;
     const size_t n = (size_t)gx * kEw + threadIdx.x;
     const uint64_t *blk = tab + ((size_t)j * alpha + (s - 1)) * tab_stride;
     uint64_t *dst = ext + (((size_t)j * (nl + K - alpha)) << log_n) + n;
     switch (s) {
-        case 1: modup_conv_s<1, SCALED>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
-        case 2: modup_conv_s<2, SCALED>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
-        case 3: modup_conv_s<3, SCALED>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
-        case 4: modup_conv_s<4, SCALED>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
-        case 5: modup_conv_s<5, SCALED>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
-        case 6: modup_conv_s<6, SCALED>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
-        case 7: modup_conv_s<7, SCALED>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
-        default: modup_conv_s<8, SCALED>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 1: modup_conv_s<1, SCALED, CH>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 2: modup_conv_s<2, SCALED, CH>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 3: modup_conv_s<3, SCALED, CH>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 4: modup_conv_s<4, SCALED, CH>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 5: modup_conv_s<5, SCALED, CH>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 6: modup_conv_s<6, SCALED, CH>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        case 7: modup_conv_s<7, SCALED, CH>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
+        default: modup_conv_s<8, SCALED, CH>(x, dst, pcs, blk, alpha, start, ntarget, t0, nl, L, log_n, n); break;
     }
 }
 

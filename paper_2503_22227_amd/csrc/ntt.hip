@@ -209,49 +209,51 @@ __global__ __launch_bounds__(TILE / E) void ntt_small_kernel(NttBatch b, const T
     else ntt_rows_small<A, B, FWD, TILE, E>(lds, v.in, v.out, tw, pc, blockIdx.x);
 }
 
-// Residues per thread of the few-limb passes (4 measured faster than 8: the
-// 8-limb inverse passes at N = 2^16 took 10.3 / 10.9 us against 10.8 / 12.7 us).
+// Default residues per thread of the few-limb passes (4 measured faster than 8:
+// the 8-limb inverse passes at N = 2^16 took 10.3 / 10.9 us against 10.8 / 12.7
+// us); rf_tuning picks per level.
 constexpr int kSmallE = 4;
-// A launch is "small" when its kTile tiles number fewer than the CUs.
-constexpr uint32_t kSmallBelowTiles = 256;
 
-template <int A, int B, int TILE>
+template <int A, int B, int TILE, int E>
 static void launch_two_pass_small(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s,
                                   const PrimeConst *pcs) {
     const uint32_t limbs = b.per_poly * b.n_polys;
-    const dim3 grid((1u << (A + B)) / TILE, limbs), block(TILE / kSmallE);
+    const dim3 grid((1u << (A + B)) / TILE, limbs), block(TILE / E);
     NttBatch b2 = b;
     b2.in = b.out;
     b2.in_poly_stride = b.out_poly_stride;
     if (forward) {
         {
             ProfScope p("ntt_fwd_cols_small", s);
-            hipLaunchKernelGGL((ntt_small_kernel<A, B, true, true, TILE, kSmallE>), grid, block, 0, s, b, c->d_tw_fwd,
-                               pcs);
+            hipLaunchKernelGGL((ntt_small_kernel<A, B, true, true, TILE, E>), grid, block, 0, s, b, c->d_tw_fwd, pcs);
         }
         ProfScope p("ntt_fwd_rows_small", s);
-        hipLaunchKernelGGL((ntt_small_kernel<A, B, true, false, TILE, kSmallE>), grid, block, 0, s, b2, c->d_tw_fwd,
-                           pcs);
+        hipLaunchKernelGGL((ntt_small_kernel<A, B, true, false, TILE, E>), grid, block, 0, s, b2, c->d_tw_fwd, pcs);
     } else {
         {
             ProfScope p("ntt_inv_rows_small", s);
-            hipLaunchKernelGGL((ntt_small_kernel<A, B, false, false, TILE, kSmallE>), grid, block, 0, s, b,
-                               c->d_tw_inv, pcs);
+            hipLaunchKernelGGL((ntt_small_kernel<A, B, false, false, TILE, E>), grid, block, 0, s, b, c->d_tw_inv,
+                               pcs);
         }
         ProfScope p("ntt_inv_cols_small", s);
-        hipLaunchKernelGGL((ntt_small_kernel<A, B, false, true, TILE, kSmallE>), grid, block, 0, s, b2, c->d_tw_inv,
-                           pcs);
+        hipLaunchKernelGGL((ntt_small_kernel<A, B, false, true, TILE, E>), grid, block, 0, s, b2, c->d_tw_inv, pcs);
     }
 }
 
 template <int A, int B>
 static void launch_two_pass(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s,
-                            const PrimeConst *pcs) {
+                            const PrimeConst *pcs, const rf_tuning &tn) {
     const uint32_t limbs = b.per_poly * b.n_polys;
     const uint32_t tiles = limbs << (A + B - 12);
-    if (tiles < kSmallBelowTiles) {
-        if (tiles * 2 >= kSmallBelowTiles) launch_two_pass_small<A, B, 2048>(c, b, forward, s, pcs);
-        else launch_two_pass_small<A, B, 1024>(c, b, forward, s, pcs);
+    if (tiles < tn.ntt_small_below) {
+        const bool big = tn.ntt_small_tile == 2048 || (tn.ntt_small_tile == 0 && tiles * 2 >= tn.ntt_small_below);
+        if (tn.ntt_small_radix == 8) {
+            if (big) launch_two_pass_small<A, B, 2048, 8>(c, b, forward, s, pcs);
+            else launch_two_pass_small<A, B, 1024, 8>(c, b, forward, s, pcs);
+        } else {
+            if (big) launch_two_pass_small<A, B, 2048, kSmallE>(c, b, forward, s, pcs);
+            else launch_two_pass_small<A, B, 1024, kSmallE>(c, b, forward, s, pcs);
+        }
         return;
     }
     const dim3 block(kThreads);
@@ -382,9 +384,11 @@ int launch_intt_first(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uin
     return RF_OK;
 }
 
-int launch_ntt(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s, const PrimeConst *pcs) {
+int launch_ntt(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s, const PrimeConst *pcs,
+               const rf_tuning *tn) {
     const uint32_t limbs = b.per_poly * b.n_polys;
     if (!pcs) pcs = c->d_pc;
+    const rf_tuning &t = tn ? *tn : kDefaultTuning;
     if (limbs == 0) return RF_OK;
     if (limbs > 65535) return fail(RF_EUNSUPPORTED, "too many limbs in one NTT launch");
     switch (c->log_n) {
@@ -398,10 +402,10 @@ int launch_ntt(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s, 
                                    c->d_tw_inv, pcs);
             break;
         }
-        case 13: launch_two_pass<7, 6>(c, b, forward, s, pcs); break;
-        case 14: launch_two_pass<7, 7>(c, b, forward, s, pcs); break;
-        case 15: launch_two_pass<8, 7>(c, b, forward, s, pcs); break;
-        case 16: launch_two_pass<8, 8>(c, b, forward, s, pcs); break;
+        case 13: launch_two_pass<7, 6>(c, b, forward, s, pcs, t); break;
+        case 14: launch_two_pass<7, 7>(c, b, forward, s, pcs, t); break;
+        case 15: launch_two_pass<8, 7>(c, b, forward, s, pcs, t); break;
+        case 16: launch_two_pass<8, 8>(c, b, forward, s, pcs, t); break;
         default: return fail(RF_EUNSUPPORTED, "ring degree");
     }
     hipError_t e = hipGetLastError();

@@ -82,6 +82,7 @@ struct rf_ctx {
     std::vector<uint64_t> primes;  // L + K: q_0..q_{L-1}, p_0..p_{k-1}
     std::vector<uint64_t> psi;     // primitive 2N-th roots
     std::vector<rf::ModupLevel> modup_levels;  // index nl in [1, L]
+    std::vector<rf_tuning> tuning;             // kernel variants per level nl in [1, L] (index 0 unused)
 
     // device tables (owned)
     rf::PrimeConst *d_pc = nullptr;        // [L+K]
@@ -113,6 +114,12 @@ struct rf_ctx {
 };
 
 namespace rf {
+
+// Defaults of rf_tuning.
+constexpr rf_tuning kDefaultTuning = {256, 0, 4, 8};
+inline const rf_tuning &level_tuning(const rf_ctx *c, uint32_t nl) {
+    return c->tuning[nl < 1 ? 1 : (nl > c->L ? c->L : nl)];
+}
 
 // What the inner product adds on the Q-limbs when the ModDown tail that follows
 // is reduced to out = ip' - NTT(conv) P^-1 (the fused two-pass path):
@@ -178,7 +185,9 @@ int fail(int code, const std::string &msg);
 
 // kernel launchers (kernels.hip)
 // pcs: per-prime constants (null: the context's d_pc).
-int launch_ntt(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s, const PrimeConst *pcs = nullptr);
+// tn: the level's kernel variants (null: the defaults).
+int launch_ntt(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s, const PrimeConst *pcs = nullptr,
+               const rf_tuning *tn = nullptr);
 // ModDown after the inner product, two-pass ring degrees only: ip = [2][nl + K][N]
 // whose K P-limbs hold the INTT with d_pc_md (so already scaled by the input
 // factor).  The first forward pass computes the base conversion of each Q
@@ -205,8 +214,9 @@ int launch_tensor(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_
                   uint64_t *d2, uint32_t nl, hipStream_t s);
 // scaled: x is an INTT taken with pc_modup(c, nl), so each limb already carries
 // its digit's input factor [(Q_j/q_i)^-1]_{q_i}.
+// chunk: output limbs per thread (4, 8 or 16).
 int launch_modup_bconv(const rf_ctx *c, const uint64_t *x, uint64_t *ext, uint32_t nl, hipStream_t s,
-                       bool scaled = false);
+                       bool scaled = false, uint32_t chunk = 8);
 // fold (non-null): the Q-limbs leave as ip P^-1 + add_c with the sources fold
 // names (its pinv is filled in here), for launch_ntt_fwd_moddown.
 int launch_inner_product(const rf_ctx *c, const uint64_t *d_ntt, const uint64_t *ext,

@@ -105,6 +105,22 @@ class Context:
             self._ws[slot] = ws
         return ws
 
+    # ---------------------------------------------------------------- kernel variants
+    TUNING_FIELDS = ("ntt_small_below", "ntt_small_tile", "ntt_small_radix", "modup_chunk")
+
+    def set_tuning(self, nlimbs: int, setting: dict) -> None:
+        """Kernel variants of level ``nlimbs`` (0: every level); fields not given keep
+        their current value (rf_tuning in include/rnsfhe.h)."""
+        cur = self.get_tuning(max(1, min(nlimbs, self.L)))
+        cur.update(setting)
+        t = _lib.rf_tuning(*(int(cur[f]) for f in self.TUNING_FIELDS))
+        check(lib.rf_ctx_set_tuning(self._h, nlimbs, ctypes.byref(t)), "rf_ctx_set_tuning")
+
+    def get_tuning(self, nlimbs: int) -> dict:
+        t = _lib.rf_tuning()
+        check(lib.rf_ctx_get_tuning(self._h, nlimbs, ctypes.byref(t)), "rf_ctx_get_tuning")
+        return {f: int(getattr(t, f)) for f in self.TUNING_FIELDS}
+
     # ---------------------------------------------------------------- operations
     def ntt(self, data: torch.Tensor, first_limb: int, n_limbs: int, n_polys: int = 1) -> torch.Tensor:
         check(lib.rf_ntt(self._h, _ptr(data), first_limb, n_limbs, n_polys, _stream()), "rf_ntt")
@@ -313,6 +329,9 @@ class BatchPlan:
 
     def set_grid(self, stage: int, workgroups: int) -> None:
         check(lib.rf_batch_set_grid(self._h, stage, workgroups), "rf_batch_set_grid")
+
+    def set_modup_chunk(self, chunk: int) -> None:
+        check(lib.rf_batch_set_modup_chunk(self._h, chunk), "rf_batch_set_modup_chunk")
 
     def stage_units(self, stage: int) -> int:
         n = lib.rf_batch_stage_units(self._h, stage)
