@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--pdq-warmup", type=int, default=200, help="queries served before the measured points")
     ap.add_argument("--latency-reps", type=int, default=50, help="individually timed reps per op and cache state (0: skip)")
     ap.add_argument("--no-bfv-bgv", action="store_true", help="skip the BFV/BGV section")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default kernel variants (no autotuner search, no autotune section)")
     ap.add_argument("--ntt-microbench", action="store_true",
                     help="only time forward and inverse NTTs of 60 limbs at N=2^16 (kernel profiling)")
     ap.add_argument("--workload", default="ckks_n16_l24")
@@ -280,6 +282,13 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / 1e3
 
+    # kernel variants of this level picked by the autotuner (a fresh search; every
+    # variant gives the same residues)
+    from paper_2503_22227_amd import autotune
+    tuning = None
+    if not args.no_autotune:
+        tuning = autotune.tune_level(ctx, L, step, reps=10, use_cache=False)
+        _progress("autotune of the headline level done")
     for _ in range(args.warmup):
         step_concurrent()
     torch.cuda.synchronize()
@@ -373,9 +382,13 @@ def main():
     del m_out, r_out, ro_out
     shapes = other_shapes_section(max(args.steps, 20))
     _progress("alpha=4 and N=2^12 shapes done")
+    tuned_shapes = None
+    if not args.no_autotune:
+        tuned_shapes = autotune_section()
+        _progress("autotune section done")
     batch = None
     if not args.no_batch:
-        batch = batch_section(max(3, min(args.steps, 10)))
+        batch = batch_section(max(3, min(args.steps, 10)), tune=not args.no_autotune)
         _progress("batched section done")
 
     exact = None
@@ -410,7 +423,9 @@ def main():
                 "hmult_relin_us": round(t_hm / reps * 1e6, 2), "hrotate_us": round(t_ro / reps * 1e6, 2),
                 "rescale_us": round(t_rs / reps * 1e6, 2)},
         "latency": latency,
+        "tuning": tuning,
         "shapes": shapes,
+        "autotune": tuned_shapes,
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in sorted(kernels.items())},
         "roofline": roof,
         "batch": batch,
@@ -571,7 +586,70 @@ def other_shapes_section(reps: int):
     return out
 
 
-def batch_section(reps: int):
+def autotune_section(shapes=((16, 24), (16, 8), (15, 14), (15, 4), (14, 24), (14, 8)), rounds: int = 7,
+                     reps: int = 10):
+    """Kernel variants per (ring degree, limb count): the autotuner's search for the
+    level's step (HMult+Relin, rescale, HRotate at that level), then the default and
+    the tuned setting timed in alternation (``rounds`` times ``reps`` steps each;
+    medians), on the chain of the batched workload (24 Q-primes, 4 special primes,
+    alpha = 8) at N = 2^14..2^16."""
+    import statistics
+
+    import torch
+
+    import synthetic
+    from paper_2503_22227_amd import Context, autotune
+    from paper_2503_22227_amd.params import chain_for
+
+    w = synthetic.WORKLOADS["ckks_batch"]
+    ch = chain_for(w)
+    qp = ch["q"] + ch["p"]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(w["seed"] + 7)
+    out = []
+    ctxs = {}
+    for ln, nl in shapes:
+        if ln not in ctxs:
+            ctxs[ln] = Context(ch["q"], ch["p"], ln, w["alpha"], log_nmax=w["log_nmax"])
+        ctx = ctxs[ln]
+        n = 1 << ln
+        a = torch.stack([synthetic.device_uniform_residues(ch["q"][:nl], n, gen, "cuda") for _ in range(2)])
+        b = torch.stack([synthetic.device_uniform_residues(ch["q"][:nl], n, gen, "cuda") for _ in range(2)])
+        dn = (nl + w["alpha"] - 1) // w["alpha"]
+        rlk = torch.stack([torch.stack([synthetic.device_uniform_residues(qp, n, gen, "cuda") for _ in range(2)])
+                           for _ in range(ctx.dnum)])
+        g = ctx.galois_element(3)
+        mo, ro = torch.empty_like(a), torch.empty_like(a)
+        rs = ctx.empty(2, max(nl - 1, 1), n)
+
+        def step():
+            ctx.hmult_relin(a, b, rlk, out=mo)
+            if nl > 1:
+                ctx.rescale(mo, out=rs)
+            ctx.rotate(a, g, rlk, out=ro)
+
+        res = autotune.tune_level(ctx, nl, step, reps=reps, use_cache=False)
+        t_def, t_tun = [], []
+        for _ in range(rounds):
+            ctx.set_tuning(nl, res["default"])
+            t_def.append(autotune.time_fn(step, reps, repeats=1))
+            ctx.set_tuning(nl, res["setting"])
+            t_tun.append(autotune.time_fn(step, reps, repeats=1))
+        d_us, t_us = statistics.median(t_def) * 1e3, statistics.median(t_tun) * 1e3
+        out.append({"log_n": ln, "limbs": nl, "digits": dn, "step_default_us": round(d_us, 2),
+                    "step_tuned_us": round(t_us, 2), "gain": round(d_us / t_us - 1.0, 4),
+                    "setting": res["setting"], "search_trials": res["trials"],
+                    "differs_from_default": res["setting"] != res["default"]})
+        ctx.set_tuning(nl, res["default"])
+        del a, b, rlk, mo, ro, rs
+    for ctx in ctxs.values():
+        ctx.close()
+    return {"workload": "per (N, limbs): HMult+Relin, rescale and HRotate at that level on the 24 + 4 prime "
+                        "chain (alpha=8); default vs autotuned kernel variants, medians of %d alternating runs of "
+                        "%d steps" % (rounds, reps), "shapes": out}
+
+
+def batch_section(reps: int, tune: bool = True):
     """256 HMult+Relin items of mixed N in {2^14, 2^15, 2^16} and 4..24 limbs: one graph
     replay of the batched launches vs one HMult+Relin call per item on the same stream."""
     import torch
@@ -620,7 +698,7 @@ def batch_section(reps: int):
     t_plain = timed(plain)
     plan = BatchPlan(items)
     t_default = timed(lambda: plan.run(graph=True))
-    setting = autotune.tune(plan, shapes, reps=2, use_cache=False)
+    setting = autotune.tune(plan, shapes, reps=2, use_cache=False) if tune else None
     t_batch = timed(lambda: plan.run(graph=True))
     n_items = len(items)
     limb_bytes = sum(7 * nl * (8 << ln) for ln, nl in shapes)
@@ -628,7 +706,7 @@ def batch_section(reps: int):
            "items": n_items, "batched_items_per_s": round(n_items / t_batch, 1),
            "plain_items_per_s": round(n_items / t_plain, 1), "speedup": round(t_plain / t_batch, 3),
            "batched_ms": round(t_batch * 1e3, 3), "plain_ms": round(t_plain * 1e3, 3),
-           "batched_default_grid_ms": round(t_default * 1e3, 3), "autotuned_grid": setting,
+           "batched_default_ms": round(t_default * 1e3, 3), "autotuned": setting,
            "ciphertext_bytes_in_out": limb_bytes}
     plan.close()
     return out
