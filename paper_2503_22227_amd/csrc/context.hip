@@ -416,19 +416,19 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
         uint32_t at = 0;
         auto take = [&at](uint32_t n) { uint32_t r = at; at += n; return r; };
         o.ext_factor = take(2 * L);
-        o.cross_q_bsk = take(L * (nb + 1));
+        o.ext_cross = take((nb + 1) * L);
+        o.ext_q = take(2 * (nb + 1));
         o.cross_q_mt = take(L);
         o.neg_qinv_mt = take(1);
-        o.q_bsk = take(nb + 1);
-        o.mtinv_bsk = take(2 * (nb + 1));
         o.floor_factor = take(2 * L);
+        o.floor_cross = take((nb + 1) * L);
         o.t_bsk = take(2 * (nb + 1));
         o.qinv_bsk = take(2 * (nb + 1));
         o.sk_factor = take(2 * nb);
-        o.cross_b_q = take(nb * L);
+        o.sk_cross = take(L * nb);
         o.cross_b_msk = take(nb);
         o.minv_msk = take(2);
-        o.m_q = take(L);
+        o.m_q = take(2 * L);
         o.total = at;
         bz.assign(at, 0);
         const uint64_t mt_mask = 0xffffffffull;
@@ -461,17 +461,20 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
             uint64_t ff = mulmod_h(c->t % qi, qh_inv, qi);
             bz[o.floor_factor + 2 * i] = ff;
             bz[o.floor_factor + 2 * i + 1] = shoup_companion(ff, qi);
-            for (uint32_t m = 0; m <= nb; ++m) bz[o.cross_q_bsk + i * (nb + 1) + m] = qhat_mod(i, bsk(m));
+            for (uint32_t m = 0; m <= nb; ++m) {
+                const uint64_t bm = bsk(m), qh = qhat_mod(i, bm);
+                bz[o.floor_cross + m * L + i] = qh;
+                bz[o.ext_cross + m * L + i] = mulmod_h(qh, inv_h((1ull << 32) % bm, bm), bm);
+            }
             bz[o.cross_q_mt + i] = qhat_mt(i);
         }
         for (uint32_t m = 0; m <= nb; ++m) {
             uint64_t bm = bsk(m);
             uint64_t qm = 1;
             for (uint32_t h = 0; h < L; ++h) qm = mulmod_h(qm, c->primes[h] % bm, bm);
-            bz[o.q_bsk + m] = qm;
-            uint64_t mti = inv_h((1ull << 32) % bm, bm);
-            bz[o.mtinv_bsk + 2 * m] = mti;
-            bz[o.mtinv_bsk + 2 * m + 1] = shoup_companion(mti, bm);
+            const uint64_t qmt = mulmod_h(qm, inv_h((1ull << 32) % bm, bm), bm);
+            bz[o.ext_q + 2 * m] = qmt;
+            bz[o.ext_q + 2 * m + 1] = shoup_companion(qmt, bm);
             uint64_t tm = c->t % bm;
             bz[o.t_bsk + 2 * m] = tm;
             bz[o.t_bsk + 2 * m + 1] = shoup_companion(tm, bm);
@@ -491,7 +494,7 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
             uint64_t f = inv_h(mhat_mod(j, bj), bj);
             bz[o.sk_factor + 2 * j] = f;
             bz[o.sk_factor + 2 * j + 1] = shoup_companion(f, bj);
-            for (uint32_t i = 0; i < L; ++i) bz[o.cross_b_q + j * L + i] = mhat_mod(j, c->primes[i]);
+            for (uint32_t i = 0; i < L; ++i) bz[o.sk_cross + i * nb + j] = mhat_mod(j, c->primes[i]);
             bz[o.cross_b_msk + j] = mhat_mod(j, msk);
         }
         uint64_t mm = 1;
@@ -502,7 +505,8 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
         for (uint32_t i = 0; i < L; ++i) {
             uint64_t qi = c->primes[i], v = 1;
             for (uint32_t h = 0; h < nb; ++h) v = mulmod_h(v, bsk(h) % qi, qi);
-            bz[o.m_q + i] = v;
+            bz[o.m_q + 2 * i] = v;
+            bz[o.m_q + 2 * i + 1] = shoup_companion(v, qi);
         }
         for (uint32_t i = 0; i < L; ++i) pmqb.push_back((uint8_t)i);
         for (uint32_t m = 0; m <= nb; ++m) pmqb.push_back((uint8_t)(KB + m));

@@ -134,7 +134,8 @@ int launch_tensor_map(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uin
 
 int launch_behz_extend(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *ext, hipStream_t s) {
     ProfScope prof("behz_extend", s);
-    hipLaunchKernelGGL(behz_extend_kernel, ew_grid(c, 4), dim3(kEw), 0, s, a, b, ext, c->d_pc, c->d_behz, c->behz,
+    hipLaunchKernelGGL(behz_extend_kernel, ew_grid(c, 4 * behz_groups(c->nb + 1)), dim3(kEw), 0, s, a, b, ext, c->d_pc,
+                       c->d_behz, c->behz,
                        c->L + c->K, c->log_n);
     return check_launch("behz_extend");
 }

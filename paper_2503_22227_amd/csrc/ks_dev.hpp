@@ -361,57 +361,88 @@ __device__ __forceinline__ void ewise_unit(const uint64_t *a, const uint64_t *b,
 
 namespace rf {
 
-// BEHZ step 1 for one coefficient-domain polynomial (gy selects it among
-// a0, a1, b0, b1): fast conversion of [m~ x]_q to B_sk u {m~}, then the small
-// Montgomery reduction by m~ = 2^32.  ext = [poly][L + nb + 1][N]: the q part
-// is a copy of x, then b_0..b_{nb-1}, m_sk.  Prime indices: q_i = i,
-// bsk_m = kb + m.
+// Exact sum of (yh 2^30 + yl)[i] * coef(i) for i < n <= NMAX (pre-split
+// operands and coefficients below 2^60), in groups of 8 products (MacAcc).
+template <int NMAX, typename F>
+__device__ __forceinline__ u128 dot_split(const uint32_t *yl, const uint32_t *yh, F coef, int n) {
+    u128 total = {0, 0};
+#pragma unroll
+    for (int g = 0; g < (NMAX + 7) / 8; ++g) {
+        MacAcc acc;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int i = g * 8 + k;
+            if (i < NMAX && i < n) acc.mac_split(yl[i], yh[i], coef(i));
+        }
+        add_wide(total, acc.value());
+    }
+    return total;
+}
+
+// Conversions of the BEHZ multiplication, each split over groups of
+// kBehzGroup output limbs so that a launch has several threads per
+// coefficient (one thread per coefficient and every output limb left 1.5-2
+// waves per SIMD, each running thousands of dependent instructions); the
+// per-coefficient inputs of a group are recomputed by each group.
+constexpr int kBehzGroup = 4;
+
+__host__ __device__ inline uint32_t behz_groups(uint32_t limbs) { return (limbs + kBehzGroup - 1) / kBehzGroup; }
+
+// BEHZ step 1 for one coefficient-domain polynomial (a0, a1, b0, b1):
+// fast conversion of [m~ x]_q to B_sk, then the small Montgomery reduction
+// by m~ = 2^32: with y_i = [x_i m~ (Q/q_i)^-1]_{q_i} and r = -(sum_i y_i
+// [Q/q_i]_{m~}) Q^-1 mod m~ taken centred, out_m = (sum_i y_i [Q/q_i]_m + r Q)
+// m~^-1 mod bsk_m (the factor m~^-1 is folded into the tables).  gy =
+// poly * behz_groups(nb + 1) + group; the group's outputs are m = kBehzGroup
+// group + k.  ext = [poly][L + nb + 1][N]: the q part is a copy of x (written
+// by group 0), then b_0..b_{nb-1}, m_sk.  Prime indices: q_i = i, bsk_m =
+// kb + m.
 __device__ __forceinline__ void behz_extend_unit(const uint64_t *a, const uint64_t *b, uint64_t *ext,
                                                  const PrimeConst *__restrict__ pcs, const uint64_t *__restrict__ tab,
                                                  BehzLayout o, uint32_t kb, uint32_t log_n, uint32_t gx, uint32_t gy) {
     const uint32_t L = o.L, nb = o.nb, W = L + nb + 1;
+    const uint32_t ng = behz_groups(nb + 1);
+    const uint32_t poly = gy / ng, m0 = (gy - poly * ng) * kBehzGroup;
     const size_t n = (size_t)gx * kEw + threadIdx.x;
-    const size_t poly = (size_t)L << log_n;
-    const uint64_t *x = (gy < 2 ? a : b) + (gy & 1) * poly + n;
-    uint64_t *dst = ext + (((size_t)gy * W) << log_n) + n;
-    uint64_t y[kMaxBfvLimbs];
+    const size_t psz = (size_t)L << log_n;
+    const uint64_t *x = (poly < 2 ? a : b) + (poly & 1) * psz + n;
+    uint64_t *dst = ext + (((size_t)poly * W) << log_n) + n;
+    uint32_t yl[kMaxBfvLimbs], yh[kMaxBfvLimbs];
     uint32_t acc_mt = 0;
 #pragma unroll
     for (int i = 0; i < kMaxBfvLimbs; ++i) {
-        y[i] = 0;
+        yl[i] = yh[i] = 0;
         if (i < (int)L) {
             const uint64_t xi = x[(size_t)i << log_n];
-            dst[(size_t)i << log_n] = xi;
-            y[i] = shoup(xi, tab[o.ext_factor + 2 * i], tab[o.ext_factor + 2 * i + 1], pcs[i].q);
-            acc_mt += (uint32_t)y[i] * (uint32_t)tab[o.cross_q_mt + i];
+            if (m0 == 0) dst[(size_t)i << log_n] = xi;
+            const uint64_t y = shoup(xi, tab[o.ext_factor + 2 * i], tab[o.ext_factor + 2 * i + 1], pcs[i].q);
+            yl[i] = (uint32_t)y & 0x3fffffffu;
+            yh[i] = (uint32_t)(y >> 30);
+            acc_mt += (uint32_t)y * (uint32_t)tab[o.cross_q_mt + i];
         }
     }
     // r = -x~_{m~} Q^-1 mod 2^32, centred
     const uint32_t r32 = acc_mt * (uint32_t)tab[o.neg_qinv_mt];
     const bool neg = r32 >= 0x80000000u;
     const uint64_t rmag = neg ? (uint64_t)(0x100000000ull - r32) : (uint64_t)r32;
-    for (uint32_t m = 0; m <= nb; ++m) {
-        const PrimeConst pc = pcs[kb + m];
-        const u128 acc = dot_wide<kMaxBfvLimbs>(y, [&](int i) { return tab[o.cross_q_bsk + i * (nb + 1) + m]; }, L);
-        uint64_t v = barrett128(acc, pc.mu1, pc.mu0, pc.q);
-        const uint64_t qr = mulmod(tab[o.q_bsk + m], barrett64(rmag, pc.mu1, pc.mu0, pc.q), pc.mu1, pc.mu0, pc.q);
-        v = neg ? submod(v, qr, pc.q) : addmod(v, qr, pc.q);
-        dst[(size_t)(L + m) << log_n] = shoup(v, tab[o.mtinv_bsk + 2 * m], tab[o.mtinv_bsk + 2 * m + 1], pc.q);
+#pragma unroll
+    for (int k = 0; k < kBehzGroup; ++k) {
+        const uint32_t m = m0 + k;
+        if (m <= nb) {
+            const PrimeConst pc = pcs[kb + m];
+            const uint64_t *cm = tab + o.ext_cross + (size_t)m * L;
+            const u128 acc = dot_split<kMaxBfvLimbs>(yl, yh, [&](int i) { return cm[i]; }, L);
+            const uint64_t v = reduce128(acc, pc.q, pc.r64, pc.r64_p, pc.one_p);
+            const uint64_t rq = shoup(rmag, tab[o.ext_q + 2 * m], tab[o.ext_q + 2 * m + 1], pc.q);
+            dst[(size_t)(L + m) << log_n] = neg ? submod(v, rq, pc.q) : addmod(v, rq, pc.q);
+        }
     }
 }
 
-// BEHZ fast floor and Shenoy-Kumaresan conversion, split over groups of
-// kBehzGroup output limbs so that a launch has several threads per
-// coefficient (one thread per coefficient and every limb left 1.5 waves per
-// SIMD, each running thousands of dependent instructions); the per-coefficient
-// inputs shared by a group are recomputed by each.
-constexpr int kBehzGroup = 4;
-
-__host__ __device__ inline uint32_t behz_groups(uint32_t limbs) { return (limbs + kBehzGroup - 1) / kBehzGroup; }
-
 // Fast floor into B_sk of polynomial gy / behz_groups(nb + 1), outputs
 // m = kBehzGroup (gy % behz_groups(nb + 1)) + k: f_m = (t d_m - conv_m) Q^-1
-// mod bsk_m, into f [3][nb+1][N].
+// mod bsk_m with conv_m = sum_i [d_i t (Q/q_i)^-1]_{q_i} [Q/q_i]_m, into
+// f [3][nb+1][N].
 __device__ __forceinline__ void behz_floor_unit(const uint64_t *tens, uint64_t *f, const PrimeConst *__restrict__ pcs,
                                                 const uint64_t *__restrict__ tab, BehzLayout o, uint32_t kb,
                                                 uint32_t log_n, uint32_t gx, uint32_t gy) {
@@ -420,22 +451,25 @@ __device__ __forceinline__ void behz_floor_unit(const uint64_t *tens, uint64_t *
     const uint32_t poly = gy / ng, m0 = (gy - poly * ng) * kBehzGroup;
     const size_t n = (size_t)gx * kEw + threadIdx.x;
     const uint64_t *d = tens + (((size_t)poly * W) << log_n) + n;
-    uint64_t z[kMaxBfvLimbs];
+    uint32_t zl[kMaxBfvLimbs], zh[kMaxBfvLimbs];
 #pragma unroll
     for (int i = 0; i < kMaxBfvLimbs; ++i) {
-        z[i] = 0;
-        if (i < (int)L)
-            z[i] = shoup(d[(size_t)i << log_n], tab[o.floor_factor + 2 * i], tab[o.floor_factor + 2 * i + 1],
-                         pcs[i].q);
+        zl[i] = zh[i] = 0;
+        if (i < (int)L) {
+            const uint64_t z = shoup(d[(size_t)i << log_n], tab[o.floor_factor + 2 * i],
+                                     tab[o.floor_factor + 2 * i + 1], pcs[i].q);
+            zl[i] = (uint32_t)z & 0x3fffffffu;
+            zh[i] = (uint32_t)(z >> 30);
+        }
     }
 #pragma unroll
     for (int k = 0; k < kBehzGroup; ++k) {
         const uint32_t m = m0 + k;
         if (m <= nb) {
             const PrimeConst pc = pcs[kb + m];
-            const u128 acc =
-                dot_wide<kMaxBfvLimbs>(z, [&](int i) { return tab[o.cross_q_bsk + i * (nb + 1) + m]; }, L);
-            const uint64_t conv = barrett128(acc, pc.mu1, pc.mu0, pc.q);
+            const uint64_t *cm = tab + o.floor_cross + (size_t)m * L;
+            const u128 acc = dot_split<kMaxBfvLimbs>(zl, zh, [&](int i) { return cm[i]; }, L);
+            const uint64_t conv = reduce128(acc, pc.q, pc.r64, pc.r64_p, pc.one_p);
             const uint64_t td = shoup(d[(size_t)(L + m) << log_n], tab[o.t_bsk + 2 * m], tab[o.t_bsk + 2 * m + 1],
                                       pc.q);
             f[(((size_t)poly * (nb + 1) + m) << log_n) + n] =
@@ -456,17 +490,21 @@ __device__ __forceinline__ void behz_sk_unit(const uint64_t *f, uint64_t *out01,
     const uint32_t poly = gy / ng, i0 = (gy - poly * ng) * kBehzGroup;
     const size_t n = (size_t)gx * kEw + threadIdx.x;
     const uint64_t *fp = f + (((size_t)poly * (nb + 1)) << log_n) + n;
-    uint64_t w[kMaxBfvLimbs];
+    uint32_t wl[kMaxBfvLimbs], wh[kMaxBfvLimbs];
 #pragma unroll
     for (int j = 0; j < kMaxBfvLimbs; ++j) {
-        w[j] = 0;
-        if (j < (int)nb)
-            w[j] = shoup(fp[(size_t)j << log_n], tab[o.sk_factor + 2 * j], tab[o.sk_factor + 2 * j + 1], pcs[kb + j].q);
+        wl[j] = wh[j] = 0;
+        if (j < (int)nb) {
+            const uint64_t w = shoup(fp[(size_t)j << log_n], tab[o.sk_factor + 2 * j], tab[o.sk_factor + 2 * j + 1],
+                                     pcs[kb + j].q);
+            wl[j] = (uint32_t)w & 0x3fffffffu;
+            wh[j] = (uint32_t)(w >> 30);
+        }
     }
-    const u128 acc_msk = dot_wide<kMaxBfvLimbs>(w, [&](int j) { return tab[o.cross_b_msk + j]; }, nb);
+    const u128 acc_msk = dot_split<kMaxBfvLimbs>(wl, wh, [&](int j) { return tab[o.cross_b_msk + j]; }, nb);
     const PrimeConst pm = pcs[kb + nb];
     const uint64_t fmsk = fp[(size_t)nb << log_n];
-    const uint64_t cmsk = barrett128(acc_msk, pm.mu1, pm.mu0, pm.q);
+    const uint64_t cmsk = reduce128(acc_msk, pm.q, pm.r64, pm.r64_p, pm.one_p);
     const uint64_t alpha = shoup(submod(cmsk, fmsk, pm.q), tab[o.minv_msk], tab[o.minv_msk + 1], pm.q);
     const bool neg = alpha > (pm.q >> 1);
     const uint64_t amag = neg ? pm.q - alpha : alpha;
@@ -476,9 +514,11 @@ __device__ __forceinline__ void behz_sk_unit(const uint64_t *f, uint64_t *out01,
         const uint32_t i = i0 + k;
         if (i < L) {
             const PrimeConst pc = pcs[i];
-            const u128 acc = dot_wide<kMaxBfvLimbs>(w, [&](int j) { return tab[o.cross_b_q + j * L + i]; }, nb);
-            const uint64_t r = barrett128(acc, pc.mu1, pc.mu0, pc.q);
-            const uint64_t am = mulmod(barrett64(amag, pc.mu1, pc.mu0, pc.q), tab[o.m_q + i], pc.mu1, pc.mu0, pc.q);
+            const uint64_t *ci = tab + o.sk_cross + (size_t)i * nb;
+            const u128 acc = dot_split<kMaxBfvLimbs>(wl, wh, [&](int j) { return ci[j]; }, nb);
+            const uint64_t r = reduce128(acc, pc.q, pc.r64, pc.r64_p, pc.one_p);
+            // amag < m_sk < 2^64: one Shoup product by [M]_{q_i}
+            const uint64_t am = shoup(amag, tab[o.m_q + 2 * i], tab[o.m_q + 2 * i + 1], pc.q);
             out[(size_t)i << log_n] = neg ? addmod(r, am, pc.q) : submod(r, am, pc.q);
         }
     }

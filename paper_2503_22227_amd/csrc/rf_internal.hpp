@@ -44,23 +44,25 @@ struct NttBatch {
 };
 
 // Offsets (uint64 entries) of the BEHZ tables of a BFV context (L Q-primes,
-// nb auxiliary primes B, B_sk = B u {m_sk}, m~ = 2^32).
+// nb auxiliary primes B, B_sk = B u {m_sk}, m~ = 2^32).  The constants of one
+// output limb of a conversion are contiguous (target-major), so a thread reads
+// them with wide scalar loads.
 struct BehzLayout {
     uint32_t L, nb;
     uint32_t ext_factor;   // [L] pairs: m~ (Q/q_i)^-1 mod q_i
-    uint32_t cross_q_bsk;  // [L][nb+1]: Q/q_i mod bsk_m
+    uint32_t ext_cross;    // [nb+1][L]: (Q/q_i) m~^-1 mod bsk_m
+    uint32_t ext_q;        // [nb+1] pairs: Q m~^-1 mod bsk_m
     uint32_t cross_q_mt;   // [L]: Q/q_i mod 2^32
     uint32_t neg_qinv_mt;  // [1]: -Q^-1 mod 2^32
-    uint32_t q_bsk;        // [nb+1]: Q mod bsk_m
-    uint32_t mtinv_bsk;    // [nb+1] pairs: m~^-1 mod bsk_m
     uint32_t floor_factor; // [L] pairs: t (Q/q_i)^-1 mod q_i
+    uint32_t floor_cross;  // [nb+1][L]: Q/q_i mod bsk_m
     uint32_t t_bsk;        // [nb+1] pairs: t mod bsk_m
     uint32_t qinv_bsk;     // [nb+1] pairs: Q^-1 mod bsk_m
     uint32_t sk_factor;    // [nb] pairs: (M/b_j)^-1 mod b_j
-    uint32_t cross_b_q;    // [nb][L]: M/b_j mod q_i
+    uint32_t sk_cross;     // [L][nb]: M/b_j mod q_i
     uint32_t cross_b_msk;  // [nb]: M/b_j mod m_sk
     uint32_t minv_msk;     // [1] pair: M^-1 mod m_sk
-    uint32_t m_q;          // [L]: M mod q_i
+    uint32_t m_q;          // [L] pairs: M mod q_i
     uint32_t total;
 };
 
