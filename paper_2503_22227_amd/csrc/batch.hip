@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kEw) void ks_batched_kernel(const KsJob *__restrict
             f.mode = 1;
             f.a = J.a;
             f.b = J.b;
-            inner_product_unit(J.d2, J.ext, J.evk, J.ip, J.pcs, J.log_n, J.nl, J.L, J.K, J.alpha, gx, gy, f);
+            inner_product_unit<1>(J.d2, J.ext, J.evk, J.ip, J.pcs, J.log_n, J.nl, J.L, J.K, J.alpha, gx, gy, f);
         } else if constexpr (STAGE == kModdownConv) {
             moddown_bconv_unit(J.ip, J.conv, J.pcs, J.moddown_tab, J.log_n, J.nl, J.L, J.K, gx, gy);
         } else if constexpr (STAGE == kTail) {

@@ -57,6 +57,7 @@ __global__ __launch_bounds__(kEw) void modup_bconv_kernel(const uint64_t *__rest
     modup_bconv_unit<SCALED, CH>(x, ext, pcs, tab, tab_stride, log_n, nl, L, K, alpha, blockIdx.x, blockIdx.y);
 }
 
+template <int V>
 __global__ __launch_bounds__(kEw) void inner_product_kernel(const uint64_t *__restrict__ d,
                                                             const uint64_t *__restrict__ ext,
                                                             const uint64_t *__restrict__ evk,
@@ -64,7 +65,7 @@ __global__ __launch_bounds__(kEw) void inner_product_kernel(const uint64_t *__re
                                                             const PrimeConst *__restrict__ pcs, uint32_t log_n,
                                                             uint32_t nl, uint32_t L, uint32_t K, uint32_t alpha,
                                                             IpFold fold) {
-    inner_product_unit(d, ext, evk, ip, pcs, log_n, nl, L, K, alpha, blockIdx.x, blockIdx.y, fold);
+    inner_product_unit<V>(d, ext, evk, ip, pcs, log_n, nl, L, K, alpha, blockIdx.x, blockIdx.y, fold);
 }
 
 __global__ __launch_bounds__(kEw) void moddown_bconv_kernel(const uint64_t *__restrict__ ip, uint64_t *__restrict__ conv,
@@ -184,8 +185,8 @@ int launch_inner_product(const rf_ctx *c, const uint64_t *d, const uint64_t *ext
         f = *fold;
         f.pinv = c->d_moddown + moddown_pinv_off(c);
     }
-    hipLaunchKernelGGL(inner_product_kernel, ew_grid(c, nl + c->K), dim3(kEw), 0, s, d, ext, evk, ip, c->d_pc,
-                       c->log_n, nl, c->L, c->K, c->alpha, f);
+    hipLaunchKernelGGL(inner_product_kernel<kIpVec>, dim3(c->n / (kEw * kIpVec), nl + c->K), dim3(kEw), 0, s, d, ext,
+                       evk, ip, c->d_pc, c->log_n, nl, c->L, c->K, c->alpha, f);
     return check_launch("inner_product");
 }
 

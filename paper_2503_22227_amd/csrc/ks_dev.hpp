@@ -116,85 +116,161 @@ __device__ __forceinline__ void modup_bconv_unit(const uint64_t *__restrict__ x,
     }
 }
 
+// V consecutive residues of one limb, read or written with one access of
+// 8 V bytes (V = 2: 16-byte accesses, which the HBM streams faster than 8-byte
+// ones).
+template <int V>
+__device__ __forceinline__ void load_v(const uint64_t *p, uint64_t (&r)[V]) {
+    if constexpr (V == 2) {
+        typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+        const u64x2 t = *reinterpret_cast<const u64x2 *>(p);
+        r[0] = t.x;
+        r[1] = t.y;
+    } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) r[v] = p[v];
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void store_v(uint64_t *p, const uint64_t (&r)[V]) {
+    if constexpr (V == 2) {
+        typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+        u64x2 t;
+        t.x = r[0];
+        t.y = r[1];
+        *reinterpret_cast<u64x2 *>(p) = t;
+    } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) p[v] = r[v];
+    }
+}
+
+// Coefficients per thread of the inner product.  Two (16-byte accesses) was
+// measured slower at N = 2^16, 24 + 4 limbs, alpha = 8: 36.0 against 34.8 us
+// per launch (half the threads keep fewer loads in flight).
+constexpr int kIpVec = 1;
+
 // Inner product with the key on every limb m of Q_l u P (grid.y = m):
 // ip[c][m] = sum_j src_j(m) * evk[j][c][g(m)], src_j(m) = d[m] if m is in digit j,
-// else the ModUp output of digit j.
+// else the ModUp output of digit j.  A thread takes V consecutive coefficients
+// (gx = block of kEw V coefficients).
+template <int V>
 __device__ __forceinline__ void inner_product_unit(const uint64_t *__restrict__ d,
-                                                            const uint64_t *__restrict__ ext,
-                                                            const uint64_t *__restrict__ evk,
-                                                            uint64_t *__restrict__ ip,
-                                                            const PrimeConst *__restrict__ pcs, uint32_t log_n,
-                                                            uint32_t nl, uint32_t L, uint32_t K, uint32_t alpha, uint32_t gx, uint32_t gy,
-                                                            const IpFold &fold = IpFold()) {
+                                                   const uint64_t *__restrict__ ext,
+                                                   const uint64_t *__restrict__ evk,
+                                                   uint64_t *__restrict__ ip,
+                                                   const PrimeConst *__restrict__ pcs, uint32_t log_n,
+                                                   uint32_t nl, uint32_t L, uint32_t K, uint32_t alpha, uint32_t gx,
+                                                   uint32_t gy, const IpFold &fold = IpFold()) {
     const uint32_t m = gy;
-    const size_t n = (size_t)gx * kEw + threadIdx.x;
+    const size_t n = ((size_t)gx * kEw + threadIdx.x) * V;
     const uint32_t g = m < nl ? m : L + (m - nl);
     const PrimeConst pc = pcs[g];
     const uint32_t dn = (nl + alpha - 1) / alpha;
     const size_t key_poly = (size_t)(L + K) << log_n;
     // HMult / HRotate sources of the Q-limbs (the P-limbs belong to no digit)
-    uint64_t own = 0, ad0 = 0, ad1 = 0;
+    uint64_t own[V], ad0[V], ad1[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) own[v] = ad0[v] = ad1[v] = 0;
     if (fold.mode != 0 && m < nl) {
         const size_t lo = (size_t)m << log_n, poly = (size_t)nl << log_n;
         if (fold.mode == 1) {
-            const uint64_t x0 = fold.a[lo + n], x1 = fold.a[poly + lo + n];
-            const uint64_t y0 = fold.b[lo + n], y1 = fold.b[poly + lo + n];
-            MacAcc s2, s0, s1;
-            s2.mac(x1, y1);
-            s0.mac(x0, y0);
-            s1.mac(x0, y1);
-            s1.mac(x1, y0);
-            own = reduce128(s2.value(), pc.q, pc.r64, pc.r64_p, pc.one_p);
-            ad0 = reduce128(s0.value(), pc.q, pc.r64, pc.r64_p, pc.one_p);
-            ad1 = reduce128(s1.value(), pc.q, pc.r64, pc.r64_p, pc.one_p);
+            uint64_t x0[V], x1[V], y0[V], y1[V];
+            load_v<V>(fold.a + lo + n, x0);
+            load_v<V>(fold.a + poly + lo + n, x1);
+            load_v<V>(fold.b + lo + n, y0);
+            load_v<V>(fold.b + poly + lo + n, y1);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                MacAcc s2, s0, s1;
+                s2.mac(x1[v], y1[v]);
+                s0.mac(x0[v], y0[v]);
+                s1.mac(x0[v], y1[v]);
+                s1.mac(x1[v], y0[v]);
+                own[v] = reduce128(s2.value(), pc.q, pc.r64, pc.r64_p, pc.one_p);
+                ad0[v] = reduce128(s0.value(), pc.q, pc.r64, pc.r64_p, pc.one_p);
+                ad1[v] = reduce128(s1.value(), pc.q, pc.r64, pc.r64_p, pc.one_p);
+            }
         } else {
-            const size_t src = lo + galois_src((uint32_t)n, fold.galois, log_n);
-            own = fold.a[poly + src];
-            ad0 = fold.a[src];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const size_t src = lo + galois_src((uint32_t)(n + v), fold.galois, log_n);
+                own[v] = fold.a[poly + src];
+                ad0[v] = fold.a[src];
+            }
         }
     }
-    u128 acc0 = {0, 0}, acc1 = {0, 0};
+    u128 acc0[V], acc1[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc0[v] = acc1[v] = u128{0, 0};
 #pragma unroll 4
     for (uint32_t j = 0; j < dn; ++j) {
         const uint32_t start = j * alpha;
         const uint32_t s = min(alpha, nl - start);
-        uint64_t src;
+        uint64_t src[V];
         if (m >= start && m < start + s) {
-            src = fold.mode != 0 ? own : d[((size_t)m << log_n) + n];
+            if (fold.mode != 0) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) src[v] = own[v];
+            } else {
+                load_v<V>(d + ((size_t)m << log_n) + n, src);
+            }
         } else {
             const uint32_t tt = m < start ? m : m - s;
-            src = ext[(((size_t)j * (nl + K - alpha) + tt) << log_n) + n];
+            load_v<V>(ext + (((size_t)j * (nl + K - alpha) + tt) << log_n) + n, src);
         }
         const uint64_t *kj = evk + (size_t)(2 * j) * key_poly + ((size_t)g << log_n) + n;
-        mac(acc0, src, kj[0]);
-        mac(acc1, src, kj[key_poly]);
+        uint64_t k0[V], k1[V];
+        load_v<V>(kj, k0);
+        load_v<V>(kj + key_poly, k1);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            mac(acc0[v], src[v], k0[v]);
+            mac(acc1[v], src[v], k1[v]);
+        }
     }
     const size_t out_poly = (size_t)(nl + K) << log_n;
-    // [0, 4q): the Shoup product by P^-1 takes any 64-bit input, the other
-    // outputs are made canonical below
-    uint64_t r0 = reduce128_lazy(acc0, pc.q, pc.r64, pc.r64_p, pc.one_p);
-    uint64_t r1 = reduce128_lazy(acc1, pc.q, pc.r64, pc.r64_p, pc.one_p);
+    uint64_t r0[V], r1[V];
     const uint64_t q2 = 2 * pc.q;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        // [0, 4q): the Shoup product by P^-1 takes any 64-bit input, the other
+        // outputs are made canonical below
+        r0[v] = reduce128_lazy(acc0[v], pc.q, pc.r64, pc.r64_p, pc.one_p);
+        r1[v] = reduce128_lazy(acc1[v], pc.q, pc.r64, pc.r64_p, pc.one_p);
+    }
     if (fold.pinv && m < nl) {
         const uint64_t pinv = fold.pinv[2 * m], pinv_p = fold.pinv[2 * m + 1];
-        r0 = shoup(r0, pinv, pinv_p, pc.q);
-        r1 = shoup(r1, pinv, pinv_p, pc.q);
         const size_t lo = (size_t)m << log_n;
-        if (fold.mode == 1) {
-            r0 = addmod(r0, ad0, pc.q);
-            r1 = addmod(r1, ad1, pc.q);
-        } else if (fold.mode == 2) {
-            r0 = addmod(r0, ad0, pc.q);
-        } else {
-            if (fold.add0) r0 = addmod(r0, fold.add0[lo + n], pc.q);
-            if (fold.add1) r1 = addmod(r1, fold.add1[lo + n], pc.q);
+        uint64_t a0[V], a1[V];
+        if (fold.mode == 0) {
+            if (fold.add0) load_v<V>(fold.add0 + lo + n, a0);
+            if (fold.add1) load_v<V>(fold.add1 + lo + n, a1);
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            r0[v] = shoup(r0[v], pinv, pinv_p, pc.q);
+            r1[v] = shoup(r1[v], pinv, pinv_p, pc.q);
+            if (fold.mode == 1) {
+                r0[v] = addmod(r0[v], ad0[v], pc.q);
+                r1[v] = addmod(r1[v], ad1[v], pc.q);
+            } else if (fold.mode == 2) {
+                r0[v] = addmod(r0[v], ad0[v], pc.q);
+            } else {
+                if (fold.add0) r0[v] = addmod(r0[v], a0[v], pc.q);
+                if (fold.add1) r1[v] = addmod(r1[v], a1[v], pc.q);
+            }
         }
     } else {
-        r0 = csub(csub(r0, q2), pc.q);
-        r1 = csub(csub(r1, q2), pc.q);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            r0[v] = csub(csub(r0[v], q2), pc.q);
+            r1[v] = csub(csub(r1[v], q2), pc.q);
+        }
     }
-    ip[((size_t)m << log_n) + n] = r0;
-    ip[out_poly + ((size_t)m << log_n) + n] = r1;
+    store_v<V>(ip + ((size_t)m << log_n) + n, r0);
+    store_v<V>(ip + out_poly + ((size_t)m << log_n) + n, r1);
 }
 
 // ModDown conversion of one chunk of Q targets from KP special primes
