@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--pdq-warmup", type=int, default=200, help="queries served before the measured points")
     ap.add_argument("--latency-reps", type=int, default=50, help="individually timed reps per op and cache state (0: skip)")
     ap.add_argument("--no-bfv-bgv", action="store_true", help="skip the BFV/BGV section")
+    ap.add_argument("--no-shapes", action="store_true",
+                    help="skip the alpha=4 and N=2^12 shapes (profiling runs of the headline workload alone)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default kernel variants (no autotuner search, no autotune section)")
     ap.add_argument("--ntt-microbench", action="store_true",
@@ -380,8 +382,10 @@ def main():
 
     _progress("timed steps and kernel roofline done")
     del m_out, r_out, ro_out
-    shapes = other_shapes_section(max(args.steps, 20))
-    _progress("alpha=4 and N=2^12 shapes done")
+    shapes = None
+    if not args.no_shapes:
+        shapes = other_shapes_section(max(args.steps, 20))
+        _progress("alpha=4 and N=2^12 shapes done")
     tuned_shapes = None
     if not args.no_autotune:
         tuned_shapes = autotune_section()
@@ -496,7 +500,8 @@ def _kernel_symbol(name: str) -> str:
              "ntt_fwd_cols_moddown": "ntt_cols_moddown_kernel<8, 8, 4>",
              "ntt_fwd_cols_lift": "ntt_cols_lift_kernel<8, 8, false>",
              "ntt_inv_rows_tensor": "ntt_inv_rows_tensor_kernel<8, 8>",
-             "ntt_inv_rows_gather": "ntt_inv_rows_gather_kernel<8, 8>"}
+             "ntt_inv_rows_gather": "ntt_inv_rows_gather_kernel<8, 8>",
+             "modup_bconv": "modup_bconv_kernel<true, 8>", "inner_product": "inner_product_kernel<1>"}
     return table.get(name, name + "_kernel")
 
 

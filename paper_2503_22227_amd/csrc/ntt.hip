@@ -197,6 +197,21 @@ __global__ __launch_bounds__(kThreads) void ntt_single_kernel(NttBatch b, const 
 
 // A pass of a launch with few limbs (ntt_cols_small / ntt_rows_small): one
 // workgroup per TILE residues of a limb, E residues per thread.
+// Tile of a small column pass.  Its U = TILE / 2^A columns are narrower than
+// a 128-byte line (G = 16 / U tiles share each line of a row), and workgroups
+// are dealt to the 8 XCDs in turn, each with its own L2: dispatch order
+// w = blockIdx.x is mapped so that the G tiles of one line group go to the
+// same XCD one after another (w, w + 8, ...), and the line is read from HBM
+// once instead of G times.  Identity when the grid is not a multiple of 8 G.
+template <int TILE, int A>
+__device__ __forceinline__ int xcd_grouped_tile() {
+    constexpr int U = TILE >> A, G = U >= 16 ? 1 : 16 / U;
+    const int w = blockIdx.x;
+    if (G == 1 || gridDim.x % (8 * G) != 0) return w;
+    const int x = w & 7, r = w >> 3;
+    return ((r / G) * 8 + x) * G + r % G;
+}
+
 template <int A, int B, bool FWD, bool COLS, int TILE, int E>
 __global__ __launch_bounds__(TILE / E) void ntt_small_kernel(NttBatch b, const TwPair *__restrict__ tw_all,
                                                              const PrimeConst *__restrict__ pcs) {
@@ -205,7 +220,7 @@ __global__ __launch_bounds__(TILE / E) void ntt_small_kernel(NttBatch b, const T
     const LimbView v = limb_view(b, A + B, blockIdx.y);
     const PrimeConst pc = pcs[v.g];
     const TwPair *tw = tw_all + ((size_t)v.g << (A + B));
-    if constexpr (COLS) ntt_cols_small<A, B, FWD, TILE, E>(lds, v.in, v.out, tw, pc, blockIdx.x);
+    if constexpr (COLS) ntt_cols_small<A, B, FWD, TILE, E>(lds, v.in, v.out, tw, pc, xcd_grouped_tile<TILE, A>());
     else ntt_rows_small<A, B, FWD, TILE, E>(lds, v.in, v.out, tw, pc, blockIdx.x);
 }
 
