@@ -170,3 +170,35 @@ def test_batch_modup_chunks_bit_identical():
             for i, it in enumerate(items):
                 assert np.array_equal(host(it[4]), want[i]), (chunk, grid, graph, shapes[i])
     plan.close()
+
+
+@pytest.mark.parametrize("scheme", ["bfv", "bgv"])
+def test_variants_exact_schemes_match_default(scheme):
+    """BFV (whose NTTs of q u B_sk and of the 14-digit ModUp run through the tuned
+    launches) and BGV at N = 2^15, 14 limbs: HMult+Relin and HRotate under every
+    variant equal the default."""
+    from paper_2503_22227_amd import Context
+    w = synthetic.WORKLOADS["%s_n15" % scheme]
+    p = P.make_params(w)
+    kw = dict(scheme=scheme, t=p.t)
+    if scheme == "bfv":
+        kw.update(b=p.b, m_sk=p.msk)
+    ctx = Context(p.q, p.p, p.log_n, p.alpha, log_nmax=p.log_nmax, **kw)
+    nl = p.L
+    rng = np.random.default_rng(1515)
+    a, b = dev(rand_ct(p, nl, rng)), dev(rand_ct(p, nl, rng))
+    rlk, gk = dev(rand_key(p, rng)), dev(rand_key(p, rng))
+    g = C.galois_element(3, p.n)
+
+    def run():
+        return host(ctx.hmult_relin(a, b, rlk)), host(ctx.rotate(a, g, gk))
+
+    want = run()
+    for v in VARIANTS:
+        print("%s variant %s" % (scheme, v), flush=True)
+        ctx.set_tuning(nl, v)
+        got = run()
+        for w_, g_ in zip(want, got):
+            assert np.array_equal(w_, g_), v
+        ctx.set_tuning(nl, DEFAULT)
+    ctx.close()
