@@ -60,6 +60,12 @@ class rf_tuning(ctypes.Structure):
     ]
 
 
+# torch ships its own HIP runtime; it has to be in the process before the
+# library is loaded, so that the library binds to that runtime.  Loaded the
+# other way round, the library pulls in the system's runtime first, torch's
+# HIP libraries bind to it, and torch then finds no GPU.
+import torch  # noqa: E402,F401
+
 if not os.path.exists(LIB_PATH):
     raise ImportError("librnsfhe.so is not built (run __graft_entry__.build() or "
                       "python paper_2503_22227_amd/build.py): %s" % LIB_PATH)
