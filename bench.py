@@ -656,7 +656,9 @@ def autotune_section(shapes=((16, 24), (16, 8), (15, 14), (15, 4), (14, 24), (14
 
 def batch_section(reps: int, tune: bool = True):
     """256 HMult+Relin items of mixed N in {2^14, 2^15, 2^16} and 4..24 limbs: one graph
-    replay of the batched launches vs one HMult+Relin call per item on the same stream."""
+    replay of the batched launches vs one HMult+Relin call per item on the same stream,
+    issued back to back (``plain``) and with a synchronisation after every call
+    (``plain_synced``, one operation per launch chain)."""
     import torch
 
     import synthetic
@@ -700,7 +702,13 @@ def batch_section(reps: int, tune: bool = True):
         for ctx, a, b, k, out in items:
             ctx.hmult_relin(a, b, k, out=out)
 
+    def plain_synced():
+        for ctx, a, b, k, out in items:
+            ctx.hmult_relin(a, b, k, out=out)
+            torch.cuda.synchronize()
+
     t_plain = timed(plain)
+    t_plain_synced = timed(plain_synced)
     plan = BatchPlan(items)
     t_default = timed(lambda: plan.run(graph=True))
     setting = autotune.tune(plan, shapes, reps=2, use_cache=False) if tune else None
@@ -710,6 +718,8 @@ def batch_section(reps: int, tune: bool = True):
     out = {"workload": "256 CKKS HMult+Relin items, N in {2^14,2^15,2^16}, 4..24 limbs, k=4, alpha=8",
            "items": n_items, "batched_items_per_s": round(n_items / t_batch, 1),
            "plain_items_per_s": round(n_items / t_plain, 1), "speedup": round(t_plain / t_batch, 3),
+           "plain_synced_items_per_s": round(n_items / t_plain_synced, 1),
+           "speedup_vs_synced": round(t_plain_synced / t_batch, 3),
            "batched_ms": round(t_batch * 1e3, 3), "plain_ms": round(t_plain * 1e3, 3),
            "batched_default_ms": round(t_default * 1e3, 3), "autotuned": setting,
            "ciphertext_bytes_in_out": limb_bytes}
