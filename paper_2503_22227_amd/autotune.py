@@ -17,6 +17,12 @@ Batches (``tune``): the workgroup count of each class of batched launch (one
 per work unit, or a fixed persistent count walking contiguous ranges) and the
 batched ModUp limb grouping.
 
+Settings found on a device can be shipped with the package
+(``tuned_variants.json``, written by ``python -m paper_2503_22227_amd.autotune
+--write-table``): a context created on a device of the same name and CU count
+applies the entry of its ring degree, alpha and special-prime count at every
+level it lists (``apply_shipped``; RF_NO_SHIPPED_TUNING=1 keeps the defaults).
+
 Both searches are coordinate descent from the defaults: each candidate value of
 one knob is timed with HIP events, and a change is kept only if it is faster
 than the best so far by more than ``min_gain`` (a relative margin, so timing
@@ -215,3 +221,104 @@ def tune(plan, shape, reps: int = 3, use_cache: bool = True, min_gain: float = 0
         cache.setdefault(dkey, {})[key] = {"setting": setting, "ms": best, "trials": len(trials)}
         _store_cache(path, cache)
     return setting
+
+
+# ---------------------------------------------------------------- shipped table
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_variants.json")
+
+
+def shipped_key(log_n: int, alpha: int, k: int, nlimbs: int) -> str:
+    return "ckks:%d:%d:%d:%d" % (log_n, alpha, k, nlimbs)
+
+
+def apply_shipped(ctx, path: str = SHIPPED) -> int:
+    """Apply the shipped settings of ``ctx``'s device and shape to its levels;
+    returns the number of levels set (0 when the table has no entry)."""
+    if os.environ.get("RF_NO_SHIPPED_TUNING") == "1" or ctx.scheme != "ckks" or not os.path.exists(path):
+        return 0
+    try:
+        with open(path) as f:
+            table = json.load(f).get(device_key(ctx.device), {})
+    except (OSError, ValueError):
+        return 0
+    n = 0
+    for nl in range(1, ctx.L + 1):
+        setting = table.get(shipped_key(ctx.log_n, ctx.alpha, ctx.k, nl))
+        if setting:
+            ctx.set_tuning(nl, setting)
+            n += 1
+    return n
+
+
+def write_table(out: str, log_ns=(14, 15, 16), levels=(4, 8, 12, 16, 20, 24), reps: int = 10) -> dict:
+    """Tune HMult+Relin, rescale and HRotate at each (ring degree, level) of the
+    batched workload's chain (24 + 4 primes, alpha = 8) and of the serving
+    workload's (alpha = 4, N = 2^16), keep the settings that differ from the
+    defaults, and write them for this device into ``out``; every level between two
+    tuned ones takes the lower one's setting."""
+    import synthetic
+    from .fhe import Context
+    from .params import chain_for
+
+    dkey = device_key()
+    table = {}
+    saved = os.environ.get("RF_NO_SHIPPED_TUNING")
+    os.environ["RF_NO_SHIPPED_TUNING"] = "1"  # search from the defaults
+    for wname, lns in (("ckks_batch", log_ns), ("pdq", (16,))):
+        w = synthetic.WORKLOADS[wname]
+        ch = chain_for(w)
+        qp = ch["q"] + ch["p"]
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(w["seed"] + 11)
+        for ln in lns:
+            ctx = Context(ch["q"], ch["p"], ln, w["alpha"], log_nmax=w["log_nmax"])
+            n = 1 << ln
+            key = torch.stack([torch.stack([_residues(qp, n, gen) for _ in range(2)]) for _ in range(ctx.dnum)])
+            prev = None
+            for nl in range(1, ctx.L + 1):
+                if nl in levels:
+                    a = torch.stack([_residues(ch["q"][:nl], n, gen) for _ in range(2)])
+                    b = torch.stack([_residues(ch["q"][:nl], n, gen) for _ in range(2)])
+                    g = ctx.galois_element(3)
+
+                    def step():
+                        m = ctx.hmult_relin(a, b, key)
+                        if nl > 1:
+                            ctx.rescale(m)
+                        ctx.rotate(a, g, key)
+
+                    res = tune_level(ctx, nl, step, reps=reps, use_cache=False)
+                    prev = res["setting"] if res["setting"] != res["default"] else None
+                    print("tuned %s N=2^%d limbs=%d: %s (%.4f -> %.4f ms)" % (
+                        wname, ln, nl, res["setting"], res["default_ms"], res["tuned_ms"]), flush=True)
+                if prev is not None:
+                    table[shipped_key(ln, w["alpha"], len(ch["p"]), nl)] = prev
+            ctx.close()
+    if saved is None:
+        del os.environ["RF_NO_SHIPPED_TUNING"]
+    else:
+        os.environ["RF_NO_SHIPPED_TUNING"] = saved
+    doc = {}
+    if os.path.exists(out):
+        try:
+            with open(out) as f:
+                doc = json.load(f)
+        except (OSError, ValueError):
+            doc = {}
+    doc[dkey] = table
+    with open(out, "w") as f:
+        json.dump(doc, f, indent=1, sort_keys=True)
+    return table
+
+
+def _residues(moduli, n, gen):
+    import synthetic
+    return synthetic.device_uniform_residues(moduli, n, gen, "cuda")
+
+
+if __name__ == "__main__":
+    import sys
+    if len(sys.argv) >= 2 and sys.argv[1] == "--write-table":
+        print(json.dumps(write_table(sys.argv[2] if len(sys.argv) > 2 else SHIPPED), indent=1))
+    else:
+        raise SystemExit("usage: python -m paper_2503_22227_amd.autotune --write-table [path]")

@@ -72,6 +72,9 @@ class Context:
         check(lib.rf_ctx_create(ctypes.byref(prm), device, ctypes.byref(h)), "rf_ctx_create")
         self._h = h
         self._ws = {}
+        # kernel variants tuned on this device for this shape, when shipped
+        from . import autotune
+        self.shipped_levels = autotune.apply_shipped(self)
 
     def close(self) -> None:
         if getattr(self, "_h", None):

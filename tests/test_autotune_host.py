@@ -86,3 +86,20 @@ def test_level_candidates_are_the_library_values():
     assert set(A.MODUP_CHUNKS) == {4, 8, 16}
     for k, v in A.DEFAULT_LEVEL.items():
         assert v in A.LEVEL_CANDIDATES[k]
+
+
+def test_shipped_table_applies_matching_entries(tmp_path, monkeypatch):
+    monkeypatch.setattr(A, "device_key", lambda device=None: "fake-gpu|256cu")
+    monkeypatch.delenv("RF_NO_SHIPPED_TUNING", raising=False)
+    table = {"fake-gpu|256cu": {A.shipped_key(15, 8, 1, 2): dict(A.DEFAULT_LEVEL, modup_chunk=4)},
+             "other|304cu": {A.shipped_key(15, 8, 1, 1): dict(A.DEFAULT_LEVEL, modup_chunk=16)}}
+    path = tmp_path / "t.json"
+    path.write_text(json.dumps(table))
+    ctx = FakeCtx()
+    ctx.L, ctx.k = 2, 1
+    assert A.apply_shipped(ctx, str(path)) == 1
+    assert ctx.levels == {2: dict(A.DEFAULT_LEVEL, modup_chunk=4)}
+    monkeypatch.setenv("RF_NO_SHIPPED_TUNING", "1")
+    ctx2 = FakeCtx()
+    ctx2.L, ctx2.k = 2, 1
+    assert A.apply_shipped(ctx2, str(path)) == 0 and ctx2.levels == {}

@@ -70,6 +70,7 @@ def test_variant_ops_match_oracle(log_n, vi):
     nl = 5
     v = VARIANTS[vi]
     print("variant %s log_n=%d nl=%d" % (v, log_n, nl), flush=True)
+    ctx.set_tuning(0, DEFAULT)
     ctx.set_tuning(nl, v)
     try:
         assert ctx.get_tuning(nl) == dict(DEFAULT, **v)
@@ -105,6 +106,7 @@ def test_variants_full_shape_match_default():
     p = P.make_params(synthetic.WORKLOADS["ckks_n16_l24"])
     ctx = Context(p.q, p.p, p.log_n, p.alpha, log_nmax=p.log_nmax)
     nl = p.L
+    ctx.set_tuning(0, DEFAULT)
     rng = np.random.default_rng(2416)
     a, b = dev(rand_ct(p, nl, rng)), dev(rand_ct(p, nl, rng))
     rlk, gk = dev(rand_key(p, rng)), dev(rand_key(p, rng))
@@ -129,6 +131,7 @@ def test_tuning_rejects_unsupported_values():
     from paper_2503_22227_amd import Context
     from paper_2503_22227_amd._lib import RFError
     p, ctx = small_context(14)
+    ctx.set_tuning(0, DEFAULT)
     for bad in (dict(ntt_small_tile=4096), dict(ntt_small_radix=16), dict(modup_chunk=5)):
         with pytest.raises(RFError):
             ctx.set_tuning(3, bad)
