@@ -117,12 +117,18 @@ void rf_ctx_destroy(rf_ctx *ctx);
  *                    The 4096-residue tiles always hold 16 (radix-16 rounds).
  *   modup_chunk      ModUp base-conversion output limbs per thread (the limb
  *                    grouping of the conversion): 4, 8 (default) or 16.
+ *   ntt_fused_small_below  the same threshold for the (I)NTT launches that carry a
+ *                    fused step (the tensor or automorphism before the first INTT
+ *                    pass, the ModDown conversion and tail, the rescale lift and
+ *                    tail); their small tiles take ntt_small_tile and 4 residues per
+ *                    thread.  Default 0 (always 4096-residue tiles).
  * The settings of every level start at the defaults. */
 typedef struct rf_tuning {
     uint32_t ntt_small_below;
     uint32_t ntt_small_tile;
     uint32_t ntt_small_radix;
     uint32_t modup_chunk;
+    uint32_t ntt_fused_small_below;
 } rf_tuning;
 
 /* Use `t` for operations at level `n_limbs` (1 <= n_limbs <= L; 0 = every

@@ -57,6 +57,7 @@ class rf_tuning(ctypes.Structure):
         ("ntt_small_tile", _u32),
         ("ntt_small_radix", _u32),
         ("modup_chunk", _u32),
+        ("ntt_fused_small_below", _u32),
     ]
 
 

@@ -11,7 +11,10 @@ Single operations, per (ring degree, limb count) of a context
   * ntt_small_tile: 1024- or 2048-residue small tiles (0: by launch size);
   * ntt_small_radix: residues per thread of the small tiles, i.e. radix-4 or
     radix-8 LDS rounds (the 4096-residue tiles always run radix-16 rounds);
-  * modup_chunk: ModUp output limbs per thread (the conversion's limb grouping).
+  * modup_chunk: ModUp output limbs per thread (the conversion's limb grouping);
+  * ntt_fused_small_below: the small-tile threshold of the launches that carry
+    a fused step (tensor, automorphism, ModDown conversion and tail, rescale
+    lift and tail).
 
 Batches (``tune``): the workgroup count of each class of batched launch (one
 per work unit, or a fixed persistent count walking contiguous ranges) and the
@@ -54,8 +57,10 @@ LEVEL_CANDIDATES = {
     "ntt_small_tile": (0, 1024, 2048),
     "ntt_small_radix": (4, 8),
     "modup_chunk": (4, 8, 16),
+    "ntt_fused_small_below": (0, 128, 256, 512, 1024),
 }
-DEFAULT_LEVEL = {"ntt_small_below": 256, "ntt_small_tile": 0, "ntt_small_radix": 4, "modup_chunk": 8}
+DEFAULT_LEVEL = {"ntt_small_below": 256, "ntt_small_tile": 0, "ntt_small_radix": 4, "modup_chunk": 8,
+                 "ntt_fused_small_below": 0}
 
 
 def cache_path() -> str:

@@ -111,7 +111,7 @@ int keyswitch_core(const rf_ctx *c, const uint64_t *d, const uint64_t *evk, uint
         }
         if ((rc = launch_inner_product(c, d, ext, evk, ip, nl, s, &f))) return rc;
         if ((rc = launch_ntt(c, pl, false, s, c->d_pc_md, &tn))) return rc;
-        return launch_ntt_fwd_moddown(c, conv, ip, out, nl, s);
+        return launch_ntt_fwd_moddown(c, conv, ip, out, nl, s, &tn);
     }
     // inner product with the key over Q_l u P
     if ((rc = launch_inner_product(c, d, ext, evk, ip, nl, s))) return rc;
@@ -237,7 +237,8 @@ extern "C" int rf_hmult_relin(const rf_ctx *c, const uint64_t *a, const uint64_t
     if (c->log_n > 12) {
         // d2 = a1 b1 is formed by the first pass of its INTT and, with d0 and d1,
         // by the inner product
-        if ((rc = launch_intt_first(c, a, b, ks_ws + ks_layout(c, nl).d_coeff, 0, nl, s))) return rc;
+        if ((rc = launch_intt_first(c, a, b, ks_ws + ks_layout(c, nl).d_coeff, 0, nl, s, &level_tuning(c, nl))))
+            return rc;
         IpFold f;
         f.mode = 1;
         f.a = a;
@@ -259,7 +260,9 @@ static int rotate_ntt(const rf_ctx *c, const uint64_t *in, uint32_t galois, cons
     if (c->log_n > 12) {
         // sigma_g(a1) is gathered by the first pass of its INTT and, with sigma_g(a0),
         // by the inner product
-        if ((rc = launch_intt_first(c, in, nullptr, ks_ws + ks_layout(c, nl).d_coeff, galois, nl, s))) return rc;
+        if ((rc = launch_intt_first(c, in, nullptr, ks_ws + ks_layout(c, nl).d_coeff, galois, nl, s,
+                                    &level_tuning(c, nl))))
+            return rc;
         IpFold f;
         f.mode = 2;
         f.a = in;
@@ -340,8 +343,8 @@ static int divide_last(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint3
                          (const void *)in < (const void *)(out + 2 * (size_t)(nl - 1) * N);
     if (c->log_n > 12) {
         // the lift runs in the first pass of the NTT and the tail in its last pass
-        if (!overlap) return launch_ntt_fwd_rescale(c, last, lift, in, out, nl, keep_t, s);
-        if ((rc = launch_ntt_fwd_rescale(c, last, lift, in, lift, nl, keep_t, s))) return rc;
+        if (!overlap) return launch_ntt_fwd_rescale(c, last, lift, in, out, nl, keep_t, s, &tn);
+        if ((rc = launch_ntt_fwd_rescale(c, last, lift, in, lift, nl, keep_t, s, &tn))) return rc;
     } else {
         if ((rc = launch_rescale_lift(c, last, lift, nl, keep_t, s))) return rc;
         if ((rc = launch_ntt(c, batch(lift, lift, (uint64_t)(nl - 1) * N, (uint64_t)(nl - 1) * N, nl - 1, 2, 0,

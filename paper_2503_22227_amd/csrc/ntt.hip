@@ -46,17 +46,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
     ntt_rows_unit<A, B, FWD>(lds, v.in, v.out, tw_all + ((size_t)v.g << (A + B)), pc, tile);
 }
 
-// First forward pass of NTT(conv) with the ModDown base conversion as its
-// prologue: limb (c, i) of conv [2][nl][N] from the K P-limbs of ip[c].
-template <int A, int B, int KP>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KP == 8 ? kNttWavesCols : kNttWavesFused))) void ntt_cols_moddown_kernel(
-    const uint64_t *ip, uint64_t *conv, const TwPair *__restrict__ tw_all, const PrimeConst *__restrict__ pcs,
-    const uint64_t *__restrict__ cross, const uint64_t *__restrict__ negp, uint32_t nl, uint32_t L, uint32_t K) {
-    __shared__ uint64_t lds[(1 << A) * (kTile / (1 << A) + 1)];
-    constexpr int LOGN = A + B;
-    const uint32_t tile = blockIdx.x;
-    const uint32_t c = blockIdx.y & 1, i = blockIdx.y >> 1;  // polynomials interleaved
-    const PrimeConst pc = pcs[i];
+// Prologue of the first pass of NTT(conv): the ModDown conversion of target i
+// of polynomial c from the K P-limbs of ip[c] ([2][nl + K][N]).
+template <int KP, int LOGN>
+__device__ __forceinline__ ModdownPro<KP> moddown_pro(const uint64_t *ip, const PrimeConst *__restrict__ pcs,
+                                                      const PrimeConst &pc, const uint64_t *__restrict__ cross,
+                                                      const uint64_t *__restrict__ negp, uint32_t c, uint32_t i,
+                                                      uint32_t nl, uint32_t L, uint32_t K) {
     ModdownPro<KP> pro;
     pro.src = ip + (((size_t)c * (nl + K) + nl) << LOGN);
     pro.stride = (size_t)1 << LOGN;
@@ -71,6 +67,43 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KP == 
     pro.r64 = pc.r64;
     pro.r64_p = pc.r64_p;
     pro.one_p = pc.one_p;
+    return pro;
+}
+
+// Prologue of the first pass of NTT(lift): the lift of polynomial c's last
+// limb (last [2][N], dropped prime l = nl - 1) into prime i.
+template <bool KEEP_T, int LOGN>
+__device__ __forceinline__ LiftPro<KEEP_T> lift_pro(const uint64_t *last, const PrimeConst *__restrict__ pcs,
+                                                    const PrimeConst &pc, const uint64_t *__restrict__ tab,
+                                                    uint32_t c, uint32_t i, uint32_t nl, uint32_t L) {
+    const uint32_t l = nl - 1;
+    const PrimeConst pl = pcs[l];
+    LiftPro<KEEP_T> pro;
+    pro.last = last + ((size_t)c << LOGN);
+    pro.ql = pl.q;
+    pro.ql_half = pl.q >> 1;
+    pro.tinv = pl.tinv;
+    pro.tinv_p = pl.tinv_p;
+    pro.q = pc.q;
+    pro.one_p = pc.one_p;
+    pro.corr = tab[((size_t)l * L + i) * 3 + 2];
+    pro.tmod = pc.tmod;
+    pro.tmod_p = pc.tmod_p;
+    return pro;
+}
+
+// First forward pass of NTT(conv) with the ModDown base conversion as its
+// prologue: limb (c, i) of conv [2][nl][N] from the K P-limbs of ip[c].
+template <int A, int B, int KP>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KP == 8 ? kNttWavesCols : kNttWavesFused))) void ntt_cols_moddown_kernel(
+    const uint64_t *ip, uint64_t *conv, const TwPair *__restrict__ tw_all, const PrimeConst *__restrict__ pcs,
+    const uint64_t *__restrict__ cross, const uint64_t *__restrict__ negp, uint32_t nl, uint32_t L, uint32_t K) {
+    __shared__ uint64_t lds[(1 << A) * (kTile / (1 << A) + 1)];
+    constexpr int LOGN = A + B;
+    const uint32_t tile = blockIdx.x;
+    const uint32_t c = blockIdx.y & 1, i = blockIdx.y >> 1;  // polynomials interleaved
+    const PrimeConst pc = pcs[i];
+    const ModdownPro<KP> pro = moddown_pro<KP, LOGN>(ip, pcs, pc, cross, negp, c, i, nl, L, K);
     ntt_cols_unit_pro<A, B, true, B == 8>(lds, conv + (((size_t)c * nl + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
                                   tile, pro);
 }
@@ -86,19 +119,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
     const uint32_t l = nl - 1;
     const uint32_t tile = blockIdx.x;
     const uint32_t c = blockIdx.y & 1, i = blockIdx.y >> 1;  // polynomials interleaved
-    const PrimeConst pl = pcs[l];
     const PrimeConst pc = pcs[i];
-    LiftPro<KEEP_T> pro;
-    pro.last = last + ((size_t)c << LOGN);
-    pro.ql = pl.q;
-    pro.ql_half = pl.q >> 1;
-    pro.tinv = pl.tinv;
-    pro.tinv_p = pl.tinv_p;
-    pro.q = pc.q;
-    pro.one_p = pc.one_p;
-    pro.corr = tab[((size_t)l * L + i) * 3 + 2];
-    pro.tmod = pc.tmod;
-    pro.tmod_p = pc.tmod_p;
+    const LiftPro<KEEP_T> pro = lift_pro<KEEP_T, LOGN>(last, pcs, pc, tab, c, i, nl, L);
     ntt_cols_unit_pro<A, B, true, B == 8>(lds, lift + (((size_t)c * l + i) << LOGN), tw_all + ((size_t)i << LOGN), pc,
                                   tile, pro);
 }
@@ -229,6 +251,87 @@ __global__ __launch_bounds__(TILE / E) void ntt_small_kernel(NttBatch b, const T
 // us); rf_tuning picks per level.
 constexpr int kSmallE = 4;
 
+// The passes of the fused ModDown, rescale and first-INTT launches on small
+// tiles (the same prologues and epilogues as their 4096-tile kernels; natural
+// twiddle tables, strict butterflies in both passes of a limb).
+template <int A, int B, int TILE, int KP>
+__global__ __launch_bounds__(TILE / kSmallE) void ntt_small_cols_moddown_kernel(
+    const uint64_t *ip, uint64_t *conv, const TwPair *__restrict__ tw_all, const PrimeConst *__restrict__ pcs,
+    const uint64_t *__restrict__ cross, const uint64_t *__restrict__ negp, uint32_t nl, uint32_t L, uint32_t K) {
+    __shared__ uint64_t lds[(1 << A) * (TILE / (1 << A) + 1)];
+    constexpr int LOGN = A + B;
+    const uint32_t c = blockIdx.y & 1, i = blockIdx.y >> 1;
+    const PrimeConst pc = pcs[i];
+    const ModdownPro<KP> pro = moddown_pro<KP, LOGN>(ip, pcs, pc, cross, negp, c, i, nl, L, K);
+    ntt_cols_small_pro<A, B, true, TILE, kSmallE>(lds, pro, conv + (((size_t)c * nl + i) << LOGN),
+                                                  tw_all + ((size_t)i << LOGN), pc, xcd_grouped_tile<TILE, A>());
+}
+
+template <int A, int B, int TILE>
+__global__ __launch_bounds__(TILE / kSmallE) void ntt_small_rows_moddown_kernel(
+    const uint64_t *conv, const TwPair *__restrict__ tw_all, const PrimeConst *__restrict__ pcs, const uint64_t *ip,
+    uint64_t *out, const uint64_t *__restrict__ pinv, uint32_t nl, uint32_t K) {
+    __shared__ uint64_t lds[(1 << B) * (TILE / (1 << B) + 1)];
+    constexpr int LOGN = A + B;
+    const uint32_t c = blockIdx.y & 1, i = blockIdx.y >> 1;
+    const PrimeConst pc = pcs[i];
+    const ModdownFoldEpi epi{ip + (((size_t)c * (nl + K) + i) << LOGN), out + (((size_t)c * nl + i) << LOGN),
+                             pinv[2 * i], pinv[2 * i + 1], pc.q};
+    ntt_rows_small_pe<A, B, true, TILE, kSmallE>(lds, LoadPro{conv + (((size_t)c * nl + i) << LOGN)},
+                                                 tw_all + ((size_t)i << LOGN), pc, blockIdx.x, epi);
+}
+
+template <int A, int B, int TILE, bool KEEP_T>
+__global__ __launch_bounds__(TILE / kSmallE) void ntt_small_cols_lift_kernel(
+    const uint64_t *last, uint64_t *lift, const TwPair *__restrict__ tw_all, const PrimeConst *__restrict__ pcs,
+    const uint64_t *__restrict__ tab, uint32_t nl, uint32_t L) {
+    __shared__ uint64_t lds[(1 << A) * (TILE / (1 << A) + 1)];
+    constexpr int LOGN = A + B;
+    const uint32_t l = nl - 1;
+    const uint32_t c = blockIdx.y & 1, i = blockIdx.y >> 1;
+    const PrimeConst pc = pcs[i];
+    const LiftPro<KEEP_T> pro = lift_pro<KEEP_T, LOGN>(last, pcs, pc, tab, c, i, nl, L);
+    ntt_cols_small_pro<A, B, true, TILE, kSmallE>(lds, pro, lift + (((size_t)c * l + i) << LOGN),
+                                                  tw_all + ((size_t)i << LOGN), pc, xcd_grouped_tile<TILE, A>());
+}
+
+template <int A, int B, int TILE>
+__global__ __launch_bounds__(TILE / kSmallE) void ntt_small_rows_rescale_kernel(
+    const uint64_t *lift, const TwPair *__restrict__ tw_all, const PrimeConst *__restrict__ pcs, const uint64_t *in,
+    uint64_t *out, const uint64_t *__restrict__ tab, uint32_t nl, uint32_t L) {
+    __shared__ uint64_t lds[(1 << B) * (TILE / (1 << B) + 1)];
+    constexpr int LOGN = A + B;
+    const uint32_t l = nl - 1;
+    const uint32_t c = blockIdx.y & 1, i = blockIdx.y >> 1;
+    const PrimeConst pc = pcs[i];
+    const uint64_t *t = tab + ((size_t)l * L + i) * 3;
+    const RescaleTailEpi epi{in + (((size_t)c * nl + i) << LOGN), out + (((size_t)c * l + i) << LOGN), t[0], t[1],
+                             pc.q};
+    ntt_rows_small_pe<A, B, true, TILE, kSmallE>(lds, LoadPro{lift + (((size_t)c * l + i) << LOGN)},
+                                                 tw_all + ((size_t)i << LOGN), pc, blockIdx.x, epi);
+}
+
+// First pass of INTT(d2) (galois == 0: d2 = a1 b1 of a, b) or of INTT(sigma_g(a1))
+// on small tiles, into dc [nl][N].
+template <int A, int B, int TILE>
+__global__ __launch_bounds__(TILE / kSmallE) void ntt_small_inv_rows_first_kernel(
+    const uint64_t *a, const uint64_t *b, uint64_t *dc, uint32_t galois, const TwPair *__restrict__ tw_all,
+    const PrimeConst *__restrict__ pcs, uint32_t nl) {
+    __shared__ uint64_t lds[(1 << B) * (TILE / (1 << B) + 1)];
+    constexpr int LOGN = A + B;
+    const uint32_t i = blockIdx.y;
+    const PrimeConst pc = pcs[i];
+    const size_t li = (size_t)i << LOGN, poly = (size_t)nl << LOGN;
+    if (galois) {
+        const GatherPro pro{a + poly + li, galois, (uint32_t)LOGN};
+        ntt_rows_small_pe<A, B, false, TILE, kSmallE>(lds, pro, tw_all + li, pc, blockIdx.x, StoreEpi{dc + li});
+    } else {
+        const TensorPro pro{a + poly + li, b + poly + li, pc.q, pc.r64, pc.r64_p, pc.one_p};
+        ntt_rows_small_pe<A, B, false, TILE, kSmallE>(lds, pro, tw_all + li, pc, blockIdx.x, StoreEpi{dc + li});
+    }
+}
+
+
 template <int A, int B, int TILE, int E>
 static void launch_two_pass_small(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s,
                                   const PrimeConst *pcs) {
@@ -294,12 +397,57 @@ static void launch_two_pass(const rf_ctx *c, const NttBatch &b, bool forward, hi
     }
 }
 
+// Small-tile size of a fused launch of `limbs` limbs, or 0 for the 4096-residue
+// tiles (launch_two_pass's rule with the fused launches' threshold).
+static int small_tile_of(const rf_ctx *c, uint32_t limbs, const rf_tuning *tn) {
+    const rf_tuning &t = tn ? *tn : kDefaultTuning;
+    const uint32_t tiles = limbs * (c->n / kTile);
+    if (c->log_n < 13 || tiles >= t.ntt_fused_small_below) return 0;
+    return t.ntt_small_tile == 2048 || (t.ntt_small_tile == 0 && tiles * 2 >= t.ntt_fused_small_below) ? 2048 : 1024;
+}
+
 int launch_ntt_fwd_moddown(const rf_ctx *c, uint64_t *conv, const uint64_t *ip, uint64_t *out, uint32_t nl,
-                           hipStream_t s) {
+                           hipStream_t s, const rf_tuning *tn) {
     const uint64_t *tab = c->scheme == RF_BGV ? c->d_moddown_t : c->d_moddown;
     const uint64_t *cross = tab + moddown_cross_off(c), *negp = tab + moddown_negp_off(c);
     const uint64_t *pinv = c->d_moddown + moddown_pinv_off(c);
     const dim3 g(c->n / kTile, 2 * nl);
+    const int st = small_tile_of(c, 2 * nl, tn);
+    if (st) {
+#define RF_SMDK(A, B, T, KP)                                                                                     \
+    hipLaunchKernelGGL((ntt_small_cols_moddown_kernel<A, B, T, KP>), dim3(c->n / T, 2 * nl), dim3(T / kSmallE), 0, s, \
+                       ip, conv, c->d_tw_fwd, c->d_pc, cross, negp, nl, c->L, c->K)
+#define RF_SMD(A, B, T)                                                                                          \
+    {                                                                                                            \
+        {                                                                                                        \
+            ProfScope p("ntt_fwd_cols_moddown_small", s);                                                        \
+            switch (c->K) {                                                                                      \
+                case 1: RF_SMDK(A, B, T, 1); break;                                                              \
+                case 2: RF_SMDK(A, B, T, 2); break;                                                              \
+                case 3: RF_SMDK(A, B, T, 3); break;                                                              \
+                case 4: RF_SMDK(A, B, T, 4); break;                                                              \
+                default: RF_SMDK(A, B, T, 8); break;                                                             \
+            }                                                                                                    \
+        }                                                                                                        \
+        ProfScope p("ntt_fwd_rows_moddown_small", s);                                                            \
+        hipLaunchKernelGGL((ntt_small_rows_moddown_kernel<A, B, T>), dim3(c->n / T, 2 * nl), dim3(T / kSmallE), 0, s, \
+                           conv, c->d_tw_fwd, c->d_pc, ip, out, pinv, nl, c->K);                                 \
+    }
+#define RF_SMDT(A, B) \
+    if (st == 2048) RF_SMD(A, B, 2048) else RF_SMD(A, B, 1024)
+        switch (c->log_n) {
+            case 13: RF_SMDT(7, 6) break;
+            case 14: RF_SMDT(7, 7) break;
+            case 15: RF_SMDT(8, 7) break;
+            default: RF_SMDT(8, 8) break;
+        }
+#undef RF_SMDT
+#undef RF_SMD
+#undef RF_SMDK
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(RF_EHIP, std::string("NTT launch: ") + hipGetErrorString(e));
+        return RF_OK;
+    }
 #define RF_MDK(A, B, KP)                                                                                         \
     hipLaunchKernelGGL((ntt_cols_moddown_kernel<A, B, KP>), dim3((1u << B) / (kTile >> A), 2 * nl), dim3(kThreads), \
                        0, s, ip, conv, c->d_tw_fwd, c->d_pc, cross, negp, nl, c->L, c->K)
@@ -334,9 +482,41 @@ int launch_ntt_fwd_moddown(const rf_ctx *c, uint64_t *conv, const uint64_t *ip, 
 }
 
 int launch_ntt_fwd_rescale(const rf_ctx *c, const uint64_t *last, uint64_t *lift, const uint64_t *in,
-                           uint64_t *out, uint32_t nl, bool keep_t, hipStream_t s) {
+                           uint64_t *out, uint32_t nl, bool keep_t, hipStream_t s, const rf_tuning *tn) {
     const uint32_t l = nl - 1;
     const dim3 g(c->n / kTile, 2 * l);
+    const int st = small_tile_of(c, 2 * l, tn);
+    if (st) {
+#define RF_SRS(A, B, T)                                                                                          \
+    {                                                                                                            \
+        const dim3 gs(c->n / T, 2 * l), bs(T / kSmallE);                                                         \
+        {                                                                                                        \
+            ProfScope p("ntt_fwd_cols_lift_small", s);                                                           \
+            if (keep_t)                                                                                          \
+                hipLaunchKernelGGL((ntt_small_cols_lift_kernel<A, B, T, true>), gs, bs, 0, s, last, lift,        \
+                                   c->d_tw_fwd, c->d_pc, c->d_rescale, nl, c->L);                                \
+            else                                                                                                 \
+                hipLaunchKernelGGL((ntt_small_cols_lift_kernel<A, B, T, false>), gs, bs, 0, s, last, lift,       \
+                                   c->d_tw_fwd, c->d_pc, c->d_rescale, nl, c->L);                                \
+        }                                                                                                        \
+        ProfScope p("ntt_fwd_rows_rescale_small", s);                                                            \
+        hipLaunchKernelGGL((ntt_small_rows_rescale_kernel<A, B, T>), gs, bs, 0, s, lift, c->d_tw_fwd, c->d_pc, in, \
+                           out, c->d_rescale, nl, c->L);                                                         \
+    }
+#define RF_SRST(A, B) \
+    if (st == 2048) RF_SRS(A, B, 2048) else RF_SRS(A, B, 1024)
+        switch (c->log_n) {
+            case 13: RF_SRST(7, 6) break;
+            case 14: RF_SRST(7, 7) break;
+            case 15: RF_SRST(8, 7) break;
+            default: RF_SRST(8, 8) break;
+        }
+#undef RF_SRST
+#undef RF_SRS
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(RF_EHIP, std::string("NTT launch: ") + hipGetErrorString(e));
+        return RF_OK;
+    }
 #define RF_RS(A, B)                                                                                              \
     {                                                                                                            \
         {                                                                                                        \
@@ -367,8 +547,37 @@ int launch_ntt_fwd_rescale(const rf_ctx *c, const uint64_t *last, uint64_t *lift
 }
 
 int launch_intt_first(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *dc, uint32_t galois,
-                      uint32_t nl, hipStream_t s) {
+                      uint32_t nl, hipStream_t s, const rf_tuning *tn) {
     const uint64_t N = c->n;
+    const int st = small_tile_of(c, nl, tn);
+    if (st) {
+#define RF_SIF(A, B, T)                                                                                          \
+    {                                                                                                            \
+        const dim3 gs(c->n / T, nl), bs(T / kSmallE);                                                            \
+        {                                                                                                        \
+            ProfScope p(galois ? "ntt_inv_rows_gather_small" : "ntt_inv_rows_tensor_small", s);                  \
+            hipLaunchKernelGGL((ntt_small_inv_rows_first_kernel<A, B, T>), gs, bs, 0, s, a, b, dc, galois,      \
+                               c->d_tw_inv, c->d_pc, nl);                                                        \
+        }                                                                                                        \
+        NttBatch bc{dc, dc, 0, 0, nl, 1, 0, nullptr};                                                            \
+        ProfScope p("ntt_inv_cols_small", s);                                                                    \
+        hipLaunchKernelGGL((ntt_small_kernel<A, B, false, true, T, kSmallE>), gs, bs, 0, s, bc, c->d_tw_inv,     \
+                           pc_modup(c, nl));                                                                     \
+    }
+#define RF_SIFT(A, B) \
+    if (st == 2048) RF_SIF(A, B, 2048) else RF_SIF(A, B, 1024)
+        switch (c->log_n) {
+            case 13: RF_SIFT(7, 6) break;
+            case 14: RF_SIFT(7, 7) break;
+            case 15: RF_SIFT(8, 7) break;
+            default: RF_SIFT(8, 8) break;
+        }
+#undef RF_SIFT
+#undef RF_SIF
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(RF_EHIP, std::string("NTT launch: ") + hipGetErrorString(e));
+        return RF_OK;
+    }
 #define RF_IF(A, B)                                                                                              \
     {                                                                                                            \
         const dim3 gr((1u << A) / (kTile >> B), nl);                                                             \

@@ -219,6 +219,20 @@ __device__ __forceinline__ void ntt_rounds(uint64_t *lds, int ldu, int u, int t,
     ntt_rounds_from<S_LOG, 0, FWD, SCALE_LAST, ROW_A, LZ, E>(lds, ldu, u, t, tw_base, tw, pc);
 }
 
+// Plain load of a pass (no prologue).
+struct LoadPro {
+    const uint64_t *in;
+    __device__ __forceinline__ uint64_t operator()(size_t idx) const { return in[idx]; }
+};
+
+// Final store of a pass: out[idx] = x.  Passes take the store as a functor, so
+// an element-wise step that follows the transform (the ModDown or rescale
+// tail) runs in the pass's epilogue instead of another kernel.
+struct StoreEpi {
+    uint64_t *out;
+    __device__ __forceinline__ void operator()(size_t idx, uint64_t x) const { out[idx] = x; }
+};
+
 // Passes of launches with few limbs (the INTT of the special-prime limbs before
 // ModDown, the INTT of the dropped limb before a rescale): a tile of TILE
 // residues (fewer than kTile) and E residues per thread (fewer than kElems), so
@@ -228,16 +242,16 @@ __device__ __forceinline__ void ntt_rounds(uint64_t *lds, int ldu, int u, int t,
 // ranges as the kTile passes (forward columns lazy below 4q, forward rows in
 // [0, q); inverse rows lazy below 2q, inverse columns in [0, q)).  Ends with a
 // barrier.
-template <int A, int B, bool FWD, int TILE, int E>
-__device__ __forceinline__ void ntt_cols_small(uint64_t *lds, const uint64_t *in, uint64_t *out,
-                                               const TwPair *__restrict__ tw, const PrimeConst &pc, int tile) {
+template <int A, int B, bool FWD, int TILE, int E, typename Pro>
+__device__ __forceinline__ void ntt_cols_small_pro(uint64_t *lds, const Pro &pro, uint64_t *out,
+                                                   const TwPair *__restrict__ tw, const PrimeConst &pc, int tile) {
     constexpr int U = TILE >> A, LDU = U + 1, NT = TILE / E;
     static_assert(U >= 1 && NT >= 64, "small column tile");
     const int col0 = tile * U;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int idx = threadIdx.x + r * NT;
-        lds[(idx / U) * LDU + idx % U] = in[((size_t)(idx / U) << B) + col0 + idx % U];
+        lds[(idx / U) * LDU + idx % U] = pro(((size_t)(idx / U) << B) + col0 + idx % U);
     }
     __syncthreads();
     ntt_rounds<A, FWD, !FWD, 0, false, E>(lds, LDU, threadIdx.x % U, threadIdx.x / U, 1u, tw, pc);
@@ -251,15 +265,23 @@ __device__ __forceinline__ void ntt_cols_small(uint64_t *lds, const uint64_t *in
 }
 
 template <int A, int B, bool FWD, int TILE, int E>
-__device__ __forceinline__ void ntt_rows_small(uint64_t *lds, const uint64_t *in, uint64_t *out,
+__device__ __forceinline__ void ntt_cols_small(uint64_t *lds, const uint64_t *in, uint64_t *out,
                                                const TwPair *__restrict__ tw, const PrimeConst &pc, int tile) {
+    ntt_cols_small_pro<A, B, FWD, TILE, E>(lds, LoadPro{in}, out, tw, pc, tile);
+}
+
+// The result for limb index idx goes through epi(idx, value) (forward: in
+// [0, q); inverse: lazy in [0, 2q)).
+template <int A, int B, bool FWD, int TILE, int E, typename Pro, typename Epi>
+__device__ __forceinline__ void ntt_rows_small_pe(uint64_t *lds, const Pro &pro, const TwPair *__restrict__ tw,
+                                                  const PrimeConst &pc, int tile, const Epi &epi) {
     constexpr int S = 1 << B, U = TILE >> B, LDU = U + 1, NT = TILE / E;
     static_assert(U >= 1 && NT >= 64, "small row tile");
     const int row0 = tile * U;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int idx = threadIdx.x + r * NT;
-        lds[(idx & (S - 1)) * LDU + (idx >> B)] = in[((size_t)(row0 + (idx >> B)) << B) + (idx & (S - 1))];
+        lds[(idx & (S - 1)) * LDU + (idx >> B)] = pro(((size_t)(row0 + (idx >> B)) << B) + (idx & (S - 1)));
     }
     __syncthreads();
     const int u = threadIdx.x % U;
@@ -269,9 +291,15 @@ __device__ __forceinline__ void ntt_rows_small(uint64_t *lds, const uint64_t *in
     for (int r = 0; r < E; ++r) {
         const int idx = threadIdx.x + r * NT;
         const uint64_t x = lds[(idx & (S - 1)) * LDU + (idx >> B)];
-        out[((size_t)(row0 + (idx >> B)) << B) + (idx & (S - 1))] = FWD ? csub(csub(x, q2), pc.q) : x;
+        epi(((size_t)(row0 + (idx >> B)) << B) + (idx & (S - 1)), FWD ? csub(csub(x, q2), pc.q) : x);
     }
     __syncthreads();
+}
+
+template <int A, int B, bool FWD, int TILE, int E>
+__device__ __forceinline__ void ntt_rows_small(uint64_t *lds, const uint64_t *in, uint64_t *out,
+                                               const TwPair *__restrict__ tw, const PrimeConst &pc, int tile) {
+    ntt_rows_small_pe<A, B, FWD, TILE, E>(lds, LoadPro{in}, tw, pc, tile, StoreEpi{out});
 }
 
 // Column pass: sub-transforms are columns (2^A rows, stride 2^B), tile
@@ -373,11 +401,6 @@ __device__ __forceinline__ void ntt_cols_unit_pro(uint64_t *lds, uint64_t *out, 
     ntt_cols_compute<A, B, FWD, LZOK>(lds, out, tw, pc, tile, regs);
 }
 
-struct LoadPro {
-    const uint64_t *in;
-    __device__ __forceinline__ uint64_t operator()(size_t idx) const { return in[idx]; }
-};
-
 template <int A, int B, bool FWD>
 __device__ __forceinline__ void ntt_cols_unit(uint64_t *lds, const uint64_t *in, uint64_t *out,
                                               const TwPair *__restrict__ tw, const PrimeConst &pc, int tile) {
@@ -430,14 +453,6 @@ struct ModdownPro {
         acc.add(cnt * negp);
         return reduce128_lazy(acc.value(), q, r64, r64_p, one_p);
     }
-};
-
-// Final store of a pass: out[idx] = x.  Passes take the store as a functor, so
-// an element-wise step that follows the transform (the ModDown or rescale
-// tail) runs in the pass's epilogue instead of another kernel.
-struct StoreEpi {
-    uint64_t *out;
-    __device__ __forceinline__ void operator()(size_t idx, uint64_t x) const { out[idx] = x; }
 };
 
 // Row pass: sub-transforms are rows (2^B contiguous residues), tile `tile`

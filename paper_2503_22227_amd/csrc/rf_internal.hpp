@@ -118,7 +118,7 @@ struct rf_ctx {
 namespace rf {
 
 // Defaults of rf_tuning.
-constexpr rf_tuning kDefaultTuning = {256, 0, 4, 8};
+constexpr rf_tuning kDefaultTuning = {256, 0, 4, 8, 0};
 inline const rf_tuning &level_tuning(const rf_ctx *c, uint32_t nl) {
     return c->tuning[nl < 1 ? 1 : (nl > c->L ? c->L : nl)];
 }
@@ -198,20 +198,20 @@ int launch_ntt(const rf_ctx *c, const NttBatch &b, bool forward, hipStream_t s, 
 // ip's Q-limbs must come from launch_inner_product with fold (P^-1 and the addends
 // applied), so the tail is out[c][i] = ip[c][i] - NTT(conv)[c][i] P^-1.
 int launch_ntt_fwd_moddown(const rf_ctx *c, uint64_t *conv, const uint64_t *ip, uint64_t *out, uint32_t nl,
-                           hipStream_t s);
+                           hipStream_t s, const rf_tuning *tn = nullptr);
 // INTT of the polynomial to key-switch (two-pass ring degrees only), with the
 // step that produces it as the prologue of its first pass, into dc [nl][N]
 // (coefficient domain, scaled for ModUp by pc_modup(c, nl)):
 //   galois == 0 (HMult): d2 = a1 b1 of a, b ([2][nl][N]);
 //   galois != 0 (HRotate): sigma_g of a's polynomial 1.
 int launch_intt_first(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *dc, uint32_t galois,
-                      uint32_t nl, hipStream_t s);
+                      uint32_t nl, hipStream_t s, const rf_tuning *tn = nullptr);
 // Rescale / modulus switch after the INTT of the last limb (last = [2][N]),
 // two-pass ring degrees only: the first forward pass lifts the last limb into
 // each remaining prime in its prologue (into lift [2][nl-1][N]; KEEP_T for BGV),
 // the last applies the tail out[c][i] = (in[c][i] - NTT(lift)) q_l^-1.
 int launch_ntt_fwd_rescale(const rf_ctx *c, const uint64_t *last, uint64_t *lift, const uint64_t *in,
-                           uint64_t *out, uint32_t nl, bool keep_t, hipStream_t s);
+                           uint64_t *out, uint32_t nl, bool keep_t, hipStream_t s, const rf_tuning *tn = nullptr);
 int launch_tensor(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *d01,
                   uint64_t *d2, uint32_t nl, hipStream_t s);
 // scaled: x is an INTT taken with pc_modup(c, nl), so each limb already carries

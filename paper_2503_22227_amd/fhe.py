@@ -109,7 +109,7 @@ class Context:
         return ws
 
     # ---------------------------------------------------------------- kernel variants
-    TUNING_FIELDS = ("ntt_small_below", "ntt_small_tile", "ntt_small_radix", "modup_chunk")
+    TUNING_FIELDS = ("ntt_small_below", "ntt_small_tile", "ntt_small_radix", "modup_chunk", "ntt_fused_small_below")
 
     def set_tuning(self, nlimbs: int, setting: dict) -> None:
         """Kernel variants of level ``nlimbs`` (0: every level); fields not given keep

@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 # every value of every knob at least once; small_below 4096 sends every plain
-# (I)NTT launch of these shapes to the small tiles
+# (I)NTT launch of these shapes to the small tiles, fused_small_below 4096 every
+# launch with a fused step
 VARIANTS = [
     dict(ntt_small_below=0),
     dict(ntt_small_below=4096, ntt_small_tile=1024, ntt_small_radix=4),
@@ -26,8 +27,11 @@ VARIANTS = [
     dict(modup_chunk=4),
     dict(modup_chunk=16),
     dict(ntt_small_below=64, modup_chunk=16),
+    dict(ntt_fused_small_below=4096, ntt_small_tile=1024),
+    dict(ntt_fused_small_below=4096, ntt_small_tile=2048),
+    dict(ntt_small_below=4096, ntt_fused_small_below=512, ntt_small_tile=0, modup_chunk=4),
 ]
-DEFAULT = dict(ntt_small_below=256, ntt_small_tile=0, ntt_small_radix=4, modup_chunk=8)
+DEFAULT = dict(ntt_small_below=256, ntt_small_tile=0, ntt_small_radix=4, modup_chunk=8, ntt_fused_small_below=0)
 
 
 def dev(a):
