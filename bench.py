@@ -48,8 +48,12 @@ def parse():
     ap.add_argument("--no-bfv-bgv", action="store_true", help="skip the BFV/BGV section")
     ap.add_argument("--no-shapes", action="store_true",
                     help="skip the alpha=4 and N=2^12 shapes (profiling runs of the headline workload alone)")
+    ap.add_argument("--variants", choices=("tuned", "default"), default="tuned",
+                    help="tuned: the shipped per-device settings (a search of the headline level where none "
+                         "ships); default: the library's default kernel variants everywhere")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default kernel variants (no autotuner search, no autotune section)")
+                    help="skip the autotune section (searches against the defaults at six shapes) and the "
+                         "batch autotune")
     ap.add_argument("--ntt-microbench", action="store_true",
                     help="only time forward and inverse NTTs of 60 limbs at N=2^16 (kernel profiling)")
     ap.add_argument("--workload", default="ckks_n16_l24")
@@ -210,6 +214,8 @@ def main():
         print(json.dumps({"section": args.section, "reps": args.steps, "result": fn(args.steps)}), flush=True)
         return
 
+    if args.variants == "default":
+        os.environ["RF_NO_SHIPPED_TUNING"] = "1"
     import synthetic
 
     w = synthetic.WORKLOADS[args.workload]
@@ -284,12 +290,16 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / 1e3
 
-    # kernel variants of this level picked by the autotuner (a fresh search; every
-    # variant gives the same residues)
+    # kernel variants of this level: the setting shipped for this device and
+    # shape (applied when the context was created), or the autotuner's search
+    # when none ships; every variant gives the same residues
     from paper_2503_22227_amd import autotune
-    tuning = None
-    if not args.no_autotune:
-        tuning = autotune.tune_level(ctx, L, step, reps=10, use_cache=False)
+    if args.variants == "default":
+        tuning = {"source": "default", "setting": ctx.get_tuning(L)}
+    elif ctx.get_tuning(L) != autotune.DEFAULT_LEVEL:
+        tuning = {"source": "shipped", "setting": ctx.get_tuning(L), "default": dict(autotune.DEFAULT_LEVEL)}
+    else:
+        tuning = dict(autotune.tune_level(ctx, L, step, reps=10, use_cache=False), source="search")
         _progress("autotune of the headline level done")
     for _ in range(args.warmup):
         step_concurrent()
