@@ -22,15 +22,15 @@ batched ModUp limb grouping.
 
 Settings found on a device can be shipped with the package
 (``tuned_variants.json``, written by ``python -m paper_2503_22227_amd.autotune
---write-table``): a context created on a device of the same name and CU count
+--write-table``): a context created on a device of the same architecture and CU count
 applies the entry of its ring degree, alpha and special-prime count at every
 level it lists (``apply_shipped``; RF_NO_SHIPPED_TUNING=1 keeps the defaults).
 
 Both searches are coordinate descent from the defaults: each candidate value of
 one knob is timed with HIP events, and a change is kept only if it is faster
 than the best so far by more than ``min_gain`` (a relative margin, so timing
-noise does not move the setting).  Results are cached per device (name and CU
-count) and shape in a JSON file (RF_AUTOTUNE_CACHE, default
+noise does not move the setting).  Results are cached per device (architecture and
+CU count) and shape in a JSON file (RF_AUTOTUNE_CACHE, default
 ~/.cache/rnsfhe_autotune.json).  Every variant computes the same residues, so
 tuning changes speed only.
 """
@@ -68,8 +68,11 @@ def cache_path() -> str:
 
 
 def device_key(device=None) -> str:
+    """Architecture and CU count (the marketing name a process sees depends on
+    how the runtime was loaded, e.g. under a profiler)."""
     p = torch.cuda.get_device_properties(device if device is not None else torch.cuda.current_device())
-    return "%s|%dcu" % (p.name, p.multi_processor_count)
+    arch = getattr(p, "gcnArchName", "") or p.name
+    return "%s|%dcu" % (arch.split(":")[0], p.multi_processor_count)
 
 
 def shape_key(shape) -> str:
