@@ -235,14 +235,14 @@ def tune(plan, shape, reps: int = 3, use_cache: bool = True, min_gain: float = 0
 SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_variants.json")
 
 
-def shipped_key(log_n: int, alpha: int, k: int, nlimbs: int) -> str:
-    return "ckks:%d:%d:%d:%d" % (log_n, alpha, k, nlimbs)
+def shipped_key(scheme: str, log_n: int, alpha: int, k: int, nlimbs: int) -> str:
+    return "%s:%d:%d:%d:%d" % (scheme, log_n, alpha, k, nlimbs)
 
 
 def apply_shipped(ctx, path: str = SHIPPED) -> int:
     """Apply the shipped settings of ``ctx``'s device and shape to its levels;
     returns the number of levels set (0 when the table has no entry)."""
-    if os.environ.get("RF_NO_SHIPPED_TUNING") == "1" or ctx.scheme != "ckks" or not os.path.exists(path):
+    if os.environ.get("RF_NO_SHIPPED_TUNING") == "1" or not os.path.exists(path):
         return 0
     try:
         with open(path) as f:
@@ -251,19 +251,24 @@ def apply_shipped(ctx, path: str = SHIPPED) -> int:
         return 0
     n = 0
     for nl in range(1, ctx.L + 1):
-        setting = table.get(shipped_key(ctx.log_n, ctx.alpha, ctx.k, nl))
+        setting = table.get(shipped_key(ctx.scheme, ctx.log_n, ctx.alpha, ctx.k, nl))
         if setting:
             ctx.set_tuning(nl, setting)
             n += 1
     return n
 
 
-def write_table(out: str, log_ns=(14, 15, 16), levels=(4, 8, 12, 16, 20, 24), reps: int = 10) -> dict:
-    """Tune HMult+Relin, rescale and HRotate at each (ring degree, level) of the
-    batched workload's chain (24 + 4 primes, alpha = 8) and of the serving
-    workload's (alpha = 4, N = 2^16), keep the settings that differ from the
-    defaults, and write them for this device into ``out``; every level between two
-    tuned ones takes the lower one's setting."""
+# (workload, ring degrees) searched by write_table
+TABLE_WORKLOADS = (("ckks_batch", (14, 15, 16)), ("pdq", (16,)), ("bgv_n15", (15,)), ("bfv_n15", (15,)))
+
+
+def write_table(out: str, workloads=TABLE_WORKLOADS, levels=None, reps: int = 10) -> dict:
+    """Tune each level of each workload's chain for one operation at a time: CKKS
+    HMult+Relin, rescale and HRotate; BGV HMult+Relin, modulus switch and HRotate;
+    BFV HMult+Relin and HRotate (at all L limbs, the only level BFV runs at).
+    Settings that differ from the defaults are merged into this device's entry of
+    ``out``; with ``levels`` given, a level in between takes the setting of the
+    tuned level below it."""
     import synthetic
     from .fhe import Context
     from .params import chain_for
@@ -272,35 +277,44 @@ def write_table(out: str, log_ns=(14, 15, 16), levels=(4, 8, 12, 16, 20, 24), re
     table = {}
     saved = os.environ.get("RF_NO_SHIPPED_TUNING")
     os.environ["RF_NO_SHIPPED_TUNING"] = "1"  # search from the defaults
-    for wname, lns in (("ckks_batch", log_ns), ("pdq", (16,))):
+    for wname, lns in workloads:
         w = synthetic.WORKLOADS[wname]
         ch = chain_for(w)
         qp = ch["q"] + ch["p"]
+        scheme = w["scheme"]
+        kw = {}
+        if scheme != "ckks":
+            kw = dict(scheme=scheme, t=w["t"])
+        if scheme == "bfv":
+            kw.update(b=ch["b"], m_sk=ch["msk"])
         gen = torch.Generator(device="cuda")
         gen.manual_seed(w["seed"] + 11)
         for ln in lns:
-            ctx = Context(ch["q"], ch["p"], ln, w["alpha"], log_nmax=w["log_nmax"])
+            ctx = Context(ch["q"], ch["p"], ln, w["alpha"], log_nmax=w["log_nmax"], **kw)
             n = 1 << ln
             key = torch.stack([torch.stack([_residues(qp, n, gen) for _ in range(2)]) for _ in range(ctx.dnum)])
+            tuned_levels = [ctx.L] if scheme == "bfv" else (levels or range(1, ctx.L + 1))
             prev = None
             for nl in range(1, ctx.L + 1):
-                if nl in levels:
+                if nl in tuned_levels:
                     a = torch.stack([_residues(ch["q"][:nl], n, gen) for _ in range(2)])
                     b = torch.stack([_residues(ch["q"][:nl], n, gen) for _ in range(2)])
                     g = ctx.galois_element(3)
 
                     def step():
                         m = ctx.hmult_relin(a, b, key)
-                        if nl > 1:
+                        if nl > 1 and scheme == "ckks":
                             ctx.rescale(m)
+                        elif nl > 1 and scheme == "bgv":
+                            ctx.modswitch(m)
                         ctx.rotate(a, g, key)
 
                     res = tune_level(ctx, nl, step, reps=reps, use_cache=False)
                     prev = res["setting"] if res["setting"] != res["default"] else None
                     print("tuned %s N=2^%d limbs=%d: %s (%.4f -> %.4f ms)" % (
                         wname, ln, nl, res["setting"], res["default_ms"], res["tuned_ms"]), flush=True)
-                if prev is not None:
-                    table[shipped_key(ln, w["alpha"], len(ch["p"]), nl)] = prev
+                if prev is not None and (levels is not None or nl in tuned_levels):
+                    table[shipped_key(scheme, ln, w["alpha"], len(ch["p"]), nl)] = prev
             ctx.close()
     if saved is None:
         del os.environ["RF_NO_SHIPPED_TUNING"]
@@ -313,7 +327,7 @@ def write_table(out: str, log_ns=(14, 15, 16), levels=(4, 8, 12, 16, 20, 24), re
                 doc = json.load(f)
         except (OSError, ValueError):
             doc = {}
-    doc[dkey] = table
+    doc.setdefault(dkey, {}).update(table)
     with open(out, "w") as f:
         json.dump(doc, f, indent=1, sort_keys=True)
     return table
@@ -327,6 +341,8 @@ def _residues(moduli, n, gen):
 if __name__ == "__main__":
     import sys
     if len(sys.argv) >= 2 and sys.argv[1] == "--write-table":
-        print(json.dumps(write_table(sys.argv[2] if len(sys.argv) > 2 else SHIPPED), indent=1))
+        names = sys.argv[3:]
+        wl = tuple(w for w in TABLE_WORKLOADS if not names or w[0] in names)
+        print(json.dumps(write_table(sys.argv[2] if len(sys.argv) > 2 else SHIPPED, wl), indent=1))
     else:
-        raise SystemExit("usage: python -m paper_2503_22227_amd.autotune --write-table [path]")
+        raise SystemExit("usage: python -m paper_2503_22227_amd.autotune --write-table [path [workload ...]]")

@@ -91,8 +91,8 @@ def test_level_candidates_are_the_library_values():
 def test_shipped_table_applies_matching_entries(tmp_path, monkeypatch):
     monkeypatch.setattr(A, "device_key", lambda device=None: "fake-gpu|256cu")
     monkeypatch.delenv("RF_NO_SHIPPED_TUNING", raising=False)
-    table = {"fake-gpu|256cu": {A.shipped_key(15, 8, 1, 2): dict(A.DEFAULT_LEVEL, modup_chunk=4)},
-             "other|304cu": {A.shipped_key(15, 8, 1, 1): dict(A.DEFAULT_LEVEL, modup_chunk=16)}}
+    table = {"fake-gpu|256cu": {A.shipped_key("ckks", 15, 8, 1, 2): dict(A.DEFAULT_LEVEL, modup_chunk=4)},
+             "other|304cu": {A.shipped_key("ckks", 15, 8, 1, 1): dict(A.DEFAULT_LEVEL, modup_chunk=16)}}
     path = tmp_path / "t.json"
     path.write_text(json.dumps(table))
     ctx = FakeCtx()
