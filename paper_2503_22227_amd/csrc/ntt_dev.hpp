@@ -124,22 +124,49 @@ __device__ __forceinline__ uint32_t row_or_natural(uint32_t tw_base, int s, int 
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
 
+// Where a round takes its twiddles: loads from the table as each stage needs
+// them (kTwLoad); kTwPrefetch only loads the pairs every round of the pass will
+// use into a register array (no butterflies, no LDS access), so that all of
+// them are in flight together with the tile's own loads; kTwCached then takes
+// them from that array.  A pass with few residues per thread (the small-tile
+// passes) otherwise waits one table latency after every round's barrier.
+constexpr int kTwLoad = 0, kTwPrefetch = 1, kTwCached = 2;
+
+// Register slots of the prefetched twiddles of a pass of S_LOG stages with E
+// residues per thread: round r, group gi, stage c, element e at
+// SLOT0(r) + (gi C + c) 2^C + e, each round taking E C slots.  Slots a round
+// does not use are never written or read.
+__host__ __device__ constexpr int tw_slots(int S_LOG, int E) { return E * S_LOG; }
+
 // One round of C butterfly stages of a size-2^S_LOG sub-transform held in LDS
 // (element p of sub-transform u at lds[p * ldu + u]).  Thread t of the
 // sub-transform owns E residues (kElems unless stated): E / 2^C groups of 2^C
 // residues spaced by the round's smallest distance 2^DL.
 //
 // IN_REGS / OUT_REGS: the round takes its residues from regs / leaves them in
-// regs (group gi, element e at regs[gi * 2^C + e]) instead of LDS.
+// regs (group gi, element e at regs[gi * 2^C + e]) instead of LDS.  TW, SLOT0,
+// cache: the twiddle source above.
 template <int S_LOG, int ST0, int C, bool FWD, bool SCALE_LAST, int ROW_A, bool IN_REGS = false,
-          bool OUT_REGS = false, bool LZ = false, int E = kElems>
+          bool OUT_REGS = false, bool LZ = false, int E = kElems, int TW = kTwLoad, int SLOT0 = 0>
 __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, uint32_t tw_base,
                                           const TwPair *__restrict__ tw, const PrimeConst &pc,
-                                          uint64_t *regs = nullptr) {
+                                          uint64_t *regs = nullptr, TwPair *cache = nullptr) {
     constexpr int G = 1 << C;
     constexpr int NG = E / G;
     constexpr int DL = FWD ? (S_LOG - ST0 - C) : ST0;
+    constexpr bool RUN = TW != kTwPrefetch;
     const uint64_t q = pc.q, q2 = 2 * q, nq = 0 - q;
+    // twiddle (slot, table index): fetched, loaded or taken from the cache
+    auto twiddle = [&](int slot, uint32_t idx) -> TwPair {
+        if constexpr (TW == kTwPrefetch) {
+            cache[slot] = tw[idx];
+            return TwPair{};
+        } else if constexpr (TW == kTwCached) {
+            return cache[slot];
+        } else {
+            return tw[idx];
+        }
+    };
 #pragma unroll
     for (int gi = 0; gi < NG; ++gi) {
         const int grp = t * NG + gi;
@@ -147,8 +174,10 @@ __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, 
         const int hi = grp >> DL;
         const int base = (hi << (DL + C)) + lo;
         uint64_t v[G];
+        if constexpr (RUN) {
 #pragma unroll
-        for (int e = 0; e < G; ++e) v[e] = IN_REGS ? regs[gi * G + e] : lds[(base + (e << DL)) * ldu + u];
+            for (int e = 0; e < G; ++e) v[e] = IN_REGS ? regs[gi * G + e] : lds[(base + (e << DL)) * ldu + u];
+        }
         if constexpr (FWD) {
 #pragma unroll
             for (int c = 0; c < C; ++c) {
@@ -161,8 +190,9 @@ __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, 
                     // index depends on e only (uniform across the sub-transform)
                     const uint32_t j = ST0 == 0 ? (uint32_t)(e >> (C - c))
                                                 : (uint32_t)((base + (e << DL)) >> (S_LOG - st));
-                    const TwPair w = tw[row_or_natural<S_LOG, ROW_A, true>(tw_base, st, t, j)];
-                    ct_bfly<LZ>(v[e], v[e + h], w.w, w.wp, nq, q2);
+                    const TwPair w = twiddle(SLOT0 + (gi * C + c) * G + e,
+                                             row_or_natural<S_LOG, ROW_A, true>(tw_base, st, t, j));
+                    if constexpr (RUN) ct_bfly<LZ>(v[e], v[e + h], w.w, w.wp, nq, q2);
                 }
             }
         } else {
@@ -175,48 +205,58 @@ __device__ __forceinline__ void ntt_round(uint64_t *lds, int ldu, int u, int t, 
                 for (int e = 0; e < G; ++e) {
                     if (e & h) continue;
                     if (SCALE_LAST && us == S_LOG - 1) {
-                        gs_bfly_last(v[e], v[e + h], pc, off);
+                        if constexpr (RUN) gs_bfly_last(v[e], v[e + h], pc, off);
                     } else {
                         // in the last round every group starts below 2^DL: index from e only
                         const uint32_t lo_part = ST0 + C == S_LOG ? (uint32_t)(e >> (c + 1))
                                                                   : (uint32_t)((base + (e << DL)) >> (us + 1));
-                        const TwPair w = tw[row_or_natural<S_LOG, ROW_A, false>(tw_base, S_LOG - us - 1, t, lo_part)];
-                        gs_bfly<LZ>(v[e], v[e + h], w.w, w.wp, nq, q2, off);
+                        const TwPair w = twiddle(SLOT0 + (gi * C + c) * G + e,
+                                                 row_or_natural<S_LOG, ROW_A, false>(tw_base, S_LOG - us - 1, t,
+                                                                                     lo_part));
+                        if constexpr (RUN) gs_bfly<LZ>(v[e], v[e + h], w.w, w.wp, nq, q2, off);
                     }
                 }
             }
         }
+        if constexpr (RUN) {
 #pragma unroll
-        for (int e = 0; e < G; ++e) {
-            if constexpr (OUT_REGS) regs[gi * G + e] = v[e];
-            else lds[(base + (e << DL)) * ldu + u] = v[e];
+            for (int e = 0; e < G; ++e) {
+                if constexpr (OUT_REGS) regs[gi * G + e] = v[e];
+                else lds[(base + (e << DL)) * ldu + u] = v[e];
+            }
         }
     }
 }
 
 // Rounds of a size-2^S_LOG sub-transform from stage ST0 on: radix-E rounds,
-// the last one shorter when log2(E) does not divide S_LOG.
-template <int S_LOG, int ST0, bool FWD, bool SCALE_LAST, int ROW_A, bool LZ = false, int E = kElems>
+// the last one shorter when log2(E) does not divide S_LOG.  With kTwPrefetch
+// only the twiddle loads run (no barriers).
+template <int S_LOG, int ST0, bool FWD, bool SCALE_LAST, int ROW_A, bool LZ = false, int E = kElems,
+          int TW = kTwLoad, int SLOT0 = 0>
 __device__ __forceinline__ void ntt_rounds_from(uint64_t *lds, int ldu, int u, int t, uint32_t tw_base,
-                                                const TwPair *__restrict__ tw, const PrimeConst &pc) {
+                                                const TwPair *__restrict__ tw, const PrimeConst &pc,
+                                                TwPair *cache = nullptr) {
     constexpr int CL = ilog2(E);
     constexpr int C = (S_LOG - ST0) < CL ? (S_LOG - ST0) : CL;
     constexpr bool LAST = ST0 + C == S_LOG;
-    ntt_round<S_LOG, ST0, C, FWD, SCALE_LAST && LAST, ROW_A, false, false, LZ, E>(lds, ldu, u, t, tw_base, tw, pc);
-    __syncthreads();
+    ntt_round<S_LOG, ST0, C, FWD, SCALE_LAST && LAST, ROW_A, false, false, LZ, E, TW, SLOT0>(
+        lds, ldu, u, t, tw_base, tw, pc, nullptr, cache);
+    if constexpr (TW != kTwPrefetch) __syncthreads();
     if constexpr (!LAST)
-        ntt_rounds_from<S_LOG, ST0 + C, FWD, SCALE_LAST, ROW_A, LZ, E>(lds, ldu, u, t, tw_base, tw, pc);
+        ntt_rounds_from<S_LOG, ST0 + C, FWD, SCALE_LAST, ROW_A, LZ, E, TW, SLOT0 + E * C>(lds, ldu, u, t, tw_base,
+                                                                                        tw, pc, cache);
 }
 
 // ROW_A: 0 for the natural twiddle table; A for a row pass reading the row table
 // (which needs exactly two rounds of kElems residues: S_LOG in (kElemsLog, 2 kElemsLog]).
-template <int S_LOG, bool FWD, bool SCALE_LAST, int ROW_A = 0, bool LZ = false, int E = kElems>
+template <int S_LOG, bool FWD, bool SCALE_LAST, int ROW_A = 0, bool LZ = false, int E = kElems, int TW = kTwLoad>
 __device__ __forceinline__ void ntt_rounds(uint64_t *lds, int ldu, int u, int t, uint32_t tw_base,
-                                           const TwPair *__restrict__ tw, const PrimeConst &pc) {
+                                           const TwPair *__restrict__ tw, const PrimeConst &pc,
+                                           TwPair *cache = nullptr) {
     static_assert(S_LOG >= 5 && S_LOG <= 12, "sub-transform size");
     static_assert(ROW_A == 0 || (E == kElems && S_LOG > kElemsLog && S_LOG <= 2 * kElemsLog),
                   "row table: two rounds of kElems residues");
-    ntt_rounds_from<S_LOG, 0, FWD, SCALE_LAST, ROW_A, LZ, E>(lds, ldu, u, t, tw_base, tw, pc);
+    ntt_rounds_from<S_LOG, 0, FWD, SCALE_LAST, ROW_A, LZ, E, TW, 0>(lds, ldu, u, t, tw_base, tw, pc, cache);
 }
 
 // Plain load of a pass (no prologue).
@@ -248,13 +288,21 @@ __device__ __forceinline__ void ntt_cols_small_pro(uint64_t *lds, const Pro &pro
     constexpr int U = TILE >> A, LDU = U + 1, NT = TILE / E;
     static_assert(U >= 1 && NT >= 64, "small column tile");
     const int col0 = tile * U;
+    uint64_t x[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int idx = threadIdx.x + r * NT;
-        lds[(idx / U) * LDU + idx % U] = pro(((size_t)(idx / U) << B) + col0 + idx % U);
+        x[r] = pro(((size_t)(idx / U) << B) + col0 + idx % U);
+    }
+    TwPair twc[tw_slots(A, E)];
+    ntt_rounds<A, FWD, !FWD, 0, false, E, kTwPrefetch>(lds, LDU, threadIdx.x % U, threadIdx.x / U, 1u, tw, pc, twc);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int idx = threadIdx.x + r * NT;
+        lds[(idx / U) * LDU + idx % U] = x[r];
     }
     __syncthreads();
-    ntt_rounds<A, FWD, !FWD, 0, false, E>(lds, LDU, threadIdx.x % U, threadIdx.x / U, 1u, tw, pc);
+    ntt_rounds<A, FWD, !FWD, 0, false, E, kTwCached>(lds, LDU, threadIdx.x % U, threadIdx.x / U, 1u, tw, pc, twc);
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int idx = threadIdx.x + r * NT;
@@ -278,14 +326,24 @@ __device__ __forceinline__ void ntt_rows_small_pe(uint64_t *lds, const Pro &pro,
     constexpr int S = 1 << B, U = TILE >> B, LDU = U + 1, NT = TILE / E;
     static_assert(U >= 1 && NT >= 64, "small row tile");
     const int row0 = tile * U;
+    uint64_t x[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int idx = threadIdx.x + r * NT;
-        lds[(idx & (S - 1)) * LDU + (idx >> B)] = pro(((size_t)(row0 + (idx >> B)) << B) + (idx & (S - 1)));
+        x[r] = pro(((size_t)(row0 + (idx >> B)) << B) + (idx & (S - 1)));
+    }
+    const int u = threadIdx.x % U;
+    TwPair twc[tw_slots(B, E)];
+    ntt_rounds<B, FWD, false, 0, false, E, kTwPrefetch>(lds, LDU, u, threadIdx.x / U, (1u << A) + row0 + u, tw, pc,
+                                                        twc);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int idx = threadIdx.x + r * NT;
+        lds[(idx & (S - 1)) * LDU + (idx >> B)] = x[r];
     }
     __syncthreads();
-    const int u = threadIdx.x % U;
-    ntt_rounds<B, FWD, false, 0, false, E>(lds, LDU, u, threadIdx.x / U, (1u << A) + row0 + u, tw, pc);
+    ntt_rounds<B, FWD, false, 0, false, E, kTwCached>(lds, LDU, u, threadIdx.x / U, (1u << A) + row0 + u, tw, pc,
+                                                      twc);
     const uint64_t q2 = 2 * pc.q;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
