@@ -56,7 +56,7 @@ struct DeviceGuard {
 };
 
 NttBatch batch(const uint64_t *in, uint64_t *out, uint64_t in_stride, uint64_t out_stride, uint32_t per_poly,
-               uint32_t n_polys, uint32_t prime_base, const uint8_t *pmap) {
+               uint32_t n_polys, uint32_t prime_base, const uint32_t *pmap) {
     NttBatch b;
     b.in = in;
     b.out = out;

@@ -388,7 +388,7 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
     }
 
     // ModUp extension prime maps per level nl: for each digit, the basis Q_l u P minus the digit
-    std::vector<uint8_t> pm;
+    std::vector<uint32_t> pm;
     c->modup_levels.assign(c->L + 1, ModupLevel{0, 0, 0});
     c->tuning.assign(c->L + 1, kDefaultTuning);
     for (uint32_t nl = 1; nl <= c->L; ++nl) {
@@ -398,8 +398,8 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
         for (uint32_t j = 0; j < lv.dnum; ++j) {
             uint32_t start = j * A, s = std::min(A, nl - start);
             for (uint32_t g = 0; g < nl; ++g)
-                if (g < start || g >= start + s) pm.push_back((uint8_t)g);
-            for (uint32_t g = 0; g < c->K; ++g) pm.push_back((uint8_t)(c->L + g));
+                if (g < start || g >= start + s) pm.push_back(g);
+            for (uint32_t g = 0; g < c->K; ++g) pm.push_back(c->L + g);
         }
         lv.ext_limbs = (uint32_t)pm.size() - lv.pmap_off;
         c->modup_levels[nl] = lv;
@@ -407,7 +407,7 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
 
     // BFV: BEHZ tables and the prime map of q u B_sk
     std::vector<uint64_t> bz;
-    std::vector<uint8_t> pmqb;
+    std::vector<uint32_t> pmqb;
     if (c->scheme == RF_BFV) {
         const uint32_t L = c->L, nb = c->nb, KB = c->L + c->K;  // index of b_0 in `primes`
         BehzLayout &o = c->behz;
@@ -508,8 +508,8 @@ extern "C" int rf_ctx_create(const rf_params *p, int device, rf_ctx **out) {
             bz[o.m_q + 2 * i] = v;
             bz[o.m_q + 2 * i + 1] = shoup_companion(v, qi);
         }
-        for (uint32_t i = 0; i < L; ++i) pmqb.push_back((uint8_t)i);
-        for (uint32_t m = 0; m <= nb; ++m) pmqb.push_back((uint8_t)(KB + m));
+        for (uint32_t i = 0; i < L; ++i) pmqb.push_back(i);
+        for (uint32_t m = 0; m <= nb; ++m) pmqb.push_back(KB + m);
     }
 
     // Client-side tables.  [P]_{p_g} for the P [i in D_j] s' term of key

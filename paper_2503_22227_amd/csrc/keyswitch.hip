@@ -23,7 +23,7 @@ namespace rf {
 __global__ __launch_bounds__(kEw) void tensor_kernel(const uint64_t *__restrict__ a, const uint64_t *__restrict__ b,
                                                      uint64_t *__restrict__ d01, uint64_t *__restrict__ d2,
                                                      const PrimeConst *__restrict__ pcs, uint32_t log_n, uint32_t nl,
-                                                     const uint8_t *pmap) {
+                                                     const uint32_t *pmap) {
     tensor_unit(a, b, d01, d2, pcs, log_n, nl, pmap, blockIdx.x, blockIdx.y);
 }
 
@@ -122,12 +122,12 @@ int launch_tensor(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_
                   hipStream_t s) {
     ProfScope prof("tensor", s);
     hipLaunchKernelGGL(tensor_kernel, ew_grid(c, nl), dim3(kEw), 0, s, a, b, d01, d2, c->d_pc, c->log_n, nl,
-                       (const uint8_t *)nullptr);
+                       (const uint32_t *)nullptr);
     return check_launch("tensor");
 }
 
 int launch_tensor_map(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *d01, uint64_t *d2,
-                      uint32_t nl, const uint8_t *pmap, hipStream_t s) {
+                      uint32_t nl, const uint32_t *pmap, hipStream_t s) {
     ProfScope prof("tensor", s);
     hipLaunchKernelGGL(tensor_kernel, ew_grid(c, nl), dim3(kEw), 0, s, a, b, d01, d2, c->d_pc, c->log_n, nl, pmap);
     return check_launch("tensor");

@@ -16,7 +16,7 @@ constexpr int kEw = 256;  // threads per block of the element-wise kernels
 // d0 = a0 b0, d1 = a0 b1 + a1 b0 (into d01 = [2][nl][N]), d2 = a1 b1 (into d2 = [nl][N]).
 __device__ __forceinline__ void tensor_unit(const uint64_t *__restrict__ a, const uint64_t *__restrict__ b,
                                                      uint64_t *__restrict__ d01, uint64_t *__restrict__ d2,
-                                                     const PrimeConst *__restrict__ pcs, uint32_t log_n, uint32_t nl, const uint8_t *pmap, uint32_t gx, uint32_t gy) {
+                                                     const PrimeConst *__restrict__ pcs, uint32_t log_n, uint32_t nl, const uint32_t *pmap, uint32_t gx, uint32_t gy) {
     const uint32_t i = gy;
     const size_t n = (size_t)gx * kEw + threadIdx.x;
     const size_t poly = (size_t)nl << log_n;

@@ -17,10 +17,14 @@ struct LimbView {
 // are launched back to back, 16 workgroups apart at N = 2^16, which places them
 // on the same XCD (workgroups are dealt to the 8 XCDs in turn), so the second
 // reads the twiddles from that XCD's L2.
+//
+// The limb index is uniform across the workgroup: held in a scalar register, so
+// the prime map and the prime's constants are read with scalar loads instead of
+// a vector load whose latency would delay the tile's own loads.
 __device__ __forceinline__ LimbView limb_view(const NttBatch &b, int log_n, uint32_t limb) {
-    const uint32_t li = limb / b.n_polys, poly = limb - li * b.n_polys;
+    const uint32_t li = __builtin_amdgcn_readfirstlane(limb / b.n_polys), poly = limb - li * b.n_polys;
     LimbView v;
-    v.g = b.pmap ? (uint32_t)b.pmap[li] : b.prime_base + li;
+    v.g = b.pmap ? b.pmap[li] : b.prime_base + li;
     v.in = b.in + (size_t)poly * b.in_poly_stride + ((size_t)li << log_n);
     v.out = b.out + (size_t)poly * b.out_poly_stride + ((size_t)li << log_n);
     return v;

@@ -40,7 +40,7 @@ struct NttBatch {
     uint32_t per_poly;
     uint32_t n_polys;
     uint32_t prime_base;
-    const uint8_t *pmap;       // device array [per_poly] or nullptr
+    const uint32_t *pmap;      // device array [per_poly] or nullptr
 };
 
 // Offsets (uint64 entries) of the BEHZ tables of a BFV context (L Q-primes,
@@ -101,11 +101,11 @@ struct rf_ctx {
     uint64_t *d_moddown = nullptr;         // ModDown constants
     uint64_t *d_moddown_t = nullptr;       // ModDown constants keeping the message mod t (BGV)
     uint64_t *d_rescale = nullptr;         // rescale constants
-    uint8_t *d_pmaps = nullptr;            // ModUp extension prime maps for every level
+    uint32_t *d_pmaps = nullptr;           // ModUp extension prime maps for every level
     // BFV: auxiliary base B and m_sk follow the special primes in `primes`
     uint32_t nb = 0;
     uint64_t *d_behz = nullptr;            // BEHZ tables (rf::BehzLayout)
-    uint8_t *d_pmap_qb = nullptr;          // prime indices of q u B_sk
+    uint32_t *d_pmap_qb = nullptr;         // prime indices of q u B_sk
     rf::BehzLayout behz{};
     size_t modup_stride = 0;               // uint64 entries per (digit, size) block
     // client side (key generation, encryption, decryption, encode / decode)
@@ -241,7 +241,7 @@ int launch_behz_extend(const rf_ctx *c, const uint64_t *a, const uint64_t *b, ui
 int launch_behz_floor_sk(const rf_ctx *c, const uint64_t *tens, uint64_t *f, uint64_t *out01, uint64_t *out2,
                          hipStream_t s);
 int launch_tensor_map(const rf_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *d01, uint64_t *d2,
-                      uint32_t nl, const uint8_t *pmap, hipStream_t s);
+                      uint32_t nl, const uint32_t *pmap, hipStream_t s);
 int launch_automorphism(const rf_ctx *c, const uint64_t *in, uint64_t *out, uint32_t galois,
                         uint32_t nl, uint32_t n_polys, hipStream_t s);
 
