@@ -120,12 +120,19 @@ def time_fn(fn, reps: int, repeats: int = 3) -> float:
     return best
 
 
-def _descend(knobs: dict, apply, measure, min_gain: float, log=None, rounds: int = 2):
+def _descend(knobs: dict, apply, measure, min_gain: float, log=None, rounds: int = 2, confirm: int = 2):
     """Coordinate descent over ``knobs`` ({name: candidates}) starting from the
-    setting ``apply`` was last given; returns (setting, best_ms, trials)."""
+    setting ``apply`` was last given; returns (setting, best_ms, trials,
+    start_ms).  The first measurement is a discarded warm-up (clocks, caches,
+    first launches), and a setting that differs from the start is kept only if
+    ``confirm`` alternating re-measurements of both (best of each) still show
+    the gain; best_ms and start_ms are then those re-measured times."""
     setting = dict(apply.current)
+    start = dict(setting)
     apply(setting)
+    measure()
     best = measure()
+    start_ms = best
     trials = [(dict(setting), best)]
     for _ in range(rounds):
         moved = False
@@ -144,8 +151,20 @@ def _descend(knobs: dict, apply, measure, min_gain: float, log=None, rounds: int
                     best, setting, moved = ms, trial, True
         if not moved:
             break
+    if setting != start and confirm > 0:
+        t_start, t_best = [], []
+        for _ in range(confirm):
+            apply(start)
+            t_start.append(measure())
+            apply(setting)
+            t_best.append(measure())
+        start_ms, best = min(t_start), min(t_best)
+        if log:
+            log("autotune confirm: start %.4f ms, chosen %.4f ms" % (start_ms, best))
+        if not best < start_ms * (1.0 - min_gain):
+            setting, best = start, start_ms
     apply(setting)
-    return setting, best, trials
+    return setting, best, trials, start_ms
 
 
 class _LevelApply:
@@ -179,8 +198,8 @@ def tune_level(ctx, nlimbs: int, workload, reps: int = 10, min_gain: float = 0.0
         return dict(hit, cached=True)
     ap = _LevelApply(ctx, nlimbs)
     ap(DEFAULT_LEVEL)
-    setting, best, trials = _descend(LEVEL_CANDIDATES, ap, lambda: time_fn(workload, reps), min_gain, log)
-    default_ms = trials[0][1]
+    setting, best, trials, default_ms = _descend(LEVEL_CANDIDATES, ap, lambda: time_fn(workload, reps), min_gain,
+                                                 log)
     res = {"setting": setting, "default": dict(DEFAULT_LEVEL), "default_ms": default_ms, "tuned_ms": best,
            "trials": len(trials)}
     if use_cache:
@@ -222,8 +241,8 @@ def tune(plan, shape, reps: int = 3, use_cache: bool = True, min_gain: float = 0
     knobs = {cls: CANDIDATES for cls in CLASSES}
     knobs["modup_chunk"] = MODUP_CHUNKS
     ap = _BatchApply(plan)
-    setting, best, trials = _descend(knobs, ap, lambda: time_fn(lambda: plan.run(graph=True), reps, repeats=2),
-                                     min_gain, log, rounds=1)
+    setting, best, trials, _ = _descend(knobs, ap, lambda: time_fn(lambda: plan.run(graph=True), reps, repeats=2),
+                                        min_gain, log, rounds=1)
     if use_cache:
         cache = _load_cache(path)
         cache.setdefault(dkey, {})[key] = {"setting": setting, "ms": best, "trials": len(trials)}

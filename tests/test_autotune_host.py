@@ -24,9 +24,9 @@ def test_descent_finds_the_best_of_a_separable_cost():
     def measure():
         return cost["x"][ap.current["x"]] * cost["y"][ap.current["y"]]
 
-    setting, best, trials = A._descend(knobs, ap, measure, min_gain=0.01)
+    setting, best, trials, start_ms = A._descend(knobs, ap, measure, min_gain=0.01)
     assert setting == {"x": 1, "y": 4}
-    assert abs(best - 0.7 * 0.95) < 1e-12
+    assert abs(best - 0.7 * 0.95) < 1e-12 and start_ms == 1.0
     assert ap.current == setting
     tried = {(t["x"], t["y"]) for t, _ in trials}
     assert {(x, 8) for x in knobs["x"]} <= tried      # every x tried from the start
@@ -36,7 +36,7 @@ def test_descent_finds_the_best_of_a_separable_cost():
 def test_descent_ignores_gains_inside_the_margin():
     knobs = {"x": (0, 1)}
     ap = FakeApply({"x": 0})
-    setting, best, _ = A._descend(knobs, ap, lambda: 1.0 if ap.current["x"] == 0 else 0.995, min_gain=0.01)
+    setting, best, _, _ = A._descend(knobs, ap, lambda: 1.0 if ap.current["x"] == 0 else 0.995, min_gain=0.01)
     assert setting == {"x": 0} and best == 1.0
 
 
@@ -103,3 +103,25 @@ def test_shipped_table_applies_matching_entries(tmp_path, monkeypatch):
     ctx2 = FakeCtx()
     ctx2.L, ctx2.k = 2, 1
     assert A.apply_shipped(ctx2, str(path)) == 0 and ctx2.levels == {}
+
+
+def test_descent_discards_the_warm_up_and_confirms_a_change():
+    """A first measurement inflated by warm-up cannot make the start look slow,
+    and a change that a single noisy measurement favoured is dropped when the
+    alternating re-measurements do not confirm it."""
+    knobs = {"x": (0, 1)}
+    ap = FakeApply({"x": 0})
+    calls = {"n": 0}
+
+    def measure():
+        calls["n"] += 1
+        if calls["n"] == 1:
+            return 5.0                     # warm-up
+        if calls["n"] == 3:
+            return 0.9                     # one lucky measurement of x = 1
+        return 1.0                         # both settings really cost the same
+
+    setting, best, trials, start_ms = A._descend(knobs, ap, measure, min_gain=0.01)
+    assert trials[0][1] == 1.0             # the warm-up was not recorded
+    assert setting == {"x": 0} and best == start_ms == 1.0
+    assert ap.current == {"x": 0}
