@@ -269,6 +269,7 @@ struct LoadPro {
 // an element-wise step that follows the transform (the ModDown or rescale
 // tail) runs in the pass's epilogue instead of another kernel.
 struct StoreEpi {
+    static constexpr bool kPrefetch = false;
     uint64_t *out;
     __device__ __forceinline__ void operator()(size_t idx, uint64_t x) const { out[idx] = x; }
 };
@@ -332,6 +333,17 @@ __device__ __forceinline__ void ntt_rows_small_pe(uint64_t *lds, const Pro &pro,
         const int idx = threadIdx.x + r * NT;
         x[r] = pro(((size_t)(row0 + (idx >> B)) << B) + (idx & (S - 1)));
     }
+    // an epilogue that reads an operand of its own (the ModDown and rescale
+    // tails) has it loaded here, with the tile, instead of after the last
+    // barrier: a few registers in a pass of E residues per thread
+    uint64_t opnd[E];
+    if constexpr (Epi::kPrefetch) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int idx = threadIdx.x + r * NT;
+            opnd[r] = epi.operand(((size_t)(row0 + (idx >> B)) << B) + (idx & (S - 1)));
+        }
+    }
     const int u = threadIdx.x % U;
     TwPair twc[tw_slots(B, E)];
     ntt_rounds<B, FWD, false, 0, false, E, kTwPrefetch>(lds, LDU, u, threadIdx.x / U, (1u << A) + row0 + u, tw, pc,
@@ -349,7 +361,10 @@ __device__ __forceinline__ void ntt_rows_small_pe(uint64_t *lds, const Pro &pro,
     for (int r = 0; r < E; ++r) {
         const int idx = threadIdx.x + r * NT;
         const uint64_t x = lds[(idx & (S - 1)) * LDU + (idx >> B)];
-        epi(((size_t)(row0 + (idx >> B)) << B) + (idx & (S - 1)), FWD ? csub(csub(x, q2), pc.q) : x);
+        const size_t gi = ((size_t)(row0 + (idx >> B)) << B) + (idx & (S - 1));
+        const uint64_t v = FWD ? csub(csub(x, q2), pc.q) : x;
+        if constexpr (Epi::kPrefetch) epi.finish(gi, v, opnd[r]);
+        else epi(gi, v);
     }
     __syncthreads();
 }
@@ -612,6 +627,7 @@ struct GatherPro {
 // ModDown tail as the epilogue of the last forward pass of NTT(conv):
 // out = (ip - NTT(conv)) * P^-1 mod q (+ add).  add may alias out.
 struct ModdownTailEpi {
+    static constexpr bool kPrefetch = false;
     const uint64_t *ip;
     const uint64_t *add;
     uint64_t *out;
@@ -626,22 +642,29 @@ struct ModdownTailEpi {
 // The same tail when the inner product already left ip' = ip P^-1 + add:
 // out = ip' - NTT(conv) P^-1 mod q (one stream read besides the transform).
 struct ModdownFoldEpi {
+    // the small-tile row pass loads ip with its tile (operand), then finish
+    static constexpr bool kPrefetch = true;
     const uint64_t *ip;
     uint64_t *out;
     uint64_t pinv, pinv_p, q;
-    __device__ __forceinline__ void operator()(size_t idx, uint64_t conv) const {
-        out[idx] = submod(ip[idx], shoup(conv, pinv, pinv_p, q), q);
+    __device__ __forceinline__ void operator()(size_t idx, uint64_t conv) const { finish(idx, conv, ip[idx]); }
+    __device__ __forceinline__ uint64_t operand(size_t idx) const { return ip[idx]; }
+    __device__ __forceinline__ void finish(size_t idx, uint64_t conv, uint64_t ipv) const {
+        out[idx] = submod(ipv, shoup(conv, pinv, pinv_p, q), q);
     }
 };
 
 // Rescale / modulus-switch tail as the epilogue of the NTT of the lifted limb:
 // out = (in - NTT(lift)) * q_l^-1 mod q.
 struct RescaleTailEpi {
+    static constexpr bool kPrefetch = true;  // as ModdownFoldEpi
     const uint64_t *in;
     uint64_t *out;
     uint64_t qlinv, qlinv_p, q;
-    __device__ __forceinline__ void operator()(size_t idx, uint64_t lift) const {
-        out[idx] = shoup(submod(in[idx], lift, q), qlinv, qlinv_p, q);
+    __device__ __forceinline__ void operator()(size_t idx, uint64_t lift) const { finish(idx, lift, in[idx]); }
+    __device__ __forceinline__ uint64_t operand(size_t idx) const { return in[idx]; }
+    __device__ __forceinline__ void finish(size_t idx, uint64_t lift, uint64_t inv) const {
+        out[idx] = shoup(submod(inv, lift, q), qlinv, qlinv_p, q);
     }
 };
 
