@@ -289,18 +289,18 @@ __device__ __forceinline__ void ntt_cols_small_pro(uint64_t *lds, const Pro &pro
     constexpr int U = TILE >> A, LDU = U + 1, NT = TILE / E;
     static_assert(U >= 1 && NT >= 64, "small column tile");
     const int col0 = tile * U;
-    uint64_t x[E];
+    uint64_t vin[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int idx = threadIdx.x + r * NT;
-        x[r] = pro(((size_t)(idx / U) << B) + col0 + idx % U);
+        vin[r] = pro(((size_t)(idx / U) << B) + col0 + idx % U);
     }
     TwPair twc[tw_slots(A, E)];
     ntt_rounds<A, FWD, !FWD, 0, false, E, kTwPrefetch>(lds, LDU, threadIdx.x % U, threadIdx.x / U, 1u, tw, pc, twc);
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int idx = threadIdx.x + r * NT;
-        lds[(idx / U) * LDU + idx % U] = x[r];
+        lds[(idx / U) * LDU + idx % U] = vin[r];
     }
     __syncthreads();
     ntt_rounds<A, FWD, !FWD, 0, false, E, kTwCached>(lds, LDU, threadIdx.x % U, threadIdx.x / U, 1u, tw, pc, twc);
@@ -319,19 +319,20 @@ __device__ __forceinline__ void ntt_cols_small(uint64_t *lds, const uint64_t *in
     ntt_cols_small_pro<A, B, FWD, TILE, E>(lds, LoadPro{in}, out, tw, pc, tile);
 }
 
-// The result for limb index idx goes through epi(idx, value) (forward: in
-// [0, q); inverse: lazy in [0, 2q)).
+// The result for limb index idx (forward: in [0, q); inverse: lazy in [0, 2q))
+// goes through epi(idx, value), or, when Epi::kPrefetch, through
+// epi.finish(idx, value, epi.operand(idx)) with the operand loaded at the start.
 template <int A, int B, bool FWD, int TILE, int E, typename Pro, typename Epi>
 __device__ __forceinline__ void ntt_rows_small_pe(uint64_t *lds, const Pro &pro, const TwPair *__restrict__ tw,
                                                   const PrimeConst &pc, int tile, const Epi &epi) {
     constexpr int S = 1 << B, U = TILE >> B, LDU = U + 1, NT = TILE / E;
     static_assert(U >= 1 && NT >= 64, "small row tile");
     const int row0 = tile * U;
-    uint64_t x[E];
+    uint64_t vin[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int idx = threadIdx.x + r * NT;
-        x[r] = pro(((size_t)(row0 + (idx >> B)) << B) + (idx & (S - 1)));
+        vin[r] = pro(((size_t)(row0 + (idx >> B)) << B) + (idx & (S - 1)));
     }
     // an epilogue that reads an operand of its own (the ModDown and rescale
     // tails) has it loaded here, with the tile, instead of after the last
@@ -351,7 +352,7 @@ __device__ __forceinline__ void ntt_rows_small_pe(uint64_t *lds, const Pro &pro,
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int idx = threadIdx.x + r * NT;
-        lds[(idx & (S - 1)) * LDU + (idx >> B)] = x[r];
+        lds[(idx & (S - 1)) * LDU + (idx >> B)] = vin[r];
     }
     __syncthreads();
     ntt_rounds<B, FWD, false, 0, false, E, kTwCached>(lds, LDU, u, threadIdx.x / U, (1u << A) + row0 + u, tw, pc,
