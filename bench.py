@@ -79,8 +79,10 @@ def copy_calibration():
 
 def ntt_microbench(reps: int):
     """Forward then inverse NTT of 28, 56, 112 and 224 limbs (1, 2, 4, 8 polynomials over the
-    28-prime chain) at N=2^16, ``reps`` times each; per-kernel HIP-event averages and the
-    VALU fraction at 24 ops per butterfly."""
+    28-prime chain) at N=2^16, ``reps`` times each; per-kernel HIP-event averages, the
+    VALU fraction at 24 ops per butterfly and the HBM fraction of the pass's algorithmic
+    bytes (every residue read and written once, plus a row pass's twiddle table of N
+    16-byte pairs per prime)."""
     import torch
 
     import synthetic
@@ -110,9 +112,15 @@ def ntt_microbench(reps: int):
         prof = _lib.profile_read()
         _lib.profile_enable(False)
         bfly = 28 * polys * (n // 2) * (w["log_n"] // 2)
+
+        def pass_bytes(kernel):
+            return 2 * 8.0 * n * 28 * polys + (16.0 * n * 28 if "rows" in kernel else 0.0)
+
         res[28 * polys] = {k: {"avg_us": round(ms / c * 1e3, 3),
                                "us_per_limb": round(ms / c * 1e3 / (28 * polys), 4),
-                               "valu_frac_24ops": round(bfly * BFLY_OPS / (ms / c * 1e-3) / VALU_SLOTS_PER_S, 4)}
+                               "valu_frac_24ops": round(bfly * BFLY_OPS / (ms / c * 1e-3) / VALU_SLOTS_PER_S, 4),
+                               "mb": round(pass_bytes(k) / 1e6, 1),
+                               "hbm_frac": round(pass_bytes(k) / (ms / c * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
                            for k, (c, ms) in prof.items()}
         del x
     print(json.dumps({"ntt_microbench": "limbs per launch -> kernel stats at N=2^16", "limbs": res}), flush=True)

@@ -4,6 +4,7 @@
     python -m paper_2503_22227_amd.profsum pmc    <results.db>
     python -m paper_2503_22227_amd.profsum valu   <results.db>
     python -m paper_2503_22227_amd.profsum traffic <fetch.db> <write.db> <copy_fetch.db> <copy_write.db> <copy_bytes>
+    python -m paper_2503_22227_amd.profsum micro  <bench.py --ntt-microbench output>
 
 ``stats``: per kernel, launches and average / min / max duration.
 ``pmc``: per kernel, launches and the average value of every collected counter.
@@ -13,6 +14,8 @@ VALU issue slots they take, mean resident waves per SIMD and LDS instructions
 ``traffic``: per kernel, HBM bytes per launch from FETCH_SIZE and WRITE_SIZE
 (KiB per dispatch), each scaled by what the same counter reads for a plain
 device copy of ``copy_bytes`` bytes (expected: copy_bytes read and written).
+``micro``: the NTT pass sweep of ``bench.py --ntt-microbench`` (its JSON line) as
+one row per pass and launch size.
 """
 from __future__ import annotations
 
@@ -134,6 +137,22 @@ def traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, copy_bytes) -> str
     return "\n".join(lines)
 
 
+def micro(path: str) -> str:
+    import json
+    line = [l for l in open(path).read().splitlines() if l.startswith("{")][-1]
+    d = json.loads(line)["limbs"]
+    out = ["| pass | limbs | avg us | us per limb | algorithmic MB | HBM frac | VALU frac (24 ops) |",
+           "|---|---|---|---|---|---|---|"]
+    names = sorted({k for ks in d.values() for k in ks})
+    for k in names:
+        for limbs in sorted(d, key=int):
+            v = d[limbs].get(k)
+            if v:
+                out.append("| %s | %s | %.2f | %.4f | %.1f | %.3f | %.3f |" % (
+                    k, limbs, v["avg_us"], v["us_per_limb"], v["mb"], v["hbm_frac"], v["valu_frac_24ops"]))
+    return "\n".join(out)
+
+
 def source_digest() -> str:
     """sha1 over the library's HIP sources: a counter table is valid only for the code it measured."""
     import hashlib
@@ -155,6 +174,8 @@ def main(argv):
         print(pmc(argv[2]))
     elif mode == "valu":
         print(valu(argv[2]))
+    elif mode == "micro":
+        print(micro(argv[2]))
     elif mode == "traffic":
         print(traffic(argv[2], argv[3], argv[4], argv[5], int(argv[6])))
         print()
