@@ -674,6 +674,42 @@ def autotune_section(shapes=((16, 24), (16, 8), (15, 14), (15, 4), (14, 24), (14
                         "%d steps" % (rounds, reps), "shapes": out}
 
 
+def batch_stage_bytes(shapes, q_count: int, K: int, alpha: int) -> dict:
+    """Algorithmic HBM bytes of each stage of one batched HMult+Relin run over
+    ``shapes`` [(log_n, limbs)] (names as the library's profile scopes): every
+    residue a stage and its fused prologue / epilogue must read or write once
+    (8 B), plus each row pass's twiddle table (N 16-byte pairs) once per distinct
+    prime and ring degree.  The two inverse column passes (of d2 and of the
+    special-prime limbs) share one scope name."""
+    from collections import defaultdict
+    out = defaultdict(float)
+    primes = defaultdict(lambda: defaultdict(set))
+    for ln, nl in shapes:
+        n = 1 << ln
+        limb = 8.0 * n
+        dn = (nl + alpha - 1) // alpha
+        ext = sum(nl - min(alpha, nl - j * alpha) + K for j in range(dn))
+        out["batch_ntt_inv_rows_tensor"] += 3 * nl * limb      # a1, b1 read, d2 row written
+        out["batch_ntt_inv_cols"] += 2 * nl * limb + 2 * (2 * K) * limb
+        out["batch_modup_bconv"] += algorithmic_bytes("modup_bconv", nl, K, alpha, n, "hmult")
+        out["batch_ntt_fwd_cols"] += 2 * ext * limb
+        out["batch_ntt_fwd_rows"] += 2 * ext * limb
+        out["batch_inner_product"] += algorithmic_bytes("inner_product", nl, K, alpha, n, "hmult")
+        out["batch_ntt_inv_rows"] += 2 * (2 * K) * limb
+        out["batch_ntt_fwd_cols_moddown"] += (2 * K + 2 * nl) * limb
+        out["batch_ntt_fwd_rows_moddown"] += 6 * nl * limb      # conv, ip' read, result written
+        primes[ln]["q"].update(range(nl))
+        primes[ln]["ext"].update(list(range(nl)) + [q_count + k for k in range(K)])
+        primes[ln]["p"].update(q_count + k for k in range(K))
+    for ln, ps in primes.items():
+        tw = 16.0 * (1 << ln)
+        out["batch_ntt_inv_rows_tensor"] += tw * len(ps["q"])
+        out["batch_ntt_fwd_rows"] += tw * len(ps["ext"])
+        out["batch_ntt_inv_rows"] += tw * len(ps["p"])
+        out["batch_ntt_fwd_rows_moddown"] += tw * len(ps["q"])
+    return dict(out)
+
+
 def batch_section(reps: int, tune: bool = True):
     """256 HMult+Relin items of mixed N in {2^14, 2^15, 2^16} and 4..24 limbs: one graph
     replay of the batched launches vs one HMult+Relin call per item on the same stream,
@@ -733,6 +769,25 @@ def batch_section(reps: int, tune: bool = True):
     t_default = timed(lambda: plan.run(graph=True))
     setting = autotune.tune(plan, shapes, reps=2, use_cache=False) if tune else None
     t_batch = timed(lambda: plan.run(graph=True))
+    # per-stage times of eager runs (HIP events around each stage's launches),
+    # against the stage's algorithmic bytes
+    from paper_2503_22227_amd import _lib
+    plan.run(graph=False)
+    torch.cuda.synchronize()
+    _lib.profile_read()
+    _lib.profile_enable(True)
+    for _ in range(3):
+        plan.run(graph=False)
+    torch.cuda.synchronize()
+    prof = _lib.profile_read()
+    _lib.profile_enable(False)
+    sbytes = batch_stage_bytes(shapes, len(ch["q"]), len(ch["p"]), w["alpha"])
+    stages = {}
+    for name, (cnt, ms) in sorted(prof.items()):
+        if name in sbytes and cnt:
+            sec = ms / 3 * 1e-3  # the stage's total time per run
+            stages[name] = {"ms_per_run": round(ms / 3, 3), "gb": round(sbytes[name] / 1e9, 3),
+                            "hbm_frac": round(sbytes[name] / sec / (HBM_PEAK_GBS * 1e9), 3)}
     n_items = len(items)
     limb_bytes = sum(7 * nl * (8 << ln) for ln, nl in shapes)
     out = {"workload": "256 CKKS HMult+Relin items, N in {2^14,2^15,2^16}, 4..24 limbs, k=4, alpha=8",
@@ -742,7 +797,7 @@ def batch_section(reps: int, tune: bool = True):
            "speedup_vs_synced": round(t_plain_synced / t_batch, 3),
            "batched_ms": round(t_batch * 1e3, 3), "plain_ms": round(t_plain * 1e3, 3),
            "batched_default_ms": round(t_default * 1e3, 3), "autotuned": setting,
-           "ciphertext_bytes_in_out": limb_bytes}
+           "ciphertext_bytes_in_out": limb_bytes, "stages": stages}
     plan.close()
     return out
 
