@@ -459,8 +459,10 @@ __device__ __forceinline__ u128 dot_split(const uint32_t *yl, const uint32_t *yh
 // kBehzGroup output limbs so that a launch has several threads per
 // coefficient (one thread per coefficient and every output limb left 1.5-2
 // waves per SIMD, each running thousands of dependent instructions); the
-// per-coefficient inputs of a group are recomputed by each group.
-constexpr int kBehzGroup = 4;
+// per-coefficient inputs of a group are recomputed by each group.  Measured
+// at N = 2^15, 14 + 15 limbs, BFV HMult+Relin: groups of 4, 8 and 16 took
+// 348, 343 and 374 us (16: one group, 3 waves per SIMD).
+constexpr int kBehzGroup = 8;
 
 __host__ __device__ inline uint32_t behz_groups(uint32_t limbs) { return (limbs + kBehzGroup - 1) / kBehzGroup; }
 
