@@ -86,3 +86,42 @@ def test_bench_refuses_more_than_one_gpu():
                          stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=120)
     assert res.returncode == 2
     assert "single MI355X" in res.stdout and "--gpus 2" in res.stdout
+
+
+def test_batch_stage_bytes_one_item():
+    """One item at N = 2^12, 9 limbs, K = 4, alpha = 8 (digits of 8 and 1 limbs):
+    the ModUp extension has (9 - 8 + 4) + (9 - 1 + 4) = 17 limbs; every stage's
+    bytes follow from the limb counts and one twiddle table per distinct prime."""
+    n = 1 << 12
+    limb, tw = 8.0 * n, 16.0 * n
+    b = bench.batch_stage_bytes([(12, 9)], q_count=24, K=4, alpha=8)
+    assert b["batch_ntt_fwd_cols"] == 2 * 17 * limb
+    assert b["batch_ntt_fwd_rows"] == 2 * 17 * limb + tw * (9 + 4)
+    assert b["batch_ntt_inv_rows_tensor"] == 3 * 9 * limb + tw * 9
+    assert b["batch_ntt_inv_cols"] == 2 * 9 * limb + 2 * 8 * limb
+    assert b["batch_ntt_inv_rows"] == 2 * 8 * limb + tw * 4
+    assert b["batch_ntt_fwd_cols_moddown"] == (8 + 18) * limb
+    assert b["batch_ntt_fwd_rows_moddown"] == 6 * 9 * limb + tw * 9
+    assert b["batch_inner_product"] == bench.algorithmic_bytes("inner_product", 9, 4, 8, n, "hmult")
+    assert b["batch_modup_bconv"] == bench.algorithmic_bytes("modup_bconv", 9, 4, 8, n, "hmult") == (9 + 17) * limb
+
+
+def test_batch_stage_bytes_share_tables_per_degree():
+    # two items of one degree share each prime's row table; a third degree adds its own
+    one = bench.batch_stage_bytes([(13, 8)], 24, 4, 8)
+    two = bench.batch_stage_bytes([(13, 8), (13, 8)], 24, 4, 8)
+    tw13 = 16.0 * (1 << 13)
+    assert two["batch_ntt_fwd_rows"] == 2 * one["batch_ntt_fwd_rows"] - tw13 * (8 + 4)
+    mixed = bench.batch_stage_bytes([(13, 8), (14, 8)], 24, 4, 8)
+    assert mixed["batch_ntt_inv_rows"] == one["batch_ntt_inv_rows"] + 2 * one["batch_ntt_inv_rows"]
+
+
+def test_micro_summary(tmp_path):
+    line = ('{"ntt_microbench": "x", "limbs": {"56": {"ntt_fwd_cols": {"avg_us": 22.0, "us_per_limb": 0.3929, '
+            '"valu_frac_24ops": 0.4, "mb": 58.7, "hbm_frac": 0.3335}}, "28": {"ntt_fwd_cols": {"avg_us": 14.0, '
+            '"us_per_limb": 0.5, "valu_frac_24ops": 0.3, "mb": 29.4, "hbm_frac": 0.2625}}}}')
+    p = tmp_path / "m.json"
+    p.write_text("noise\n" + line + "\n")
+    rows = [l for l in profsum.micro(str(p)).splitlines() if l.startswith("| ntt")]
+    assert rows == ["| ntt_fwd_cols | 28 | 14.00 | 0.5000 | 29.4 | 0.263 | 0.300 |",
+                    "| ntt_fwd_cols | 56 | 22.00 | 0.3929 | 58.7 | 0.334 | 0.400 |"]
