@@ -91,6 +91,53 @@ __device__ __forceinline__ uint32_t unit_begin_of<NttJob>(const NttJob &j, int) 
     return j.unit_begin;
 }
 
+// The pointers of a job table address device memory, but loaded from the table
+// they are generic pointers, and every access through one would be a flat
+// instruction (counted by both the vector-memory and the LDS/scalar wait
+// counters, so each use waits for both).  A job is copied with its pointers'
+// bits re-typed as global-address-space pointers, which lets the compiler emit
+// global loads and stores.
+template <typename T>
+__device__ __forceinline__ T *gptr(T *p) {
+    return (T *)(__attribute__((address_space(1))) T *)(uintptr_t)p;
+}
+
+__device__ __forceinline__ KsJob global_job(const KsJob &J) {
+    KsJob g = J;
+    g.a = gptr(J.a);
+    g.b = gptr(J.b);
+    g.evk = gptr(J.evk);
+    g.out = gptr(J.out);
+    g.d2 = gptr(J.d2);
+    g.d_coeff = gptr(J.d_coeff);
+    g.ext = gptr(J.ext);
+    g.ip = gptr(J.ip);
+    g.conv = gptr(J.conv);
+    g.pcs = gptr(J.pcs);
+    g.modup_tab = gptr(J.modup_tab);
+    g.moddown_tab = gptr(J.moddown_tab);
+    g.pinv = gptr(J.pinv);
+    return g;
+}
+
+__device__ __forceinline__ NttJob global_job(const NttJob &J) {
+    NttJob g = J;
+    g.b.in = gptr(J.b.in);
+    g.b.out = gptr(J.b.out);
+    g.b.pmap = gptr(J.b.pmap);
+    g.tw_all = gptr(J.tw_all);
+    g.tw_rows = gptr(J.tw_rows);
+    g.pcs = gptr(J.pcs);
+    g.ct_a = gptr(J.ct_a);
+    g.ct_b = gptr(J.ct_b);
+    g.ip = gptr(J.ip);
+    g.out = gptr(J.out);
+    g.pinv = gptr(J.pinv);
+    g.md_cross = gptr(J.md_cross);
+    g.md_negp = gptr(J.md_negp);
+    return g;
+}
+
 // Last job whose first unit is <= u (jobs sorted by unit_begin).
 template <typename J>
 __device__ __forceinline__ uint32_t find_job(const J *jobs, uint32_t njobs, uint32_t u, int stage) {
@@ -113,7 +160,7 @@ __global__ __launch_bounds__(kEw) void ks_batched_kernel(const KsJob *__restrict
     uint32_t j = find_job(jobs, njobs, u0, STAGE);
     for (uint32_t u = u0; u < u1; ++u) {
         while (j + 1 < njobs && jobs[j + 1].unit_begin[STAGE] <= u) ++j;
-        const KsJob &J = jobs[j];
+        const KsJob J = global_job(jobs[j]);
         const uint32_t local = u - J.unit_begin[STAGE];
         const uint32_t cshift = J.log_n - 8;  // N / 256 blocks per row
         const uint32_t gy = local >> cshift, gx = local & ((1u << cshift) - 1);
@@ -228,7 +275,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
     if constexpr (!LOOP) {
         if (blockIdx.x >= total) return;
         const uint32_t u = unit0 + blockIdx.x;
-        ntt_batched_unit<A, B, FWD, FIRST, TAIL, PRO>(lds, jobs[find_job(jobs, njobs, u, 0)], u);
+        ntt_batched_unit<A, B, FWD, FIRST, TAIL, PRO>(lds, global_job(jobs[find_job(jobs, njobs, u, 0)]), u);
     } else {
         const uint32_t u0 = unit0 + blockIdx.x * per_wg;
         const uint32_t u1 = unit0 + min(total, (blockIdx.x + 1) * per_wg);
@@ -236,7 +283,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNttWa
         uint32_t j = find_job(jobs, njobs, u0, 0);
         for (uint32_t u = u0; u < u1; ++u) {
             while (j + 1 < njobs && jobs[j + 1].unit_begin <= u) ++j;
-            ntt_batched_unit<A, B, FWD, FIRST, TAIL, PRO>(lds, jobs[j], u);
+            ntt_batched_unit<A, B, FWD, FIRST, TAIL, PRO>(lds, global_job(jobs[j]), u);
         }
     }
 }
